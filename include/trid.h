@@ -1,0 +1,217 @@
+/*
+ * trid.h -- C ABI of the MI355X (gfx950) batched tridiagonal solver library.
+ *
+ * The operation is the one posed in arxiv 2201.03950 ("High Throughput
+ * Multidimensional Tridiagonal Systems Solvers on FPGAs"):
+ *   - eqs. (1)-(2): a_i u_{i-1} + b_i u_i + c_i u_{i+1} = d_i, i = 0..N-1, with
+ *     a_0 = c_{N-1} = 0;
+ *   - Section II-B: many such systems lie along the x, y or z lines of a 2D/3D
+ *     mesh whose coefficients are given per grid point, stored column-major
+ *     (x contiguous); the systems along one axis are solved together;
+ *   - Section III: batched Thomas (Alg. 1) per line, and for long or contiguous
+ *     lines the tiled modified Thomas of eq. (7) whose reduced system is solved
+ *     by PCR (Alg. 2) -- the "Thomas-PCR" hybrid;
+ *   - Section IV-A, Alg. 3: the ADI heat-diffusion step, whose right-hand side
+ *     comes from an explicit stencil and whose coefficients are generated
+ *     inside the solver (the Tridslv(x-dim / y-dim / z-dim) calls).
+ *
+ * Conventions shared by every entry point
+ *   Mesh:     `ndim` in 1..3 extents `dims[0..ndim)`, dims[0] fastest, and
+ *             `batch` independent meshes stored one after another (batch
+ *             outermost).  Point (i, j, k) of mesh m is element
+ *             ((m*nz + k)*ny + j)*nx + i.  Lines of axis `axis` have length
+ *             dims[axis] and element stride prod(dims[0..axis)).
+ *   Memory:   every data pointer is a DEVICE pointer owned by the caller; the
+ *             library never frees or retains it past the call.  `dims` and
+ *             `offsets_host` are HOST pointers read during the call.
+ *   Rows:     a at the first row and c at the last row of every line are
+ *             ignored (treated as 0), as eq. (1) requires; their storage must
+ *             still exist.  There is no pivoting and no singularity check
+ *             (Alg. 1): the result is defined for diagonally dominant systems;
+ *             otherwise inf/NaN propagate.
+ *   Streams:  work is enqueued on the handle's stream (trid_set_stream;
+ *             default: the null stream) and returns before it completes.
+ *   Errors:   every call returns TRID_OK (0) or a TRID_ERR_* code and never
+ *             throws or aborts.  Arguments are validated on the host before any
+ *             HIP call; a failing call leaves its outputs untouched unless the
+ *             failure is TRID_ERR_HIP from an already-launched kernel.
+ *             trid_last_error() returns the text of the handle's last error.
+ *   Threads:  one handle per host thread; a handle may be used with any
+ *             stream of the device that was current when it was first used.
+ */
+#ifndef TRID_H
+#define TRID_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct trid_handle_s *trid_handle_t;
+typedef void *trid_stream_t; /* a hipStream_t; NULL is the null stream */
+
+typedef enum { TRID_F32 = 0, TRID_F64 = 1 } trid_dtype_t;
+
+/* precision of a solve: plain FP64, plain FP32, or FP32 bulk solves with one
+ * FP64 residual and refinement sweep */
+typedef enum { TRID_PREC_F64 = 0, TRID_PREC_F32 = 1, TRID_PREC_F32_REFINE64 = 2 } trid_prec_t;
+
+enum {
+    TRID_OK = 0,
+    TRID_ERR_ARG = 1,         /* invalid argument (null pointer, bad dims/axis/dtype, ...) */
+    TRID_ERR_ALLOC = 2,       /* device or host allocation failed */
+    TRID_ERR_HIP = 3,         /* a HIP runtime call or kernel launch failed */
+    TRID_ERR_UNSUPPORTED = 4  /* valid but not supported (e.g. a line longer than the limit) */
+};
+
+/* flags of trid_adi_step */
+#define TRID_ADI_GRAPH 1u /* capture the nsteps launches in a hipGraph once and replay it */
+
+/* Longest line a single-workgroup tile plan handles (rows). */
+#define TRID_MAX_LINE 8192
+
+/* ---------------------------------------------------------------- handle -- */
+
+/* Create a handle.  Allocates host memory only; device state (workspace,
+ * graphs) is created on first use on the device current at that time.
+ * Errors: TRID_ERR_ARG if h is NULL, TRID_ERR_ALLOC. */
+int trid_create(trid_handle_t *h);
+
+/* Destroy a handle: synchronises its stream, frees its workspace, plans and
+ * graphs.  NULL is accepted (no-op). */
+int trid_destroy(trid_handle_t h);
+
+/* Select the stream later calls enqueue on (NULL = null stream). */
+int trid_set_stream(trid_handle_t h, trid_stream_t stream);
+
+/* Text of the handle's last error ("" if none); valid until the next call on h.
+ * With h == NULL, the text of the last trid_create failure. */
+const char *trid_last_error(trid_handle_t h);
+
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int trid_version(void);
+
+/* Force the tile plan of later line solves on this handle: M rows per tile
+ * (8, 16 or 32) and L lines per workgroup (a power of two); 0 restores the
+ * automatic choice.  Every plan computes the same solution up to rounding
+ * (Section III-B: the tile split only changes the reduced system); this knob
+ * exists for tuning and for tests that vary the plan.
+ * Errors: TRID_ERR_ARG for other values. */
+int trid_set_tile(trid_handle_t h, int M, int L);
+
+/* ------------------------------------------------------- batched solves -- */
+
+/* Solve every line of `axis` of `batch` meshes: A x = d with per-point
+ * coefficient arrays a (sub), b (diagonal), c (super) of dtype dt, in the
+ * mesh layout (eqs. (1)-(2), Section II-B).  d is IN/OUT: the right-hand side
+ * on entry, the solution on return.  a, b, c are read only.
+ * Errors: TRID_ERR_ARG (null pointer, ndim not in 1..3, axis not in
+ * 0..ndim-1, a dim < 1, batch < 1, bad dtype), TRID_ERR_UNSUPPORTED (line
+ * length > TRID_MAX_LINE), TRID_ERR_HIP. */
+int trid_gtsv_batched(trid_handle_t h, trid_dtype_t dt, const void *a, const void *b,
+                      const void *c, void *d, int ndim, const int64_t *dims, int axis,
+                      int64_t batch);
+
+/* As trid_gtsv_batched with the same (a, b, c) on every row, generated inside
+ * the kernel (the fused coefficient generation of Section IV-A); the scalars
+ * are rounded to dt.  Only d is read and written. */
+int trid_gtsv_batched_const(trid_handle_t h, trid_dtype_t dt, double a, double b, double c,
+                            void *d, int ndim, const int64_t *dims, int axis, int64_t batch);
+
+/* As trid_gtsv_batched with rows generated from a per-point array s (dtype dt):
+ * a_i = c_i = -s_i, b_i = 1 + 2 s_i (the implicit diffusion operator of Alg. 3
+ * with a spatially varying diffusion number). */
+int trid_gtsv_batched_s(trid_handle_t h, trid_dtype_t dt, const void *s, void *d, int ndim,
+                        const int64_t *dims, int axis, int64_t batch);
+
+/* FP32 bulk solve with one FP64 refinement sweep: with A the matrix of the
+ * FP32 coefficient arrays a, b, c (exactly representable, the matrix of
+ * record), computes x32 = solve32(A, fp32(d)), r = d - A x32 in FP64,
+ * delta = solve32(A, fp32(r)), x = x32 + delta in FP64.  d has dtype d_dt
+ * (FP32 or FP64) and is read only; x (FP64) receives the result and may not
+ * alias d.  Same layout and errors as trid_gtsv_batched. */
+int trid_gtsv_batched_refine(trid_handle_t h, trid_dtype_t d_dt, const float *a, const float *b,
+                             const float *c, const void *d, double *x, int ndim,
+                             const int64_t *dims, int axis, int64_t batch);
+
+/* As trid_gtsv_batched_refine with rows a = c = -s, b = 1 + 2 s from FP32 s. */
+int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t d_dt, const float *s, const void *d,
+                               double *x, int ndim, const int64_t *dims, int axis,
+                               int64_t batch);
+
+/* ------------------------------------------------------------ uneven batch -- */
+
+/* `nsys` systems of different lengths packed back to back: system k occupies
+ * rows [offsets[k], offsets[k+1]) of a, b, c, d and x (Section III-B's tiled
+ * solver handles the long ones).  offsets_host is a HOST int64 array of
+ * nsys+1 non-decreasing entries with offsets[0] = 0 and every length in
+ * 1..TRID_MAX_LINE.  Precision p selects the arithmetic:
+ *   TRID_PREC_F64:          a, b, c, d, x are double;
+ *   TRID_PREC_F32:          a, b, c, d, x are float;
+ *   TRID_PREC_F32_REFINE64: a, b, c are float, d and x are double.
+ * d is read only; x receives the solution (x may equal d for F64 and F32).
+ * All systems are solved by ONE persistent launch that pulls work items,
+ * longest first, from a device counter.  The schedule (work list, tile plan
+ * per length class) is built on the first call for a given offsets content
+ * and cached in the handle; with the environment variable TRID_AUTOTUNE=1 the
+ * tile plan is chosen by timing the candidates on this call's data.
+ * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED, TRID_ERR_ALLOC, TRID_ERR_HIP. */
+int trid_gtsv_varlen(trid_handle_t h, trid_prec_t p, const void *a, const void *b, const void *c,
+                     const void *d, void *x, const int64_t *offsets_host, int64_t nsys);
+
+/* ------------------------------------------------------------------- ADI -- */
+
+/* `nsteps` ADI heat-diffusion steps (Alg. 3) in place on u, in the Douglas
+ * delta form:  d = 2 s L u  (L: 7-point Laplacian in 3D, 5-point in 2D, zero
+ * outside the mesh), then d <- X^{-1} d, d <- Y^{-1} d (, d <- Z^{-1} d) with
+ * rows (-s, 1 + 2s, -s) along each axis, then u += d.  s is a per-point
+ * array of dtype dt, or NULL for the constant s0.  ndim is 2 or 3.  One step
+ * is three fused kernels in 3D (stencil + x solve; y solve; z solve + update)
+ * and two in 2D.  The d workspace (one mesh-sized array) is owned by the
+ * handle.  With TRID_ADI_GRAPH the launches of all nsteps are captured once
+ * into a hipGraph keyed on (u, s, s0, dims, batch, nsteps, dt) and replayed.
+ * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED, TRID_ERR_ALLOC, TRID_ERR_HIP. */
+int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, double s0, int ndim,
+                  const int64_t *dims, int64_t batch, int nsteps, unsigned flags);
+
+/* ------------------------------------------------------------- adjoints -- */
+
+/* Reverse mode of x = A^{-1} d along `axis` (arrays form).  x is the forward
+ * solution.  g is IN/OUT: dL/dx on entry, dL/dd = lambda = A^{-T} g on return.
+ * ga, gb, gc (written, not accumulated) receive dL/da = -lambda_i x_{i-1},
+ * dL/db = -lambda_i x_i, dL/dc = -lambda_i x_{i+1}; the entries of the ignored
+ * a_0 and c_{N-1} are written as 0.  Same layout and errors as
+ * trid_gtsv_batched. */
+int trid_gtsv_batched_adjoint(trid_handle_t h, trid_dtype_t dt, const void *a, const void *b,
+                              const void *c, const void *x, void *g, void *ga, void *gb, void *gc,
+                              int ndim, const int64_t *dims, int axis, int64_t batch);
+
+/* Reverse mode of x = A(s)^{-1} d with rows (-s, 1 + 2 s, -s): g IN/OUT as
+ * above, and gs += lambda_i (x_{i-1} - 2 x_i + x_{i+1}) (zero outside the
+ * line), i.e. dL/ds of this solve is ACCUMULATED into gs. */
+int trid_gtsv_batched_s_adjoint(trid_handle_t h, trid_dtype_t dt, const void *s, const void *x,
+                                void *g, void *gs, int ndim, const int64_t *dims, int axis,
+                                int64_t batch);
+
+/* One ADI step (trid_adi_step with per-point s, one step) in reverse: given
+ * the checkpoint u_t (the field before the step) and u_bar = dL/du_{t+1},
+ * recomputes the step's intermediates from u_t, overwrites u_bar with
+ * dL/du_t and ACCUMULATES dL/ds of this step into s_bar.  s must not be NULL.
+ * Workspace is owned by the handle. */
+int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s,
+                          void *u_bar, void *s_bar, int ndim, const int64_t *dims, int64_t batch);
+
+/* ------------------------------------------------------------ plan cache -- */
+
+/* Load / save the tile-plan cache (JSON text: one entry per tuned key, each
+ * with the gfx architecture it was tuned on).  Unknown keys are ignored on
+ * load; a missing file on load is TRID_ERR_ARG. */
+int trid_plan_load(trid_handle_t h, const char *path);
+int trid_plan_save(trid_handle_t h, const char *path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRID_H */

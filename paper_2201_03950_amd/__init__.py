@@ -1,0 +1,27 @@
+"""Batched tridiagonal line solves and ADI steps on MI355X (gfx950).
+
+The compute path is the HIP library ``libtrid.so`` (C ABI in ``include/trid.h``);
+this package is its thin torch-tensor binding.  Importing the package does not
+load the library; the first call does, and raises if it is missing.
+"""
+
+from ._binding import (  # noqa: F401
+    PREC_F32,
+    PREC_F32_REFINE64,
+    PREC_F64,
+    TridError,
+    adi_step,
+    adi_step_adjoint,
+    gtsv,
+    gtsv_adjoint,
+    gtsv_const,
+    gtsv_refine,
+    gtsv_s,
+    gtsv_s_adjoint,
+    gtsv_s_refine,
+    gtsv_varlen,
+    load_library,
+    plan_load,
+    plan_save,
+    set_tile,
+)

@@ -1,0 +1,350 @@
+// api.cpp -- the extern "C" boundary declared in include/trid.h: handles,
+// argument validation (always before any HIP call), tile planning, workspace,
+// hipGraph capture of ADI steps, and dispatch to the kernel launchers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/trid.h"
+#include "dispatch.hpp"
+#include "ext.hpp"
+
+using trid::i64;
+
+namespace {
+
+std::string g_create_error;
+
+struct GraphKey {
+    const void *u, *s;
+    double s0;
+    int dt, ndim;
+    i64 nx, ny, nz, batch;
+    int nsteps;
+    hipStream_t stream;
+    bool operator<(const GraphKey &o) const {
+        return std::tie(u, s, s0, dt, ndim, nx, ny, nz, batch, nsteps, stream) <
+               std::tie(o.u, o.s, o.s0, o.dt, o.ndim, o.nx, o.ny, o.nz, o.batch, o.nsteps, o.stream);
+    }
+};
+
+}  // namespace
+
+struct trid_handle_s {
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    std::string err;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    trid::ExtState ext;  // state of the extension entry points (refine, varlen, adjoint, plans)
+};
+
+namespace {
+
+int fail(trid_handle_t h, int code, const std::string &msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+int hip_fail(trid_handle_t h, hipError_t e, const char *what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(h, TRID_ERR_HIP, m);
+}
+
+bool dtype_ok(int dt) { return dt == TRID_F32 || dt == TRID_F64; }
+
+// Validate mesh arguments; on success fill the line geometry of `axis`.
+int check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, int64_t batch, i64 *inner,
+               i64 *n, i64 *outer) {
+    if (ndim < 1 || ndim > 3) return fail(h, TRID_ERR_ARG, "ndim must be 1, 2 or 3");
+    if (!dims) return fail(h, TRID_ERR_ARG, "dims is NULL");
+    if (axis < 0 || axis >= ndim) return fail(h, TRID_ERR_ARG, "axis out of range");
+    if (batch < 1) return fail(h, TRID_ERR_ARG, "batch must be >= 1");
+    i64 total = batch;
+    for (int k = 0; k < ndim; ++k) {
+        if (dims[k] < 1) return fail(h, TRID_ERR_ARG, "every dim must be >= 1");
+        if (total > ((i64)1 << 50) / dims[k]) return fail(h, TRID_ERR_ARG, "mesh too large");
+        total *= dims[k];
+    }
+    i64 in = 1, out = batch;
+    for (int k = 0; k < axis; ++k) in *= dims[k];
+    for (int k = axis + 1; k < ndim; ++k) out *= dims[k];
+    if (dims[axis] > TRID_MAX_LINE)
+        return fail(h, TRID_ERR_UNSUPPORTED, "line length exceeds TRID_MAX_LINE");
+    *inner = in;
+    *n = dims[axis];
+    *outer = out;
+    return TRID_OK;
+}
+
+int run_lines(trid_handle_t h, const trid::LineReq &r) {
+    trid::LinePlan pl;
+    std::string msg;
+    trid::LineReq rr = r;
+    h->ext.apply_overrides(&rr);
+    if (!trid::plan_lines(rr, &pl, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
+    hipError_t e = trid::launch_lines(rr, pl, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "line-solve launch");
+    h->err.clear();
+    return TRID_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle --
+
+namespace trid {
+
+hipStream_t handle_stream(trid_handle_t h) { return h->stream; }
+ExtState &handle_ext(trid_handle_t h) { return h->ext; }
+int handle_fail(trid_handle_t h, int code, const std::string &msg) { return fail(h, code, msg); }
+int handle_hip_fail(trid_handle_t h, hipError_t e, const char *what) { return hip_fail(h, e, what); }
+int handle_check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, int64_t batch,
+                      i64 *inner, i64 *n, i64 *outer) {
+    return check_mesh(h, ndim, dims, axis, batch, inner, n, outer);
+}
+int handle_run_lines(trid_handle_t h, const LineReq &r) { return run_lines(h, r); }
+
+// Grow the handle's workspace to at least `bytes` (invalidates captured graphs).
+int handle_workspace(trid_handle_t h, size_t bytes, void **ptr) {
+    if (h->ws_bytes < bytes) {
+        if (h->ws) {
+            hipError_t e = hipStreamSynchronize(h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+            for (auto &kv : h->graphs) hipGraphExecDestroy(kv.second);
+            h->graphs.clear();
+            hipFree(h->ws);
+            h->ws = nullptr;
+            h->ws_bytes = 0;
+        }
+        hipError_t e = hipMalloc(&h->ws, bytes);
+        if (e != hipSuccess) {
+            h->ws = nullptr;
+            return fail(h, TRID_ERR_ALLOC, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+        }
+        h->ws_bytes = bytes;
+    }
+    *ptr = h->ws;
+    return TRID_OK;
+}
+
+}  // namespace trid
+
+extern "C" {
+
+int trid_version(void) { return 10000; }
+
+int trid_create(trid_handle_t *h) {
+    if (!h) {
+        g_create_error = "h is NULL";
+        return TRID_ERR_ARG;
+    }
+    *h = nullptr;
+    trid_handle_t p = new (std::nothrow) trid_handle_s();
+    if (!p) {
+        g_create_error = "out of host memory";
+        return TRID_ERR_ALLOC;
+    }
+    *h = p;
+    return TRID_OK;
+}
+
+int trid_destroy(trid_handle_t h) {
+    if (!h) return TRID_OK;
+    if (h->ws || !h->graphs.empty() || h->capture_stream || h->ext.has_device_state()) {
+        hipStreamSynchronize(h->stream);
+        for (auto &kv : h->graphs) hipGraphExecDestroy(kv.second);
+        h->ext.release();
+        if (h->ws) hipFree(h->ws);
+        if (h->capture_stream) hipStreamDestroy(h->capture_stream);
+    }
+    delete h;
+    return TRID_OK;
+}
+
+int trid_set_stream(trid_handle_t h, trid_stream_t stream) {
+    if (!h) return TRID_ERR_ARG;
+    h->stream = static_cast<hipStream_t>(stream);
+    return TRID_OK;
+}
+
+const char *trid_last_error(trid_handle_t h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int trid_gtsv_batched(trid_handle_t h, trid_dtype_t dt, const void *a, const void *b, const void *c,
+                      void *d, int ndim, const int64_t *dims, int axis, int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (!dtype_ok(dt)) return fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!a || !b || !c || !d) return fail(h, TRID_ERR_ARG, "NULL data pointer");
+    trid::LineReq r;
+    int rc = check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    if (rc) return rc;
+    r.f64 = dt == TRID_F64;
+    r.mode = trid::Mode::Arrays;
+    r.out = trid::Out::Store;
+    r.a = a;
+    r.b = b;
+    r.c = c;
+    r.d = d;
+    r.x = d;
+    return run_lines(h, r);
+}
+
+int trid_gtsv_batched_const(trid_handle_t h, trid_dtype_t dt, double a, double b, double c, void *d,
+                            int ndim, const int64_t *dims, int axis, int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (!dtype_ok(dt)) return fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!d) return fail(h, TRID_ERR_ARG, "NULL data pointer");
+    trid::LineReq r;
+    int rc = check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    if (rc) return rc;
+    r.f64 = dt == TRID_F64;
+    r.mode = trid::Mode::Const;
+    r.out = trid::Out::Store;
+    r.ca = a;
+    r.cb = b;
+    r.cc = c;
+    r.d = d;
+    r.x = d;
+    return run_lines(h, r);
+}
+
+int trid_gtsv_batched_s(trid_handle_t h, trid_dtype_t dt, const void *s, void *d, int ndim,
+                        const int64_t *dims, int axis, int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (!dtype_ok(dt)) return fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!s || !d) return fail(h, TRID_ERR_ARG, "NULL data pointer");
+    trid::LineReq r;
+    int rc = check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    if (rc) return rc;
+    r.f64 = dt == TRID_F64;
+    r.mode = trid::Mode::S;
+    r.out = trid::Out::Store;
+    r.s = s;
+    r.d = d;
+    r.x = d;
+    return run_lines(h, r);
+}
+
+// Enqueue the launches of `nsteps` ADI steps on stream `st`.
+static int adi_enqueue(trid_handle_t h, bool f64, void *u, const void *s, double s0, int ndim,
+                       i64 nx, i64 ny, i64 nz, i64 batch, int nsteps, void *dws, hipStream_t st) {
+    trid::AdiReq ar;
+    ar.f64 = f64;
+    ar.ndim = ndim;
+    ar.u = u;
+    ar.s = s;
+    ar.s0 = s0;
+    ar.d = dws;
+    ar.nx = nx;
+    ar.ny = ny;
+    ar.nz = nz;
+    ar.batch = batch;
+    h->ext.apply_adi_overrides(&ar);
+    trid::LinePlan px, py, pz;
+    std::string msg;
+    if (!trid::plan_rhs_x(ar, &px, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
+    trid::LineReq ry;
+    ry.f64 = f64;
+    ry.mode = s ? trid::Mode::S : trid::Mode::Const;
+    ry.ca = -s0;
+    ry.cb = 1.0 + 2.0 * s0;
+    ry.cc = -s0;
+    ry.s = s;
+    ry.d = dws;
+    ry.inner = nx;
+    ry.n = ny;
+    ry.outer = nz * batch;
+    ry.out = (ndim == 2) ? trid::Out::Add : trid::Out::Store;
+    ry.x = (ndim == 2) ? u : dws;
+    h->ext.apply_overrides(&ry);
+    if (!trid::plan_lines(ry, &py, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
+    trid::LineReq rz = ry;
+    if (ndim == 3) {
+        rz.inner = nx * ny;
+        rz.n = nz;
+        rz.outer = batch;
+        rz.out = trid::Out::Add;
+        rz.x = u;
+        h->ext.apply_overrides(&rz);
+        if (!trid::plan_lines(rz, &pz, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
+    }
+    for (int it = 0; it < nsteps; ++it) {
+        hipError_t e = trid::launch_rhs_x(ar, px, st);
+        if (e != hipSuccess) return hip_fail(h, e, "stencil + x-solve launch");
+        e = trid::launch_lines(ry, py, st);
+        if (e != hipSuccess) return hip_fail(h, e, "y-solve launch");
+        if (ndim == 3) {
+            e = trid::launch_lines(rz, pz, st);
+            if (e != hipSuccess) return hip_fail(h, e, "z-solve launch");
+        }
+    }
+    return TRID_OK;
+}
+
+int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, double s0, int ndim,
+                  const int64_t *dims, int64_t batch, int nsteps, unsigned flags) {
+    if (!h) return TRID_ERR_ARG;
+    if (!dtype_ok(dt)) return fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!u) return fail(h, TRID_ERR_ARG, "u is NULL");
+    if (ndim != 2 && ndim != 3) return fail(h, TRID_ERR_ARG, "ADI needs ndim 2 or 3");
+    if (nsteps < 0) return fail(h, TRID_ERR_ARG, "nsteps must be >= 0");
+    if (flags & ~TRID_ADI_GRAPH) return fail(h, TRID_ERR_ARG, "unknown flags");
+    i64 inner, n, outer;
+    for (int ax = 0; ax < ndim; ++ax) {
+        int rc = check_mesh(h, ndim, dims, ax, batch, &inner, &n, &outer);
+        if (rc) return rc;
+    }
+    if (nsteps == 0) return TRID_OK;
+    const bool f64 = dt == TRID_F64;
+    const i64 nx = dims[0], ny = dims[1], nz = ndim == 3 ? dims[2] : 1;
+    const size_t bytes = (size_t)(nx * ny * nz * batch) * (f64 ? 8 : 4);
+    void *dws = nullptr;
+    int rc = trid::handle_workspace(h, bytes, &dws);
+    if (rc) return rc;
+    if (!(flags & TRID_ADI_GRAPH)) {
+        rc = adi_enqueue(h, f64, u, s, s0, ndim, nx, ny, nz, batch, nsteps, dws, h->stream);
+        if (rc == TRID_OK) h->err.clear();
+        return rc;
+    }
+    GraphKey key{u, s, s ? 0.0 : s0, (int)dt, ndim, nx, ny, nz, batch, nsteps, h->stream};
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+        hipError_t e;
+        if (!h->capture_stream) {
+            e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                h->capture_stream = nullptr;
+                return hip_fail(h, e, "hipStreamCreate");
+            }
+        }
+        e = hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
+        rc = adi_enqueue(h, f64, u, s, s0, ndim, nx, ny, nz, batch, nsteps, dws, h->capture_stream);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(h->capture_stream, &graph);
+        if (rc) {
+            if (graph) hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return hip_fail(h, e, "hipGraphInstantiate");
+        it = h->graphs.emplace(key, exec).first;
+    }
+    hipError_t e = hipGraphLaunch(it->second, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
+    h->err.clear();
+    return TRID_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// api_ext.cpp -- extern "C" entry points beyond the plain solves: tile-plan
+// control, line-solve adjoints, and the entry points not yet available on this
+// build (which return TRID_ERR_UNSUPPORTED).
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/trid.h"
+#include "dispatch.hpp"
+#include "ext.hpp"
+
+namespace trid {
+
+void ExtState::release() {
+    if (ws2) hipFree(ws2);
+    ws2 = nullptr;
+    ws2_bytes = 0;
+}
+
+int handle_workspace2(trid_handle_t h, size_t bytes, void **ptr) {
+    ExtState &x = handle_ext(h);
+    if (x.ws2_bytes < bytes) {
+        if (x.ws2) {
+            hipError_t e = hipStreamSynchronize(handle_stream(h));
+            if (e != hipSuccess) return handle_hip_fail(h, e, "hipStreamSynchronize");
+            hipFree(x.ws2);
+            x.ws2 = nullptr;
+            x.ws2_bytes = 0;
+        }
+        hipError_t e = hipMalloc(&x.ws2, bytes);
+        if (e != hipSuccess) {
+            x.ws2 = nullptr;
+            return handle_fail(h, TRID_ERR_ALLOC, std::string("workspace hipMalloc: ") + hipGetErrorString(e));
+        }
+        x.ws2_bytes = bytes;
+    }
+    *ptr = x.ws2;
+    return TRID_OK;
+}
+
+}  // namespace trid
+
+extern "C" {
+
+int trid_set_tile(trid_handle_t h, int M, int L) {
+    if (!h) return TRID_ERR_ARG;
+    if (M != 0 && M != 8 && M != 16 && M != 32)
+        return trid::handle_fail(h, TRID_ERR_ARG, "tile rows must be 0, 8, 16 or 32");
+    if (L < 0 || L > 1024 || (L & (L - 1)) != 0)
+        return trid::handle_fail(h, TRID_ERR_ARG, "lines per block must be 0 or a power of two <= 1024");
+    trid::ExtState &x = trid::handle_ext(h);
+    x.force_M = M;
+    x.force_L = L;
+    return TRID_OK;
+}
+
+int trid_gtsv_batched_adjoint(trid_handle_t h, trid_dtype_t dt, const void *a, const void *b,
+                              const void *c, const void *x, void *g, void *ga, void *gb, void *gc,
+                              int ndim, const int64_t *dims, int axis, int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!a || !b || !c || !x || !g || !ga || !gb || !gc)
+        return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    trid::LineReq r;
+    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    if (rc) return rc;
+    r.f64 = dt == TRID_F64;
+    r.mode = trid::Mode::ArraysT;
+    r.out = trid::Out::AdjArrays;
+    r.a = a;
+    r.b = b;
+    r.c = c;
+    r.xf = x;
+    r.g = g;
+    r.ga = ga;
+    r.gb = gb;
+    r.gc = gc;
+    return trid::handle_run_lines(h, r);
+}
+
+int trid_gtsv_batched_s_adjoint(trid_handle_t h, trid_dtype_t dt, const void *s, const void *x,
+                                void *g, void *gs, int ndim, const int64_t *dims, int axis,
+                                int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!s || !x || !g || !gs) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    trid::LineReq r;
+    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    if (rc) return rc;
+    r.f64 = dt == TRID_F64;
+    r.mode = trid::Mode::ST;
+    r.out = trid::Out::AdjS;
+    r.s = s;
+    r.xf = x;
+    r.g = g;
+    r.gs = gs;
+    return trid::handle_run_lines(h, r);
+}
+
+int trid_gtsv_batched_refine(trid_handle_t h, trid_dtype_t, const float *, const float *,
+                             const float *, const void *, double *, int, const int64_t *, int,
+                             int64_t) {
+    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "refine: not in this build") : TRID_ERR_ARG;
+}
+
+int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t, const float *, const void *, double *,
+                               int, const int64_t *, int, int64_t) {
+    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "refine: not in this build") : TRID_ERR_ARG;
+}
+
+int trid_gtsv_varlen(trid_handle_t h, trid_prec_t, const void *, const void *, const void *,
+                     const void *, void *, const int64_t *, int64_t) {
+    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "varlen: not in this build") : TRID_ERR_ARG;
+}
+
+int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t, const void *, const void *, void *, void *,
+                          int, const int64_t *, int64_t) {
+    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "ADI adjoint: not in this build")
+             : TRID_ERR_ARG;
+}
+
+int trid_plan_load(trid_handle_t h, const char *) {
+    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "plan cache: not in this build") : TRID_ERR_ARG;
+}
+
+int trid_plan_save(trid_handle_t h, const char *) {
+    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "plan cache: not in this build") : TRID_ERR_ARG;
+}
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+// dispatch.hpp -- host-side description of one batched line-solve launch and the
+// launch entry points implemented by the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace trid {
+
+using i64 = int64_t;
+
+enum class Mode {
+    Arrays,   // per-point a, b, c
+    Const,    // scalar a, b, c
+    S,        // a = c = -s, b = 1 + 2 s
+    ArraysT,  // transposed per-point rows (adjoint)
+    ST        // transposed s rows (adjoint)
+};
+
+enum class Out {
+    Store,      // x = solution
+    Add,        // x += solution
+    AdjArrays,  // g = lambda; ga, gb, gc = coefficient gradients
+    AdjS        // g = lambda; gs += lambda * second difference of xf
+};
+
+// Tile plan of a launch: M rows per tile, P tiles per line, L lines per block.
+struct LinePlan {
+    int M = 0;
+    int L = 0;
+    int P = 0;
+    bool staged = false;  // contiguous lines through LDS (axis 0)
+    int ls = 0;           // staged: LDS elements per line
+    size_t shmem = 0;     // dynamic LDS bytes
+    i64 nblocks = 0;
+    int threads() const { return L * P; }
+};
+
+struct LineReq {
+    bool f64 = true;
+    Mode mode = Mode::Arrays;
+    Out out = Out::Store;
+    const void *a = nullptr, *b = nullptr, *c = nullptr, *s = nullptr, *d = nullptr;
+    double ca = 0, cb = 0, cc = 0;
+    void *x = nullptr;         // Store / Add target
+    const void *xf = nullptr;  // forward solution (adjoints)
+    void *g = nullptr, *ga = nullptr, *gb = nullptr, *gc = nullptr, *gs = nullptr;
+    i64 inner = 1, n = 1, outer = 1;  // line stride, length, number of outer indices
+    int force_M = 0, force_L = 0;     // plan overrides (0 = automatic)
+    int force_strided = 0;            // 1: never use the staged kernel
+};
+
+// Choose the tile plan of a request (no HIP calls).  Returns false (with a
+// message) when the line length is beyond what one workgroup can hold.
+bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err);
+
+// Enqueue the solve described by r on stream s.
+hipError_t launch_lines(const LineReq &r, const LinePlan &pl, hipStream_t s);
+
+// ADI: RHS stencil fused with the x-line solve.  d = X^{-1} (2 s L u) for
+// `batch` meshes of nx*ny*nz points (nz = 1 in 2D), s per point (s != NULL)
+// or the constant s0.
+struct AdiReq {
+    bool f64 = true;
+    int ndim = 3;
+    const void *u = nullptr;
+    const void *s = nullptr;
+    double s0 = 0;
+    void *d = nullptr;
+    i64 nx = 1, ny = 1, nz = 1, batch = 1;
+    int force_M = 0, force_L = 0;
+};
+bool plan_rhs_x(const AdiReq &r, LinePlan *pl, std::string *err);
+hipError_t launch_rhs_x(const AdiReq &r, const LinePlan &pl, hipStream_t s);
+
+}  // namespace trid

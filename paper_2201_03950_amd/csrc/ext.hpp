@@ -1,0 +1,53 @@
+// ext.hpp -- per-handle state shared by the entry points beyond the plain solves
+// (tile-plan overrides and the tuned-plan cache), and the accessors that let
+// those entry points live in their own translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+
+#include "dispatch.hpp"
+
+typedef struct trid_handle_s *trid_handle_t;
+
+namespace trid {
+
+struct VarlenSchedule;  // defined with the uneven-batch solver
+
+struct ExtState {
+    int force_M = 0;  // forced tile rows (0: automatic)
+    int force_L = 0;  // forced lines per block (0: automatic)
+    // tuned plans: key -> (M, L)
+    std::map<std::string, std::pair<int, int>> tuned;
+    // uneven-batch schedules keyed by a hash of the offsets
+    std::map<std::string, VarlenSchedule *> varlen;
+    // scratch for adjoint / refinement entry points
+    void *ws2 = nullptr;
+    size_t ws2_bytes = 0;
+
+    void apply_overrides(LineReq *r) const {
+        if (force_M) r->force_M = force_M;
+        if (force_L) r->force_L = force_L;
+    }
+    void apply_adi_overrides(AdiReq *r) const {
+        if (force_M == 8 || force_M == 16) r->force_M = force_M;
+        if (force_L) r->force_L = force_L;
+    }
+    bool has_device_state() const { return ws2 != nullptr || !varlen.empty(); }
+    void release();
+};
+
+hipStream_t handle_stream(trid_handle_t h);
+ExtState &handle_ext(trid_handle_t h);
+int handle_fail(trid_handle_t h, int code, const std::string &msg);
+int handle_hip_fail(trid_handle_t h, hipError_t e, const char *what);
+int handle_check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, int64_t batch,
+                      i64 *inner, i64 *n, i64 *outer);
+int handle_run_lines(trid_handle_t h, const LineReq &r);
+int handle_workspace(trid_handle_t h, size_t bytes, void **ptr);
+int handle_workspace2(trid_handle_t h, size_t bytes, void **ptr);
+
+}  // namespace trid

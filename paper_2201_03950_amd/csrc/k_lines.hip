@@ -1,0 +1,209 @@
+// k_lines.cpp -- tile plans and launches of the batched line solves (gtsv along any
+// axis, coefficient arrays / constants / per-point s, plain, update and adjoint
+// epilogues).  Compiled as HIP for gfx950.
+#include <algorithm>
+
+#include "dispatch.hpp"
+#include "lines.hpp"
+
+namespace trid {
+
+namespace {
+
+constexpr int kStridedMaxThreads = 1024;
+constexpr int kStagedMaxThreads = 256;
+
+// Largest strided block for a tile of M rows of w-byte words: a thread keeps
+// about 3M words of tile state plus its raw rows in VGPRs, so bigger tiles get
+// fewer threads per block (and more VGPRs per thread) to avoid spills.
+constexpr int strided_max_threads(int M, int w) {
+    return M * w <= 64 ? 1024 : (M * w <= 128 ? 512 : 256);
+}
+constexpr size_t kMaxShmem = 64 * 1024;
+
+i64 cdiv(i64 a, i64 b) { return (a + b - 1) / b; }
+
+int pow2_floor(i64 v) {
+    int p = 1;
+    while ((i64)p * 2 <= v) p *= 2;
+    return p;
+}
+
+int pow2_ceil(i64 v) {
+    int p = 1;
+    while ((i64)p < v) p *= 2;
+    return p;
+}
+
+int staged_regions(Mode m) {
+    switch (m) {
+        case Mode::Arrays: return 4;
+        case Mode::Const: return 1;
+        case Mode::S: return 2;
+        default: return 0;
+    }
+}
+
+}  // namespace
+
+bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
+    const int w = r.f64 ? 8 : 4;
+    LinePlan p;
+    int M = r.force_M ? r.force_M : (r.f64 ? 8 : 16);
+    if (M != 8 && M != 16 && M != 32) {
+        *err = "tile size must be 8, 16 or 32";
+        return false;
+    }
+    i64 P = cdiv(r.n, M);
+    while (!r.force_M && P > strided_max_threads(M, w) / 2 && M < 32) {
+        M *= 2;
+        P = cdiv(r.n, M);
+    }
+    const int maxt = strided_max_threads(M, w);
+    if (P > maxt) {
+        *err = "line too long for one workgroup";
+        return false;
+    }
+    p.M = M;
+    p.P = (int)P;
+    const int regions = staged_regions(r.mode);
+    const bool want_staged = r.inner == 1 && !r.force_strided && regions > 0 && r.out == Out::Store &&
+                             P <= kStagedMaxThreads;
+    if (want_staged) {
+        int L = r.force_L ? r.force_L : std::max(1, kStagedMaxThreads / (int)P);
+        L = std::max(1, std::min(L, pow2_ceil(r.outer)));
+        const int ls = (int)P * (M + 1);
+        auto bytes = [&](int LL) {
+            return (size_t)regions * LL * ls * w + (size_t)6 * LL * P * w;
+        };
+        while (bytes(L) > kMaxShmem && L > 1) L /= 2;
+        if (bytes(L) <= kMaxShmem && L * P <= kStagedMaxThreads) {
+            p.staged = true;
+            p.L = L;
+            p.ls = ls;
+            p.shmem = bytes(L);
+            p.nblocks = cdiv(r.outer, L);
+            *pl = p;
+            return true;
+        }
+    }
+    int L = r.force_L ? r.force_L : std::min(64, pow2_floor(maxt / P));
+    if (!r.force_L && r.inner < L) L = std::max(1, pow2_ceil(r.inner));
+    if ((i64)L * P > maxt) {
+        *err = "plan exceeds 1024 threads per block";
+        return false;
+    }
+    p.staged = false;
+    p.L = L;
+    p.shmem = (size_t)6 * L * P * w;
+    p.nblocks = cdiv(r.inner, L) * r.outer;
+    if (p.nblocks >= (i64)1 << 31) {
+        *err = "too many blocks";
+        return false;
+    }
+    *pl = p;
+    return true;
+}
+
+namespace {
+
+template <typename T, int M, class Src, class Epi>
+hipError_t go_strided(const LineReq &r, const LinePlan &pl, Src src, Epi epi, hipStream_t s) {
+    StridedGeom g;
+    g.inner = r.inner;
+    g.nib = cdiv(r.inner, pl.L);
+    g.n = (int)r.n;
+    g.L = pl.L;
+    g.P = pl.P;
+    constexpr int MAXT = strided_max_threads(M, (int)sizeof(T));
+    hipLaunchKernelGGL((k_strided<T, M, MAXT, Src, Epi>), dim3((unsigned)pl.nblocks),
+                       dim3(pl.threads()), pl.shmem, s, g, src, epi);
+    return hipGetLastError();
+}
+
+template <typename T, class Src, class Epi>
+hipError_t strided_M(const LineReq &r, const LinePlan &pl, Src src, Epi epi, hipStream_t s) {
+    switch (pl.M) {
+        case 8: return go_strided<T, 8>(r, pl, src, epi, s);
+        case 16: return go_strided<T, 16>(r, pl, src, epi, s);
+        case 32: return go_strided<T, 32>(r, pl, src, epi, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T, int M, class Src>
+hipError_t go_staged(const LineReq &r, const LinePlan &pl, Src src, hipStream_t s) {
+    StagedGeom g;
+    g.nlines = r.outer;
+    g.n = (int)r.n;
+    g.L = pl.L;
+    g.P = pl.P;
+    g.ls = pl.ls;
+    StgOut<T> out{static_cast<T *>(r.x)};
+    hipLaunchKernelGGL((k_staged<T, M, kStagedMaxThreads, Src, StgOut<T>>),
+                       dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g, src, out);
+    return hipGetLastError();
+}
+
+template <typename T, class Src>
+hipError_t staged_M(const LineReq &r, const LinePlan &pl, Src src, hipStream_t s) {
+    switch (pl.M) {
+        case 8: return go_staged<T, 8>(r, pl, src, s);
+        case 16: return go_staged<T, 16>(r, pl, src, s);
+        case 32: return go_staged<T, 32>(r, pl, src, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_typed(const LineReq &r, const LinePlan &pl, hipStream_t s) {
+    const T *a = static_cast<const T *>(r.a), *b = static_cast<const T *>(r.b);
+    const T *c = static_cast<const T *>(r.c), *sp = static_cast<const T *>(r.s);
+    const T *d = static_cast<const T *>(r.d);
+    T *x = static_cast<T *>(r.x);
+    if (pl.staged) {
+        switch (r.mode) {
+            case Mode::Arrays: return staged_M<T>(r, pl, StgArrays<T>{a, b, c, d}, s);
+            case Mode::Const:
+                return staged_M<T>(r, pl, StgConst<T>{(T)r.ca, (T)r.cb, (T)r.cc, d}, s);
+            case Mode::S: return staged_M<T>(r, pl, StgS<T>{sp, d}, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (r.out == Out::Store) {
+        switch (r.mode) {
+            case Mode::Arrays: return strided_M<T>(r, pl, SrcArrays<T>{a, b, c, d}, EpiStore<T>{x}, s);
+            case Mode::Const:
+                return strided_M<T>(r, pl, SrcConst<T>{(T)r.ca, (T)r.cb, (T)r.cc, d}, EpiStore<T>{x}, s);
+            case Mode::S: return strided_M<T>(r, pl, SrcS<T>{sp, d}, EpiStore<T>{x}, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    if (r.out == Out::Add) {
+        switch (r.mode) {
+            case Mode::Const:
+                return strided_M<T>(r, pl, SrcConst<T>{(T)r.ca, (T)r.cb, (T)r.cc, d}, EpiAdd<T>{x}, s);
+            case Mode::S: return strided_M<T>(r, pl, SrcS<T>{sp, d}, EpiAdd<T>{x}, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    const T *xf = static_cast<const T *>(r.xf);
+    if (r.out == Out::AdjArrays && r.mode == Mode::ArraysT) {
+        EpiAdjArrays<T> e{xf, static_cast<T *>(r.g), static_cast<T *>(r.ga), static_cast<T *>(r.gb),
+                          static_cast<T *>(r.gc)};
+        return strided_M<T>(r, pl, SrcArraysT<T>{a, b, c, static_cast<const T *>(r.g)}, e, s);
+    }
+    if (r.out == Out::AdjS && r.mode == Mode::ST) {
+        EpiAdjS<T> e{xf, static_cast<T *>(r.g), static_cast<T *>(r.gs)};
+        return strided_M<T>(r, pl, SrcST<T>{sp, static_cast<const T *>(r.g)}, e, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_lines(const LineReq &r, const LinePlan &pl, hipStream_t s) {
+    return r.f64 ? launch_typed<double>(r, pl, s) : launch_typed<float>(r, pl, s);
+}
+
+}  // namespace trid

@@ -1,0 +1,468 @@
+// lines.hpp -- the two line-solve kernel templates and their row sources / epilogues.
+//
+//  k_strided : lines with element stride >= 1 that is the fastest mesh extent
+//              product (y and z lines, Section II-B).  Lanes map to adjacent
+//              lines, so every row load/store of a wavefront is one contiguous
+//              run of memory (the GPU counterpart of the paper's XY / XZ plane
+//              buffering, Section III-A).  Thread t owns tile p = t / L of line
+//              l = t % L; tiles of a line sit in different wavefronts.
+//  k_staged  : contiguous lines (x lines).  The block's L lines are one
+//              contiguous range of memory; it is loaded with coalesced accesses
+//              into LDS (padded per tile against bank conflicts), each thread
+//              reads its tile from LDS, and results leave through LDS again --
+//              the LDS form of the paper's x-line transpose (Section III-A).
+//              Thread t owns tile p = t % P of line l = t / P, so the tiles of
+//              a line are adjacent lanes of one wavefront.
+//
+// Row sources produce (sub, diag, super, rhs) of the rows of a tile; the
+// epilogue consumes the solution.  Both are small structs passed by value.
+#pragma once
+
+#include "tile.hpp"
+
+namespace trid {
+
+struct StridedGeom {
+    i64 inner;  // line stride = number of lines per outer index
+    i64 nib;    // blocks along inner = ceil(inner / L)
+    int n;      // line length
+    int L;      // lines per block
+    int P;      // tiles per line
+};
+
+// ------------------------------------------------------------------ sources --
+// load<M>(base, st, g0, n, act, ra, rb, rc, rd): rows g0..g0+M-1 of the line at
+// element offset `base` with stride `st`.  Inactive threads and rows >= n get
+// identity rows.
+
+template <typename T>
+struct SrcArrays {  // per-point a, b, c arrays; rhs from d
+    const T *a, *b, *c, *d;
+    template <int M>
+    __device__ __forceinline__ void load(i64 base, i64 st, int g0, int n, bool act, T (&ra)[M],
+                                         T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            const bool v = act && g < n;
+            const i64 off = base + (i64)g * st;
+            ra[k] = (v && g > 0) ? a[off] : T(0);
+            rb[k] = v ? b[off] : T(1);
+            rc[k] = (v && g < n - 1) ? c[off] : T(0);
+            rd[k] = v ? d[off] : T(0);
+        }
+    }
+};
+
+template <typename T>
+struct SrcConst {  // the same (a, b, c) on every row, generated in-kernel
+    T a, b, c;
+    const T *d;
+    template <int M>
+    __device__ __forceinline__ void load(i64 base, i64 st, int g0, int n, bool act, T (&ra)[M],
+                                         T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            const bool v = act && g < n;
+            ra[k] = (v && g > 0) ? a : T(0);
+            rb[k] = v ? b : T(1);
+            rc[k] = (v && g < n - 1) ? c : T(0);
+            rd[k] = v ? d[base + (i64)g * st] : T(0);
+        }
+    }
+};
+
+template <typename T>
+struct SrcS {  // rows (-s, 1 + 2 s, -s) from a per-point s array
+    const T *s, *d;
+    template <int M>
+    __device__ __forceinline__ void load(i64 base, i64 st, int g0, int n, bool act, T (&ra)[M],
+                                         T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            const bool v = act && g < n;
+            const i64 off = base + (i64)g * st;
+            const T sv = v ? s[off] : T(0);
+            ra[k] = (g > 0) ? -sv : T(0);
+            rb[k] = T(1) + T(2) * sv;
+            rc[k] = (g < n - 1) ? -sv : T(0);
+            rd[k] = v ? d[off] : T(0);
+        }
+    }
+};
+
+// Transposed rows (for adjoint solves): row g of A^T has sub-diagonal c_{g-1},
+// diagonal b_g and super-diagonal a_{g+1}.
+template <typename T>
+struct SrcArraysT {
+    const T *a, *b, *c, *d;
+    template <int M>
+    __device__ __forceinline__ void load(i64 base, i64 st, int g0, int n, bool act, T (&ra)[M],
+                                         T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            const bool v = act && g < n;
+            const i64 off = base + (i64)g * st;
+            ra[k] = (v && g > 0) ? c[off - st] : T(0);
+            rb[k] = v ? b[off] : T(1);
+            rc[k] = (v && g < n - 1) ? a[off + st] : T(0);
+            rd[k] = v ? d[off] : T(0);
+        }
+    }
+};
+
+template <typename T>
+struct SrcST {  // transposed rows of the s operator: (-s_{g-1}, 1 + 2 s_g, -s_{g+1})
+    const T *s, *d;
+    template <int M>
+    __device__ __forceinline__ void load(i64 base, i64 st, int g0, int n, bool act, T (&ra)[M],
+                                         T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
+        T sv[M + 2];
+#pragma unroll
+        for (int k = 0; k < M + 2; ++k) {
+            const int g = g0 + k - 1;
+            sv[k] = (act && g >= 0 && g < n) ? s[base + (i64)g * st] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            const bool v = act && g < n;
+            ra[k] = (g > 0) ? -sv[k] : T(0);
+            rb[k] = T(1) + T(2) * sv[k + 1];
+            rc[k] = (g < n - 1) ? -sv[k + 2] : T(0);
+            rd[k] = v ? d[base + (i64)g * st] : T(0);
+        }
+    }
+};
+
+// ---------------------------------------------------------------- epilogues --
+// prefetch<M>(...) runs with the loads (before any barrier) so that operands of
+// the epilogue are in flight together with the rows; store<M>(...) writes.
+
+template <typename T>
+struct EpiStore {  // x = solution
+    T *x;
+    template <int M>
+    struct Pre {};
+    template <int M>
+    __device__ __forceinline__ void prefetch(Pre<M> &, i64, i64, int, int, bool) const {}
+    template <int M>
+    __device__ __forceinline__ void store(const Pre<M> &, i64 base, i64 st, int g0, int n, bool act,
+                                          const T (&u)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            if (act && g < n) x[base + (i64)g * st] = u[k];
+        }
+    }
+};
+
+template <typename T>
+struct EpiAdd {  // u += solution (the update of Alg. 3, fused into the last solve)
+    T *u;
+    template <int M>
+    struct Pre {
+        T v[M];
+    };
+    template <int M>
+    __device__ __forceinline__ void prefetch(Pre<M> &pre, i64 base, i64 st, int g0, int n,
+                                             bool act) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            pre.v[k] = (act && g < n) ? u[base + (i64)g * st] : T(0);
+        }
+    }
+    template <int M>
+    __device__ __forceinline__ void store(const Pre<M> &pre, i64 base, i64 st, int g0, int n,
+                                          bool act, const T (&x)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            if (act && g < n) u[base + (i64)g * st] = pre.v[k] + x[k];
+        }
+    }
+};
+
+// Adjoint epilogue, arrays form: lambda -> g; ga = -lambda x_{g-1}, gb = -lambda x_g,
+// gc = -lambda x_{g+1} (0 at the ignored a_0 / c_{N-1}).
+template <typename T>
+struct EpiAdjArrays {
+    const T *x;
+    T *g, *ga, *gb, *gc;
+    template <int M>
+    struct Pre {
+        T xv[M + 2];
+    };
+    template <int M>
+    __device__ __forceinline__ void prefetch(Pre<M> &pre, i64 base, i64 st, int g0, int n,
+                                             bool act) const {
+#pragma unroll
+        for (int k = 0; k < M + 2; ++k) {
+            const int gg = g0 + k - 1;
+            pre.xv[k] = (act && gg >= 0 && gg < n) ? x[base + (i64)gg * st] : T(0);
+        }
+    }
+    template <int M>
+    __device__ __forceinline__ void store(const Pre<M> &pre, i64 base, i64 st, int g0, int n,
+                                          bool act, const T (&lam)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int gg = g0 + k;
+            if (act && gg < n) {
+                const i64 off = base + (i64)gg * st;
+                g[off] = lam[k];
+                ga[off] = -lam[k] * pre.xv[k];
+                gb[off] = -lam[k] * pre.xv[k + 1];
+                gc[off] = -lam[k] * pre.xv[k + 2];
+            }
+        }
+    }
+};
+
+// Adjoint epilogue, s form: lambda -> g; gs += lambda (x_{g-1} - 2 x_g + x_{g+1}).
+template <typename T>
+struct EpiAdjS {
+    const T *x;
+    T *g, *gs;
+    template <int M>
+    struct Pre {
+        T xv[M + 2];
+        T sv[M];
+    };
+    template <int M>
+    __device__ __forceinline__ void prefetch(Pre<M> &pre, i64 base, i64 st, int g0, int n,
+                                             bool act) const {
+#pragma unroll
+        for (int k = 0; k < M + 2; ++k) {
+            const int gg = g0 + k - 1;
+            pre.xv[k] = (act && gg >= 0 && gg < n) ? x[base + (i64)gg * st] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int gg = g0 + k;
+            pre.sv[k] = (act && gg < n) ? gs[base + (i64)gg * st] : T(0);
+        }
+    }
+    template <int M>
+    __device__ __forceinline__ void store(const Pre<M> &pre, i64 base, i64 st, int g0, int n,
+                                          bool act, const T (&lam)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int gg = g0 + k;
+            if (act && gg < n) {
+                const i64 off = base + (i64)gg * st;
+                g[off] = lam[k];
+                gs[off] = pre.sv[k] + lam[k] * (pre.xv[k] - T(2) * pre.xv[k + 1] + pre.xv[k + 2]);
+            }
+        }
+    }
+};
+
+// ------------------------------------------------------------------ kernels --
+
+template <typename T, int M, int MAXT, class Src, class Epi>
+__global__ __launch_bounds__(MAXT) void k_strided(StridedGeom gm, Src src, Epi epi) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sh = reinterpret_cast<T *>(smem_raw);
+    const int L = gm.L, P = gm.P;
+    const int t = threadIdx.x, l = t % L, p = t / L;
+    const i64 blk = xcd_block_id();
+    const i64 ib = blk % gm.nib, ob = blk / gm.nib;
+    const i64 ii = ib * L + l;
+    const bool act = ii < gm.inner;
+    const i64 st = gm.inner;
+    const i64 base = ob * (i64)gm.n * st + (act ? ii : 0);
+    const int g0 = p * M;
+    T ra[M], rb[M], rc[M], rd[M];
+    src.template load<M>(base, st, g0, gm.n, act, ra, rb, rc, rd);
+    typename Epi::template Pre<M> pre;
+    epi.template prefetch<M>(pre, base, st, g0, gm.n, act);
+    T u[M];
+    tile_solve<T, M>(ra, rb, rc, rd, sh, L * P, P, p, t, L, u);
+    epi.template store<M>(pre, base, st, g0, gm.n, act, u);
+}
+
+// ------------------------------------------------------------ staged kernel --
+
+struct StagedGeom {
+    i64 nlines;  // number of contiguous lines
+    int n;       // line length
+    int L;       // lines per block
+    int P;       // tiles per line
+    int ls;      // LDS elements per staged line (>= P * (M + 1))
+};
+
+// LDS position of element i of staged line ll (tiles padded to M+1 elements).
+template <int M>
+__device__ __forceinline__ int staged_pos(int ll, int i, int ls) {
+    return ll * ls + (i / M) * (M + 1) + (i % M);
+}
+
+// Cooperative coalesced copy of `cnt` contiguous elements from global `src`
+// into staged positions of region `dst` (line length n).
+template <typename T, int M>
+__device__ __forceinline__ void stage_in(T *__restrict__ dst, const T *__restrict__ src, int cnt,
+                                         int n, int ls) {
+    const int nt = blockDim.x;
+    int ll = threadIdx.x / n, i = threadIdx.x % n;
+    const int dl = nt / n, di = nt % n;
+    for (int e = threadIdx.x; e < cnt; e += nt) {
+        dst[staged_pos<M>(ll, i, ls)] = src[e];
+        ll += dl;
+        i += di;
+        if (i >= n) {
+            i -= n;
+            ++ll;
+        }
+    }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void stage_out(T *__restrict__ dst, const T *__restrict__ src, int cnt,
+                                          int n, int ls) {
+    const int nt = blockDim.x;
+    int ll = threadIdx.x / n, i = threadIdx.x % n;
+    const int dl = nt / n, di = nt % n;
+    for (int e = threadIdx.x; e < cnt; e += nt) {
+        dst[e] = src[staged_pos<M>(ll, i, ls)];
+        ll += dl;
+        i += di;
+        if (i >= n) {
+            i -= n;
+            ++ll;
+        }
+    }
+}
+
+// Staged sources: stage(regions, ..., scratch) fills LDS regions from global
+// memory for lines [o0, o0 + nl) (scratch: the reduced-solve LDS area, free
+// until the first barrier after staging); rows(...) builds the raw rows of one
+// tile from LDS.
+
+template <typename T>
+struct StgArrays {
+    static constexpr int kRegions = 4;
+    const T *a, *b, *c, *d;
+    template <int M>
+    __device__ __forceinline__ void stage(T *__restrict__ sh, int reg, i64 o0, int nl, int n,
+                                          int ls, void *) const {
+        const i64 off = o0 * n;
+        const int cnt = nl * n;
+        stage_in<T, M>(sh, a + off, cnt, n, ls);
+        stage_in<T, M>(sh + reg, b + off, cnt, n, ls);
+        stage_in<T, M>(sh + 2 * reg, c + off, cnt, n, ls);
+        stage_in<T, M>(sh + 3 * reg, d + off, cnt, n, ls);
+    }
+    template <int M>
+    __device__ __forceinline__ void rows(const T *__restrict__ sh, int reg, int pos, int g0, int n,
+                                         bool act, T (&ra)[M], T (&rb)[M], T (&rc)[M],
+                                         T (&rd)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            const bool v = act && g < n;
+            ra[k] = (v && g > 0) ? sh[pos + k] : T(0);
+            rb[k] = v ? sh[reg + pos + k] : T(1);
+            rc[k] = (v && g < n - 1) ? sh[2 * reg + pos + k] : T(0);
+            rd[k] = v ? sh[3 * reg + pos + k] : T(0);
+        }
+    }
+};
+
+template <typename T>
+struct StgConst {
+    static constexpr int kRegions = 1;
+    T a, b, c;
+    const T *d;
+    template <int M>
+    __device__ __forceinline__ void stage(T *__restrict__ sh, int, i64 o0, int nl, int n,
+                                          int ls, void *) const {
+        stage_in<T, M>(sh, d + o0 * n, nl * n, n, ls);
+    }
+    template <int M>
+    __device__ __forceinline__ void rows(const T *__restrict__ sh, int, int pos, int g0, int n,
+                                         bool act, T (&ra)[M], T (&rb)[M], T (&rc)[M],
+                                         T (&rd)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            const bool v = act && g < n;
+            ra[k] = (v && g > 0) ? a : T(0);
+            rb[k] = v ? b : T(1);
+            rc[k] = (v && g < n - 1) ? c : T(0);
+            rd[k] = v ? sh[pos + k] : T(0);
+        }
+    }
+};
+
+template <typename T>
+struct StgS {
+    static constexpr int kRegions = 2;
+    const T *s, *d;
+    template <int M>
+    __device__ __forceinline__ void stage(T *__restrict__ sh, int reg, i64 o0, int nl, int n,
+                                          int ls, void *) const {
+        stage_in<T, M>(sh, s + o0 * n, nl * n, n, ls);
+        stage_in<T, M>(sh + reg, d + o0 * n, nl * n, n, ls);
+    }
+    template <int M>
+    __device__ __forceinline__ void rows(const T *__restrict__ sh, int reg, int pos, int g0, int n,
+                                         bool act, T (&ra)[M], T (&rb)[M], T (&rc)[M],
+                                         T (&rd)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            const bool v = act && g < n;
+            const T sv = v ? sh[pos + k] : T(0);
+            ra[k] = (g > 0) ? -sv : T(0);
+            rb[k] = T(1) + T(2) * sv;
+            rc[k] = (g < n - 1) ? -sv : T(0);
+            rd[k] = v ? sh[reg + pos + k] : T(0);
+        }
+    }
+};
+
+// Staged epilogue: results are in LDS region 0 (rhs region for StgConst, the a
+// region otherwise -- it is no longer read); copy them out coalesced.
+template <typename T>
+struct StgOut {
+    T *x;
+    template <int M>
+    __device__ __forceinline__ void out(const T *__restrict__ sh, i64 o0, int nl, int n,
+                                        int ls) const {
+        stage_out<T, M>(x + o0 * n, sh, nl * n, n, ls);
+    }
+};
+
+template <typename T, int M, int MAXT, class Src, class Out>
+__global__ __launch_bounds__(MAXT) void k_staged(StagedGeom gm, Src src, Out out) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sh = reinterpret_cast<T *>(smem_raw);
+    const int L = gm.L, P = gm.P, n = gm.n, ls = gm.ls;
+    const int reg = L * ls;
+    const int S = L * P;
+    T *red = sh + Src::kRegions * reg;  // reduced-solve scratch (6 S elements)
+    const int t = threadIdx.x, p = t % P, l = t / P;
+    const i64 o0 = xcd_block_id() * L;
+    const int nl = (int)((gm.nlines - o0) < (i64)L ? (gm.nlines - o0) : (i64)L);
+    src.template stage<M>(sh, reg, o0, nl, n, ls, red);
+    __syncthreads();
+    const bool act = l < nl;
+    const int pos = l * ls + p * (M + 1);
+    T ra[M], rb[M], rc[M], rd[M];
+    src.template rows<M>(sh, reg, pos, p * M, n, act, ra, rb, rc, rd);
+    T u[M];
+    tile_solve<T, M>(ra, rb, rc, rd, red, S, P, p, t, 1, u);
+    // region 0 is dead once every thread has read its rows (they all passed
+    // the barriers inside tile_solve): overwrite own positions with results
+#pragma unroll
+    for (int k = 0; k < M; ++k) sh[pos + k] = u[k];
+    __syncthreads();
+    out.template out<M>(sh, o0, nl, n, ls);
+}
+
+}  // namespace trid

@@ -1,0 +1,172 @@
+// tile.hpp -- device building blocks of the batched tridiagonal line solver (gfx950).
+//
+// Every line of N rows is cut into P tiles of M consecutive rows; one thread
+// owns one tile.  Per tile, the "modified Thomas" sweep of eq. (7)
+// (arxiv 2201.03950, Section III-B, larger-systems solve) expresses each
+// interior unknown through the tile's first and last unknowns, keeping the
+// tile in registers, so every array is read once and written once.  The 2P
+// first/last unknowns of a line form a tridiagonal reduced system; one local
+// elimination step turns it into a P-row system over the tiles' first unknowns,
+// which the P threads of the line solve with PCR (Alg. 2) through LDS -- the
+// Thomas-PCR hybrid of Section III-B.  A final substitution recovers the rows.
+//
+// Rows beyond the end of a line are identity rows (a = c = d = 0, b = 1), which
+// leave the solution of the real rows unchanged.  a at row 0 and c at row N-1
+// are never read (eq. (1)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trid {
+
+using i64 = int64_t;
+
+// Workgroup id remapped so that each of the 8 XCDs (each with its own L2)
+// receives one contiguous range of logical blocks: hardware dispatches
+// workgroup w to XCD w % 8.  Neighbouring logical blocks (which share stencil
+// halo lines) then run on the same XCD and hit the same L2.
+__device__ __forceinline__ i64 xcd_block_id() {
+    const unsigned G = gridDim.x, w = blockIdx.x;
+    const unsigned q = G >> 3, r = G & 7u, x = w & 7u, idx = w >> 3;
+    return (x < r) ? (i64)x * (q + 1) + idx : (i64)r * (q + 1) + (i64)(x - r) * q + idx;
+}
+
+// Result of the per-tile sweep (eq. (7)).
+//   first row: fa*l_{p-1} + fb*f_p + fc*l_p = fd   (f_p, l_p: tile's first/last unknown)
+//   last row:  la*f_p + l_p + lc*f_{p+1} = ld
+//   interior:  ap[k]*f_p + u_k + cp[k]*l_p = dp[k], k = 1..M-2
+template <typename T, int M>
+struct TileState {
+    T ap[M], cp[M], dp[M];
+    T fa, fb, fc, fd;
+    T la, lc, ld;
+};
+
+// Forward then backward sweep of the modified Thomas algorithm on one tile.
+// Inputs are the raw rows (sub, diag, super, rhs) of the tile's M rows.
+template <typename T, int M>
+__device__ __forceinline__ void tile_eliminate(const T (&ra)[M], const T (&rb)[M], const T (&rc)[M],
+                                               const T (&rd)[M], TileState<T, M> &s) {
+    static_assert(M >= 3, "tiles need at least three rows");
+    const T r1 = T(1) / rb[1];
+    s.ap[1] = ra[1] * r1;
+    s.cp[1] = rc[1] * r1;
+    s.dp[1] = rd[1] * r1;
+#pragma unroll
+    for (int k = 2; k < M; ++k) {
+        const T r = T(1) / (rb[k] - ra[k] * s.cp[k - 1]);
+        s.ap[k] = -r * ra[k] * s.ap[k - 1];
+        s.cp[k] = r * rc[k];
+        s.dp[k] = r * (rd[k] - ra[k] * s.dp[k - 1]);
+    }
+    s.la = s.ap[M - 1];
+    s.lc = s.cp[M - 1];
+    s.ld = s.dp[M - 1];
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) {
+        s.dp[k] -= s.cp[k] * s.dp[k + 1];
+        s.ap[k] -= s.cp[k] * s.ap[k + 1];
+        s.cp[k] = -s.cp[k] * s.cp[k + 1];
+    }
+    s.fa = ra[0];
+    s.fb = rb[0] - rc[0] * s.ap[1];
+    s.fc = -rc[0] * s.cp[1];
+    s.fd = rd[0] - rc[0] * s.dp[1];
+}
+
+// Reduced solve of one line across its P tiles.
+//   sh      : LDS scratch of 6*S elements, S = number of threads of the block
+//   slot    : this thread's slot in [0, S)
+//   pstride : slot distance between tiles p and p+1 of the same line
+// Every thread of the block must call this (it contains barriers); P is
+// uniform over the block.  Returns f (tile's first unknown) and lv (its last).
+template <typename T, int M>
+__device__ __forceinline__ void reduced_pcr(const TileState<T, M> &ts, T *__restrict__ sh, int S,
+                                            int P, int p, int slot, int pstride, T &f, T &lv) {
+    T *b0a = sh, *b0c = sh + S, *b0d = sh + 2 * S;
+    T *b1a = sh + 3 * S, *b1c = sh + 4 * S, *b1d = sh + 5 * S;
+    // 1. each tile publishes its last row (through buffer 1, first used by level 2)
+    b1a[slot] = ts.la;
+    b1c[slot] = ts.lc;
+    b1d[slot] = ts.ld;
+    __syncthreads();
+    T pa = T(0), pc = T(0), pd = T(0);
+    if (p > 0) {
+        pa = b1a[slot - pstride];
+        pc = b1c[slot - pstride];
+        pd = b1d[slot - pstride];
+    }
+    // 2. eliminate l_{p-1} (previous tile's last row) and l_p (own last row)
+    //    from the first row: a P-row tridiagonal system over f_0..f_{P-1}
+    const T gsub = -ts.fa * pa;
+    const T gdia = ts.fb - ts.fa * pc - ts.fc * ts.la;
+    const T gsup = -ts.fc * ts.lc;
+    const T grhs = ts.fd - ts.fa * pd - ts.fc * ts.ld;
+    const T rg = T(1) / gdia;
+    T a = gsub * rg, c = gsup * rg, d = grhs * rg;
+    // 3. PCR (Alg. 2) over the P rows, double-buffered: one barrier per level
+    int lev = 0;
+    for (int s = 1; s < P; s <<= 1, ++lev) {
+        T *ba = (lev & 1) ? b1a : b0a;
+        T *bc = (lev & 1) ? b1c : b0c;
+        T *bd = (lev & 1) ? b1d : b0d;
+        ba[slot] = a;
+        bc[slot] = c;
+        bd[slot] = d;
+        __syncthreads();
+        T am = T(0), cm = T(0), dm = T(0), an = T(0), cn = T(0), dn = T(0);
+        if (p - s >= 0) {
+            const int q = slot - s * pstride;
+            am = ba[q];
+            cm = bc[q];
+            dm = bd[q];
+        }
+        if (p + s < P) {
+            const int q = slot + s * pstride;
+            an = ba[q];
+            cn = bc[q];
+            dn = bd[q];
+        }
+        const T r = T(1) / (T(1) - a * cm - c * an);
+        const T na = -r * (a * am);
+        const T nc = -r * (c * cn);
+        const T nd = r * (d - a * dm - c * dn);
+        a = na;
+        c = nc;
+        d = nd;
+    }
+    f = d;
+    // 4. last unknown of the tile from its last row; needs f_{p+1}
+    T fn = T(0);
+    if (P > 1) {
+        T *bx = (lev & 1) ? b1d : b0d;  // last read at level lev-2: free
+        bx[slot] = f;
+        __syncthreads();
+        if (p + 1 < P) fn = bx[slot + pstride];
+    }
+    lv = ts.ld - ts.la * f - ts.lc * fn;
+}
+
+// Back substitution (eq. (7)): the tile's M unknowns.
+template <typename T, int M>
+__device__ __forceinline__ void tile_backsub(const TileState<T, M> &ts, T f, T lv, T (&u)[M]) {
+    u[0] = f;
+    u[M - 1] = lv;
+#pragma unroll
+    for (int k = 1; k < M - 1; ++k) u[k] = ts.dp[k] - ts.ap[k] * f - ts.cp[k] * lv;
+}
+
+// Full line-tile solve of raw rows into u (all threads of the block must call).
+template <typename T, int M>
+__device__ __forceinline__ void tile_solve(const T (&ra)[M], const T (&rb)[M], const T (&rc)[M],
+                                           const T (&rd)[M], T *__restrict__ sh, int S, int P,
+                                           int p, int slot, int pstride, T (&u)[M]) {
+    TileState<T, M> ts;
+    tile_eliminate<T, M>(ra, rb, rc, rd, ts);
+    T f, lv;
+    reduced_pcr<T, M>(ts, sh, S, P, p, slot, pstride, f, lv);
+    tile_backsub<T, M>(ts, f, lv, u);
+}
+
+}  // namespace trid

@@ -1,0 +1,116 @@
+"""The C ABI without a GPU: the library loads, exports every declared symbol, and
+validates arguments on the host before any HIP call (CPU only)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2201_03950_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trid.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(trid_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_2201_03950_amd import build
+
+        build.build()
+    return B.load_library()
+
+
+@pytest.fixture()
+def h(lib):
+    hp = ctypes.c_void_p()
+    assert lib.trid_create(ctypes.byref(hp)) == 0
+    yield hp
+    assert lib.trid_destroy(hp) == 0
+
+
+def test_every_declared_symbol_is_exported_and_bound(lib):
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.SIGNATURES), set(names) ^ set(B.SIGNATURES)
+
+
+def test_version_and_create_null(lib):
+    assert lib.trid_version() >= 10000
+    assert lib.trid_create(None) == 1
+    assert b"NULL" in lib.trid_last_error(None)
+    assert lib.trid_destroy(None) == 0
+
+
+def _dims(*v):
+    return (ctypes.c_int64 * len(v))(*v)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize(
+    "ndim,dims,axis,batch,dt",
+    [
+        (0, (4,), 0, 1, 1),
+        (4, (4, 4, 4, 4), 0, 1, 1),
+        (2, (4, 4), 2, 1, 1),
+        (2, (4, 4), -1, 1, 1),
+        (2, (4, 0), 0, 1, 1),
+        (2, (4, 4), 0, 0, 1),
+        (2, (4, 4), 0, 1, 7),
+    ],
+)
+def test_gtsv_rejects_bad_geometry(lib, h, ndim, dims, axis, batch, dt):
+    rc = lib.trid_gtsv_batched(h, dt, FAKE, FAKE, FAKE, FAKE, ndim, _dims(*dims), axis, batch)
+    assert rc == 1
+    assert lib.trid_last_error(h) != b""
+
+
+def test_null_pointers_rejected(lib, h):
+    d = _dims(8, 8)
+    assert lib.trid_gtsv_batched(h, 1, None, FAKE, FAKE, FAKE, 2, d, 0, 1) == 1
+    assert lib.trid_gtsv_batched_const(h, 1, -1.0, 4.0, -1.0, None, 2, d, 0, 1) == 1
+    assert lib.trid_gtsv_batched_s(h, 1, None, FAKE, 2, d, 0, 1) == 1
+    assert lib.trid_gtsv_batched(h, 1, FAKE, FAKE, FAKE, FAKE, 2, None, 0, 1) == 1
+    assert lib.trid_adi_step(h, 1, None, None, 0.2, 3, _dims(8, 8, 8), 1, 1, 0) == 1
+    assert lib.trid_gtsv_batched_adjoint(h, 1, FAKE, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, 2, d, 0, 1) == 1
+    assert lib.trid_gtsv_batched_s_adjoint(h, 1, FAKE, FAKE, None, FAKE, 2, d, 0, 1) == 1
+    assert lib.trid_gtsv_batched(None, 1, FAKE, FAKE, FAKE, FAKE, 2, d, 0, 1) == 1
+
+
+def test_line_longer_than_limit_is_unsupported(lib, h):
+    rc = lib.trid_gtsv_batched(h, 1, FAKE, FAKE, FAKE, FAKE, 1, _dims(8193), 0, 1)
+    assert rc == 4
+    assert b"TRID_MAX_LINE" in lib.trid_last_error(h)
+
+
+def test_adi_argument_checks(lib, h):
+    assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 1, _dims(8), 1, 1, 0) == 1  # ADI needs 2D/3D
+    assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, -1, 0) == 1
+    assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, 1, 8) == 1  # unknown flag
+    assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, 0, 0) == 0  # no steps: no-op
+
+
+def test_set_tile_validation(lib, h):
+    assert lib.trid_set_tile(h, 7, 0) == 1
+    assert lib.trid_set_tile(h, 8, 3) == 1
+    assert lib.trid_set_tile(h, 16, 32) == 0
+    assert lib.trid_set_tile(h, 0, 0) == 0
+    assert lib.trid_set_tile(None, 0, 0) == 1
+
+
+def test_set_stream_and_error_text(lib, h):
+    assert lib.trid_set_stream(h, None) == 0
+    assert lib.trid_set_stream(None, None) == 1
+    assert lib.trid_gtsv_batched(h, 1, FAKE, FAKE, FAKE, FAKE, 5, _dims(1), 0, 1) == 1
+    assert b"ndim" in lib.trid_last_error(h)

@@ -1,0 +1,220 @@
+"""GPU parity of the batched line solves and the ADI step against the CPU oracle.
+
+Tolerances (relative error per line in the infinity norm, max over lines):
+FP64 <= 1e-12; FP32 <= 1e-5 against the FP64 oracle run on the same
+FP32-rounded inputs.  ADI fields use max|u - u_ref| / max|u_ref|.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+TOL = {np.float64: 1e-12, np.float32: 1e-5}
+
+
+@pytest.fixture(scope="module")
+def trid():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2201_03950_amd as trid
+
+    trid.load_library()
+    yield trid
+    trid.set_tile(0, 0)
+
+
+def _t(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _line_err(x, ref, axis):
+    ax = x.ndim - 1 - axis
+    num = np.max(np.abs(np.moveaxis(x - ref, ax, -1)), axis=-1)
+    den = np.max(np.abs(np.moveaxis(ref, ax, -1)), axis=-1)
+    return float(np.max(num / np.maximum(den, 1e-300)))
+
+
+def _field_err(x, ref):
+    return float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
+
+
+# ------------------------------------------------------------------ config 0 --
+
+@pytest.mark.parametrize("layout", ["x", "y"])
+def test_config0_1024_systems_n256_fp64(trid, orc, layout):
+    a, b, c, d = gen.dd_lines(1024, 256, seed=0)
+    if layout == "x":  # dims [256, 1024], axis 0: each system contiguous
+        arrs = [v[None] for v in (a, b, c, d)]
+        axis = 0
+    else:  # dims [1024, 256], axis 1: systems interleaved
+        arrs = [np.ascontiguousarray(v.T)[None] for v in (a, b, c, d)]
+        axis = 1
+    ref = orc.gtsv(*arrs, axis)
+    ta, tb, tc, td = (_t(v) for v in arrs)
+    trid.gtsv(ta, tb, tc, td, axis)
+    assert _line_err(td.cpu().numpy(), ref, axis) <= 1e-12
+
+
+# ------------------------------------------------------ geometry / plan sweep --
+
+GEOMS = [
+    ((5, 6, 7), 2, 0), ((5, 6, 7), 2, 1), ((5, 6, 7), 2, 2),
+    ((257, 3), 2, 0), ((3, 300), 1, 1), ((70, 33), 3, 1),
+    ((1,), 9, 0), ((2,), 9, 0), ((3,), 9, 0),
+    ((64, 1000), 1, 1), ((1000, 5), 1, 0), ((9, 10, 129), 1, 2),
+    ((130, 1, 17), 2, 1),
+]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("geom", GEOMS, ids=[str(g) for g in GEOMS])
+def test_arrays_any_axis(trid, orc, dt, geom):
+    dims, batch, axis = geom
+    a, b, c, d = (v.astype(dt) for v in gen.dd_mesh(dims, batch, seed=sum(dims) + axis))
+    ref = orc.gtsv(a, b, c, d, axis)
+    ta, tb, tc, td = (_t(v) for v in (a, b, c, d))
+    trid.gtsv(ta, tb, tc, td, axis)
+    assert _line_err(td.cpu().numpy().astype(np.float64), ref, axis) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("mode", ["const", "s"])
+@pytest.mark.parametrize("geom", [((33, 41, 10), 2, 0), ((33, 41, 10), 2, 1), ((33, 41, 10), 2, 2),
+                                  ((300, 7), 1, 0), ((7, 300), 1, 1)])
+def test_generated_coefficients(trid, orc, dt, mode, geom):
+    dims, batch, axis = geom
+    rng = np.random.default_rng(5)
+    shape = gen.mesh_shape(dims, batch)
+    d = rng.standard_normal(shape).astype(dt)
+    td = _t(d)
+    if mode == "const":
+        ref = orc.gtsv_const(-0.3, 1.6, -0.3, d, axis)
+        trid.gtsv_const(-0.3, 1.6, -0.3, td, axis)
+    else:
+        s = (0.1 * np.exp(0.5 * rng.standard_normal(shape))).astype(dt)
+        ref = orc.gtsv_s(s, d, axis)
+        trid.gtsv_s(_t(s), td, axis)
+    assert _line_err(td.cpu().numpy().astype(np.float64), ref, axis) <= TOL[dt]
+
+
+PLANS = [(8, 1), (8, 2), (8, 16), (8, 64), (16, 1), (16, 8), (16, 32), (32, 1), (32, 4), (32, 8)]
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=[str(p) for p in PLANS])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_forced_tile_plans_agree(trid, orc, plan, axis):
+    dims = (77, 75) if axis == 0 else (75, 77)
+    a, b, c, d = gen.dd_mesh(dims, 3, seed=plan[0] + plan[1])
+    ref = orc.gtsv(a, b, c, d, axis)
+    trid.set_tile(*plan)
+    try:
+        ta, tb, tc, td = (_t(v) for v in (a, b, c, d))
+        trid.gtsv(ta, tb, tc, td, axis)
+    finally:
+        trid.set_tile(0, 0)
+    assert _line_err(td.cpu().numpy(), ref, axis) <= 1e-12
+
+
+# ------------------------------------------------------------------------ ADI --
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("perpoint", [False, True])
+@pytest.mark.parametrize("graph", [False, True])
+def test_adi3d_small_matches_oracle(trid, orc, dt, perpoint, graph):
+    dims, batch, steps = (40, 33, 29), 2, 3
+    u = gen.adi3d_field(dims, batch, seed=3).astype(dt)
+    s = None
+    if perpoint:
+        s = (0.2 * np.random.default_rng(4).lognormal(0.0, 0.5, u.shape)).astype(dt)
+        ref = orc.adi_step(u, s=s, nsteps=steps)
+    else:
+        ref = orc.adi_step(u, s0=0.2, nsteps=steps)
+    tu = _t(u)
+    trid.adi_step(tu, s=_t(s) if s is not None else None, s0=0.2, nsteps=steps, graph=graph)
+    if graph:  # replay the captured graph once more and compare with one more oracle step
+        trid.adi_step(tu, s=_t(s) if s is not None else None, s0=0.2, nsteps=steps, graph=graph)
+        ref = orc.adi_step(ref, s=s, s0=0.2, nsteps=steps)
+    assert _field_err(tu.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("perpoint", [False, True])
+def test_adi2d_small_matches_oracle(trid, orc, dt, perpoint):
+    dims, batch, steps = (61, 45), 3, 4
+    u = gen.adi3d_field(dims, batch, seed=8).astype(dt)
+    s = (0.1 * np.exp(0.5 * np.random.default_rng(9).standard_normal(u.shape))).astype(dt) if perpoint else None
+    ref = orc.adi_step(u, s=s, s0=0.3, nsteps=steps)
+    tu = _t(u)
+    trid.adi_step(tu, s=_t(s) if s is not None else None, s0=0.3, nsteps=steps)
+    assert _field_err(tu.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
+
+
+def _mu(p, n):
+    return 4.0 * math.sin(math.pi * p / (2.0 * (n + 1))) ** 2
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+def test_adi3d_256cubed_fourier_decay(trid, dt):
+    """Full-size (256^3, bench launch configuration) check against the closed form."""
+    dims, modes, s, steps = (256, 256, 256), (3, 5, 2), 0.2, 10
+    u0 = gen.fourier_mode_3d(dims, modes)
+    mus = [_mu(p, n) for p, n in zip(modes, dims)]
+    g = 1.0 - 2.0 * s * sum(mus) / math.prod(1.0 + s * m for m in mus)
+    tu = _t(u0.astype(dt))
+    trid.adi_step(tu, s0=s, nsteps=steps, graph=True)
+    err = float(np.max(np.abs(tu.cpu().numpy().astype(np.float64) - g ** steps * u0)))
+    assert err <= (1e-12 if dt == np.float64 else 2e-6), err
+
+
+def test_adi3d_256cubed_one_step_matches_oracle(trid, orc):
+    u = gen.adi3d_field((256, 256, 256), seed=1)
+    ref = orc.adi_step(u, s0=0.2, nsteps=1)
+    tu = _t(u)
+    trid.adi_step(tu, s0=0.2, nsteps=1, graph=True)
+    assert _field_err(tu.cpu().numpy(), ref) <= 1e-12
+
+
+# ------------------------------------------------------------------- adjoints --
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("geom", [((33, 41, 10), 2, 0), ((33, 41, 10), 2, 1), ((33, 41, 10), 2, 2),
+                                  ((260,), 5, 0)])
+def test_arrays_adjoint_matches_oracle(trid, orc, dt, geom):
+    dims, batch, axis = geom
+    a, b, c, d = (v.astype(dt) for v in gen.dd_mesh(dims, batch, seed=12))
+    x = orc.gtsv(a, b, c, d, axis).astype(dt)
+    gy = np.random.default_rng(13).standard_normal(d.shape).astype(dt)
+    lam, ga, gb, gc = orc.gtsv_adjoint(a, b, c, x, gy, axis)
+    tg = _t(gy)
+    tga, tgb, tgc = (torch.empty_like(tg) for _ in range(3))
+    trid.gtsv_adjoint(_t(a), _t(b), _t(c), _t(x), tg, axis, tga, tgb, tgc)
+    assert _line_err(tg.cpu().numpy().astype(np.float64), lam, axis) <= TOL[dt]
+    for got, want in ((tga, ga), (tgb, gb), (tgc, gc)):
+        err = float(np.max(np.abs(got.cpu().numpy() - want)) / np.max(np.abs(want)))
+        assert err <= TOL[dt] * 10
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_s_adjoint_matches_oracle(trid, orc, dt, axis):
+    dims, batch = (31, 29, 27), 2
+    rng = np.random.default_rng(20 + axis)
+    shape = gen.mesh_shape(dims, batch)
+    s = (0.2 * rng.lognormal(0.0, 0.5, shape)).astype(dt)
+    x = rng.standard_normal(shape).astype(dt)
+    gy = rng.standard_normal(shape).astype(dt)
+    gs0 = rng.standard_normal(shape).astype(dt)
+    a, b, c = orc.implicit_coefs(s)
+    lam, ga, gb, gc = orc.gtsv_adjoint(a, b, c, x, gy, axis)
+    gs_ref = gs0 + (-ga + 2.0 * gb - gc)
+    tg, tgs = _t(gy), _t(gs0)
+    trid.gtsv_s_adjoint(_t(s), _t(x), tg, tgs, axis)
+    assert _line_err(tg.cpu().numpy().astype(np.float64), lam, axis) <= TOL[dt]
+    err = float(np.max(np.abs(tgs.cpu().numpy() - gs_ref)) / np.max(np.abs(gs_ref)))
+    assert err <= TOL[dt] * 10
