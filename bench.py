@@ -1,0 +1,270 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched tridiagonal line solves on one MI355X.
+
+One step = one ADI heat-diffusion step (Alg. 3 of arxiv 2201.03950) on a
+256 x 256 x 256 FP64 mesh with s = 0.2: the fused stencil + x-line solve, the
+y-line solve and the fused z-line solve + update (3 x 65,536 tridiagonal
+solves of length 256).  Inputs are seeded synthetic fields already resident in
+HBM.  Prints ONE JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-extra] [--no-cpu]
+
+value        tridiagonal solves per second over the K timed steps
+roofline     the dominant kernel's algorithmic bytes / its mean duration (HIP
+             events recorded by the library on the launch stream during the
+             timed steps) against the 8 TB/s HBM peak
+cpu_baseline the CPU oracle (plain C, OpenMP over lines) on a bounded sample
+extra        the other workloads: 1024 x 256 systems (x and y layouts, and a
+             262,144-system bandwidth variant), the FP32 ADI step, the 2D
+             64 x 1024^2 x-then-y solves, uneven batches and gradients
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "tridiag solves/s + HBM GB/s (% peak); 256^3 ADI step ms; fwd+bwd/fwd ratio"
+PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_adi3d_256_f64.json")
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources; a stored counter measurement is valid only for this hash."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2201_03950_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed PMC summary, or None if stale."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
+def log(msg):
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def sync():
+    import torch
+
+    torch.cuda.synchronize()
+
+
+def time_calls(fn, reps, warm=2):
+    """Mean wall seconds per call of fn() over `reps` calls (synchronised)."""
+    for _ in range(warm):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / reps
+
+
+def adi_main(trid, steps, warmup):
+    import torch
+
+    from workloads import gen
+
+    dims = (256, 256, 256)
+    pts = dims[0] * dims[1] * dims[2]
+    u = torch.from_numpy(gen.adi3d_field(dims, seed=1)).cuda()
+    for _ in range(warmup):
+        trid.adi_step(u, s0=0.2, nsteps=1)
+    sync()
+    trid.timing_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        trid.adi_step(u, s0=0.2, nsteps=1)
+    sync()
+    elapsed = time.perf_counter() - t0
+    kt = trid.timing_read()
+    trid.timing_enable(False)
+    # same steps replayed as one captured graph per step (production path)
+    for _ in range(2):
+        trid.adi_step(u, s0=0.2, nsteps=1, graph=True)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        trid.adi_step(u, s0=0.2, nsteps=1, graph=True)
+    sync()
+    elapsed_graph = time.perf_counter() - t0
+    w = 8
+    words = {"adi_stencil_x": 2, "adi_y": 2, "adi_z_update": 3}
+    kernels = {}
+    for name, (cnt, ms) in kt.items():
+        avg = ms / cnt
+        b = words[name] * w * pts
+        kernels[name] = {"mean_ms": round(avg, 5), "launches": cnt, "alg_bytes": b,
+                         "gbs": round(b / (avg * 1e-3) / 1e9, 1),
+                         "frac": round(b / (avg * 1e-3) / 1e9 / PEAK_GBS, 4)}
+    return {"elapsed": elapsed, "elapsed_graph": elapsed_graph, "kernels": kernels,
+            "solves_per_step": 3 * dims[1] * dims[2], "pts": pts}
+
+
+def extra_workloads(trid):
+    import numpy as np
+    import torch
+
+    from workloads import gen
+
+    out = {}
+    # -- 1024 systems of 256 rows, FP64, coefficient arrays (x and y layouts)
+    a, b, c, d = gen.dd_lines(1024, 256, seed=0)
+    for lay in ("x", "y"):
+        arr = [v[None] if lay == "x" else np.ascontiguousarray(v.T)[None] for v in (a, b, c, d)]
+        ta, tb, tc, td0 = (torch.from_numpy(v).cuda() for v in arr)
+        td = td0.clone()
+        axis = 0 if lay == "x" else 1
+        t = time_calls(lambda: trid.gtsv(ta, tb, tc, td, axis), 500, warm=20)
+        out["sys1024x256_f64_%s" % lay] = {"us_per_call": round(t * 1e6, 2),
+                                          "solves_per_s": round(1024 / t, 1),
+                                          "gbs": round(40 * 1024 * 256 / t / 1e9, 1)}
+    # -- bandwidth variant: 262,144 systems of 256 rows (2.7 GB moved per call)
+    nsys = 262144
+    rng_a, rng_b, rng_c, rng_d = gen.dd_lines(nsys, 256, seed=10)
+    for lay in ("x", "y"):
+        arr = [v[None] if lay == "x" else np.ascontiguousarray(v.T)[None]
+               for v in (rng_a, rng_b, rng_c, rng_d)]
+        ta, tb, tc, td = (torch.from_numpy(v).cuda() for v in arr)
+        del arr
+        axis = 0 if lay == "x" else 1
+        trid.timing_enable(True)
+        t = time_calls(lambda: trid.gtsv(ta, tb, tc, td, axis), 10)
+        kt = trid.timing_read()
+        trid.timing_enable(False)
+        name, (cnt, ms) = next(iter(kt.items()))
+        kern = ms / cnt * 1e-3
+        byts = 40 * nsys * 256
+        log("bandwidth variant %s layout done" % lay)
+        out["sys262144x256_f64_%s" % lay] = {
+            "ms_per_call": round(t * 1e3, 4), "kernel": name, "kernel_ms": round(kern * 1e3, 4),
+            "solves_per_s": round(nsys / kern, 1), "gbs": round(byts / kern / 1e9, 1),
+            "frac": round(byts / kern / 1e9 / PEAK_GBS, 4)}
+        del ta, tb, tc, td
+        torch.cuda.empty_cache()
+    # -- FP32 256^3 ADI step
+    u = torch.from_numpy(gen.adi3d_field((256, 256, 256), seed=1, dtype=np.float32)).cuda()
+    trid.timing_enable(True)
+    t = time_calls(lambda: trid.adi_step(u, s0=0.2, nsteps=1), 10)
+    kt = trid.timing_read()
+    trid.timing_enable(False)
+    pts = 256 ** 3
+    words = {"adi_stencil_x": 2, "adi_y": 2, "adi_z_update": 3}
+    out["adi3d_256_f32"] = {"ms_per_step": round(t * 1e3, 4), "kernels": {
+        k: {"mean_ms": round(ms / cnt, 5),
+            "frac": round(words[k] * 4 * pts / (ms / cnt * 1e-3) / 1e9 / PEAK_GBS, 4)}
+        for k, (cnt, ms) in kt.items()}}
+    del u
+    # -- 64 meshes of 1024^2: x then y solves with per-point s
+    s32, d32 = gen.adi2d_varcoef((1024, 1024), 64, seed=2)
+    for tag, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        ts = torch.from_numpy(s32).cuda().to(dt)
+        d0 = torch.from_numpy(d32).cuda().to(dt)
+        td = d0.clone()
+
+        def xy():
+            trid.gtsv_s(ts, td, 0)
+            trid.gtsv_s(ts, td, 1)
+
+        t = time_calls(xy, 5, warm=1)
+        wb = 8 if dt == torch.float64 else 4
+        byts = 6 * wb * 64 * 1024 * 1024
+        out["adi2d_64x1024sq_xy_%s" % tag] = {"ms": round(t * 1e3, 4), "gbs": round(byts / t / 1e9, 1),
+                                              "frac": round(byts / t / 1e9 / PEAK_GBS, 4)}
+        del ts, d0, td
+        torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(budget_s=12.0, max_steps=60):
+    """The oracle (never tuned) on the same 256^3 FP64 workload, a bounded number of steps."""
+    from oracle import oracle
+    from workloads import gen
+
+    oracle.build()
+    u = gen.adi3d_field((256, 256, 256), seed=1)
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < max_steps and (time.perf_counter() - t0) < budget_s:
+        u = oracle.adi_step(u, s0=0.2, nsteps=1)
+        steps += 1
+    el = time.perf_counter() - t0
+    return {"value": round(3 * 65536 * steps / el, 1), "unit": "solves/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%d ADI step(s) of the 256^3 FP64 workload (s=0.2), %.1f s wall" % (steps, el)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not run)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2201_03950_amd as trid
+
+    trid.load_library()
+    torch.cuda.init()
+    log("main workload: 256^3 FP64 ADI, %d warmup + %d timed steps" % (args.warmup, args.steps))
+    main_run = adi_main(trid, args.steps, args.warmup)
+    log("main done: %.3f ms/step" % (main_run["elapsed"] / args.steps * 1e3))
+    ms = main_run["elapsed"] / args.steps * 1e3
+    value = main_run["solves_per_step"] * args.steps / main_run["elapsed"]
+    kern = main_run["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["mean_ms"])
+    dk = kern[dom]
+    roofline = {"bound": "hbm", "achieved": dk["gbs"], "peak": PEAK_GBS, "unit": "GB/s",
+                "frac": dk["frac"], "traffic": stored_traffic(dom), "kernel": dom}
+    extra = {"adi3d_256_f64": {"ms_per_step_graph": round(main_run["elapsed_graph"] / args.steps * 1e3, 4),
+                               "kernels": kern}}
+    if not args.no_extra:
+        log("extra workloads")
+        extra.update(extra_workloads(trid))
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+    cpu = None if args.no_cpu else cpu_baseline()
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "adi3d_256x256x256_f64_const_s0.2", "mesh": [256, 256, 256], "batch": 1,
+                   "solves_per_step": main_run["solves_per_step"], "kernels_per_step": 3},
+        "roofline": roofline, "cpu_baseline": cpu, "extra": extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -100,6 +100,16 @@ int trid_version(void);
  * Errors: TRID_ERR_ARG for other values. */
 int trid_set_tile(trid_handle_t h, int M, int L);
 
+/* Per-kernel timing with HIP events (for measurement tools).  With on != 0,
+ * every kernel this handle launches outside graph capture is bracketed by two
+ * events recorded on the launch stream; on = 0 stops it.  Either call first
+ * waits for pending events and clears the accumulated totals.
+ * trid_timing_read waits for pending events, then writes NUL-terminated JSON
+ * text {"kernel": [launch count, total milliseconds], ...} into buf (len bytes).
+ * Errors: TRID_ERR_ARG (NULL handle or buffer, buffer too small), TRID_ERR_HIP. */
+int trid_timing_enable(trid_handle_t h, int on);
+int trid_timing_read(trid_handle_t h, char *buf, int64_t len);
+
 /* ------------------------------------------------------- batched solves -- */
 
 /* Solve every line of `axis` of `batch` meshes: A x = d with per-point

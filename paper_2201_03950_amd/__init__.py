@@ -24,4 +24,6 @@ from ._binding import (  # noqa: F401
     plan_load,
     plan_save,
     set_tile,
+    timing_enable,
+    timing_read,
 )

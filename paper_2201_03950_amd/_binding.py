@@ -37,6 +37,8 @@ SIGNATURES = {
     "trid_last_error": ([_H], ctypes.c_char_p),
     "trid_version": ([], _I),
     "trid_set_tile": ([_H, _I, _I], _I),
+    "trid_timing_enable": ([_H, _I], _I),
+    "trid_timing_read": ([_H, ctypes.c_char_p, _I64], _I),
     "trid_gtsv_batched": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_const": ([_H, _I, _D, _D, _D, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_s": ([_H, _I, _P, _P, _I, _I64P, _I, _I64], _I),
@@ -140,6 +142,22 @@ def set_tile(M=0, L=0):
     """Force the tile plan of later solves on this thread (0, 0 = automatic)."""
     h = handle()
     _check(load_library().trid_set_tile(h, int(M), int(L)), h)
+
+
+def timing_enable(on=True):
+    """Bracket this thread's later launches with HIP events (clears totals)."""
+    h = handle()
+    _check(load_library().trid_timing_enable(h, 1 if on else 0), h)
+
+
+def timing_read():
+    """{kernel name: (launch count, total ms)} accumulated since timing_enable."""
+    import json
+
+    h = handle()
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load_library().trid_timing_read(h, buf, len(buf)), h)
+    return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
 
 
 def gtsv(a, b, c, d, axis):

@@ -91,7 +91,8 @@ int run_lines(trid_handle_t h, const trid::LineReq &r) {
     trid::LineReq rr = r;
     h->ext.apply_overrides(&rr);
     if (!trid::plan_lines(rr, &pl, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
-    hipError_t e = trid::launch_lines(rr, pl, h->stream);
+    hipError_t e = h->ext.timer.time(pl.staged ? "gtsv_staged" : "gtsv_strided", h->stream,
+                                     [&] { return trid::launch_lines(rr, pl, h->stream); });
     if (e != hipSuccess) return hip_fail(h, e, "line-solve launch");
     h->err.clear();
     return TRID_OK;
@@ -276,13 +277,16 @@ static int adi_enqueue(trid_handle_t h, bool f64, void *u, const void *s, double
         h->ext.apply_overrides(&rz);
         if (!trid::plan_lines(rz, &pz, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
     }
+    trid::KernelTimer notimer;  // graph capture records no events
+    trid::KernelTimer &tm = (st == h->stream) ? h->ext.timer : notimer;
     for (int it = 0; it < nsteps; ++it) {
-        hipError_t e = trid::launch_rhs_x(ar, px, st);
+        hipError_t e = tm.time("adi_stencil_x", st, [&] { return trid::launch_rhs_x(ar, px, st); });
         if (e != hipSuccess) return hip_fail(h, e, "stencil + x-solve launch");
-        e = trid::launch_lines(ry, py, st);
+        e = tm.time(ndim == 3 ? "adi_y" : "adi_y_update", st,
+                    [&] { return trid::launch_lines(ry, py, st); });
         if (e != hipSuccess) return hip_fail(h, e, "y-solve launch");
         if (ndim == 3) {
-            e = trid::launch_lines(rz, pz, st);
+            e = tm.time("adi_z_update", st, [&] { return trid::launch_lines(rz, pz, st); });
             if (e != hipSuccess) return hip_fail(h, e, "z-solve launch");
         }
     }

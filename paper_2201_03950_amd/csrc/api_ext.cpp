@@ -3,6 +3,8 @@
 // build (which return TRID_ERR_UNSUPPORTED).
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+#include <cstring>
 #include <string>
 
 #include "../../include/trid.h"
@@ -12,6 +14,7 @@
 namespace trid {
 
 void ExtState::release() {
+    timer.release();
     if (ws2) hipFree(ws2);
     ws2 = nullptr;
     ws2_bytes = 0;
@@ -51,6 +54,36 @@ int trid_set_tile(trid_handle_t h, int M, int L) {
     trid::ExtState &x = trid::handle_ext(h);
     x.force_M = M;
     x.force_L = L;
+    return TRID_OK;
+}
+
+int trid_timing_enable(trid_handle_t h, int on) {
+    if (!h) return TRID_ERR_ARG;
+    trid::ExtState &x = trid::handle_ext(h);
+    hipError_t e = x.timer.flush();
+    if (e != hipSuccess) return trid::handle_hip_fail(h, e, "timing flush");
+    x.timer.acc.clear();
+    x.timer.on = on != 0;
+    return TRID_OK;
+}
+
+int trid_timing_read(trid_handle_t h, char *buf, int64_t len) {
+    if (!h || !buf || len < 3) return h ? trid::handle_fail(h, TRID_ERR_ARG, "bad buffer") : TRID_ERR_ARG;
+    trid::ExtState &x = trid::handle_ext(h);
+    hipError_t e = x.timer.flush();
+    if (e != hipSuccess) return trid::handle_hip_fail(h, e, "timing flush");
+    std::string out = "{";
+    bool first = true;
+    for (auto &kv : x.timer.acc) {
+        char tmp[256];
+        snprintf(tmp, sizeof tmp, "%s\"%s\": [%ld, %.6f]", first ? "" : ", ", kv.first.c_str(),
+                 kv.second.first, kv.second.second);
+        out += tmp;
+        first = false;
+    }
+    out += "}";
+    if ((int64_t)out.size() + 1 > len) return trid::handle_fail(h, TRID_ERR_ARG, "buffer too small");
+    memcpy(buf, out.c_str(), out.size() + 1);
     return TRID_OK;
 }
 

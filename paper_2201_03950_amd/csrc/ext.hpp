@@ -8,6 +8,7 @@
 
 #include <map>
 #include <string>
+#include <vector>
 
 #include "dispatch.hpp"
 
@@ -16,6 +17,64 @@ typedef struct trid_handle_s *trid_handle_t;
 namespace trid {
 
 struct VarlenSchedule;  // defined with the uneven-batch solver
+
+// Optional per-kernel timing: when on, every launch made outside graph capture
+// is bracketed by two HIP events recorded on the launch stream; flush()
+// waits for them and accumulates (count, milliseconds) per kernel name.
+struct KernelTimer {
+    bool on = false;
+    struct Pending {
+        std::string name;
+        hipEvent_t e0, e1;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    std::map<std::string, std::pair<long, double>> acc;
+
+    hipEvent_t take() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    // Runs f() (which enqueues one kernel on st) between two events.
+    template <class F>
+    hipError_t time(const char *name, hipStream_t st, F &&f) {
+        if (!on) return f();
+        hipEvent_t e0 = take(), e1 = take();
+        if (!e0 || !e1) return f();
+        hipEventRecord(e0, st);
+        hipError_t e = f();
+        hipEventRecord(e1, st);
+        pending.push_back({name, e0, e1});
+        return e;
+    }
+    hipError_t flush() {
+        for (auto &p : pending) {
+            hipError_t e = hipEventSynchronize(p.e1);
+            if (e != hipSuccess) return e;
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, p.e0, p.e1);
+            auto &a = acc[p.name];
+            a.first += 1;
+            a.second += ms;
+            pool.push_back(p.e0);
+            pool.push_back(p.e1);
+        }
+        pending.clear();
+        return hipSuccess;
+    }
+    void release() {
+        flush();
+        for (auto e : pool) hipEventDestroy(e);
+        pool.clear();
+        acc.clear();
+    }
+};
 
 struct ExtState {
     int force_M = 0;  // forced tile rows (0: automatic)
@@ -27,6 +86,7 @@ struct ExtState {
     // scratch for adjoint / refinement entry points
     void *ws2 = nullptr;
     size_t ws2_bytes = 0;
+    KernelTimer timer;
 
     void apply_overrides(LineReq *r) const {
         if (force_M) r->force_M = force_M;
@@ -36,7 +96,9 @@ struct ExtState {
         if (force_M == 8 || force_M == 16) r->force_M = force_M;
         if (force_L) r->force_L = force_L;
     }
-    bool has_device_state() const { return ws2 != nullptr || !varlen.empty(); }
+    bool has_device_state() const {
+        return ws2 != nullptr || !varlen.empty() || !timer.pool.empty() || !timer.pending.empty();
+    }
     void release();
 };
 
