@@ -90,9 +90,18 @@ int run_lines(trid_handle_t h, const trid::LineReq &r) {
     std::string msg;
     trid::LineReq rr = r;
     h->ext.apply_overrides(&rr);
+    hipError_t e;
+    const int cm = trid::const_lines_M(rr);
+    if (cm) {
+        e = h->ext.timer.time(rr.inner == 1 ? "gtsv_const_staged" : "gtsv_const_strided", h->stream,
+                              [&] { return trid::launch_const_lines(rr, cm, h->stream); });
+        if (e != hipSuccess) return hip_fail(h, e, "line-solve launch");
+        h->err.clear();
+        return TRID_OK;
+    }
     if (!trid::plan_lines(rr, &pl, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
-    hipError_t e = h->ext.timer.time(pl.staged ? "gtsv_staged" : "gtsv_strided", h->stream,
-                                     [&] { return trid::launch_lines(rr, pl, h->stream); });
+    e = h->ext.timer.time(pl.staged ? "gtsv_staged" : "gtsv_strided", h->stream,
+                          [&] { return trid::launch_lines(rr, pl, h->stream); });
     if (e != hipSuccess) return hip_fail(h, e, "line-solve launch");
     h->err.clear();
     return TRID_OK;
@@ -251,7 +260,8 @@ static int adi_enqueue(trid_handle_t h, bool f64, void *u, const void *s, double
     h->ext.apply_adi_overrides(&ar);
     trid::LinePlan px, py, pz;
     std::string msg;
-    if (!trid::plan_rhs_x(ar, &px, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
+    const int cmx = trid::const_rhs_M(ar);
+    if (!cmx && !trid::plan_rhs_x(ar, &px, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
     trid::LineReq ry;
     ry.f64 = f64;
     ry.mode = s ? trid::Mode::S : trid::Mode::Const;
@@ -266,8 +276,10 @@ static int adi_enqueue(trid_handle_t h, bool f64, void *u, const void *s, double
     ry.out = (ndim == 2) ? trid::Out::Add : trid::Out::Store;
     ry.x = (ndim == 2) ? u : dws;
     h->ext.apply_overrides(&ry);
-    if (!trid::plan_lines(ry, &py, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
+    const int cmy = trid::const_lines_M(ry);
+    if (!cmy && !trid::plan_lines(ry, &py, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
     trid::LineReq rz = ry;
+    int cmz = 0;
     if (ndim == 3) {
         rz.inner = nx * ny;
         rz.n = nz;
@@ -275,18 +287,27 @@ static int adi_enqueue(trid_handle_t h, bool f64, void *u, const void *s, double
         rz.out = trid::Out::Add;
         rz.x = u;
         h->ext.apply_overrides(&rz);
-        if (!trid::plan_lines(rz, &pz, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
+        cmz = trid::const_lines_M(rz);
+        if (!cmz && !trid::plan_lines(rz, &pz, &msg)) return fail(h, TRID_ERR_UNSUPPORTED, msg);
     }
+    auto run_x = [&]() {
+        return cmx ? trid::launch_const_rhs_x(ar, cmx, st) : trid::launch_rhs_x(ar, px, st);
+    };
+    auto run_y = [&]() {
+        return cmy ? trid::launch_const_lines(ry, cmy, st) : trid::launch_lines(ry, py, st);
+    };
+    auto run_z = [&]() {
+        return cmz ? trid::launch_const_lines(rz, cmz, st) : trid::launch_lines(rz, pz, st);
+    };
     trid::KernelTimer notimer;  // graph capture records no events
     trid::KernelTimer &tm = (st == h->stream) ? h->ext.timer : notimer;
     for (int it = 0; it < nsteps; ++it) {
-        hipError_t e = tm.time("adi_stencil_x", st, [&] { return trid::launch_rhs_x(ar, px, st); });
+        hipError_t e = tm.time("adi_stencil_x", st, run_x);
         if (e != hipSuccess) return hip_fail(h, e, "stencil + x-solve launch");
-        e = tm.time(ndim == 3 ? "adi_y" : "adi_y_update", st,
-                    [&] { return trid::launch_lines(ry, py, st); });
+        e = tm.time(ndim == 3 ? "adi_y" : "adi_y_update", st, run_y);
         if (e != hipSuccess) return hip_fail(h, e, "y-solve launch");
         if (ndim == 3) {
-            e = tm.time("adi_z_update", st, [&] { return trid::launch_lines(rz, pz, st); });
+            e = tm.time("adi_z_update", st, run_z);
             if (e != hipSuccess) return hip_fail(h, e, "z-solve launch");
         }
     }

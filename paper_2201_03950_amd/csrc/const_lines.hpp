@@ -1,0 +1,346 @@
+// const_lines.hpp -- line solves whose rows are the same (a, b, c) everywhere
+// (the in-kernel coefficient generation of Section IV-A; Alg. 3 with a
+// constant diffusion number).
+//
+// With constant rows every coefficient of the tiled modified Thomas sweep
+// (eq. (7)) and of the reduced system is the same for every line: only the
+// right-hand side differs.  The host therefore runs the coefficient part of the
+// elimination once, in FP64, and passes it as kernel arguments:
+//   - per tile row k: the forward multipliers, the backward factors and the
+//     back-substitution factors of eq. (7);
+//   - the reduced system over the P tiles' first unknowns, already inverted:
+//     f = W1 * fd + W2 * ld, where fd / ld are the tiles' first-row and
+//     last-row right-hand sides.  P <= 8 so the inverse is a tiny dense matrix.
+// Per point the kernel then does about five FMAs, and each block needs a single
+// LDS exchange (all tiles' fd, ld) with one barrier.
+//
+// Requirements (checked by the planner): n = P * M exactly, P <= 8.
+#pragma once
+
+#include "lines.hpp"
+
+namespace trid {
+
+constexpr int kConstMaxM = 32;
+constexpr int kConstMaxP = 8;
+
+template <typename T>
+struct ConstTab {
+    T rr[kConstMaxM];   // forward reciprocal of row k (k >= 1)
+    T am[kConstMaxM];   // rr[k] * a (k >= 2)
+    T cpf[kConstMaxM];  // forward super-diagonal factor c'_k (k = 1..M-2)
+    T apb[kConstMaxM];  // back-substitution factor of u_0 (k = 1..M-2)
+    T cpb[kConstMaxM];  // back-substitution factor of u_{M-1} (k = 1..M-2)
+    // f_p = sum_q w1[p][q] fd_q + w2[p][q] ld_q; row kConstMaxP is an all-zero
+    // row so that "row p + 1" of the last tile reads zeros
+    T w1[(kConstMaxP + 1) * kConstMaxP];
+    T w2[(kConstMaxP + 1) * kConstMaxP];
+    T c;   // super-diagonal (first-row elimination)
+    T la;  // last row: coefficient of the tile's first unknown
+    T lc;  // last row: coefficient of the next tile's first unknown (0 for the last tile)
+    int P;
+};
+
+// Host: fill the tables for rows (a, b, c), tiles of M rows, P = n / M tiles.
+// Returns false if the reduced system is singular.
+template <typename T>
+bool make_const_tab(double a, double b, double c, int M, int P, ConstTab<T> *t);
+
+// Forward / backward sweep of one tile (eq. (7)) with tabulated coefficients.
+// x holds the tile's right-hand sides on entry and d'_k on return (x[0] keeps
+// the raw first row's rhs); returns fd and ld, the reduced rows' rhs.
+template <typename T, int M, class Tab>
+__device__ __forceinline__ void const_tile_sweep(const Tab &tb, T (&x)[M], T &fd, T &ld) {
+    x[1] = tb.rr[1] * x[1];
+#pragma unroll
+    for (int k = 2; k < M; ++k) x[k] = tb.rr[k] * x[k] - tb.am[k] * x[k - 1];
+    ld = x[M - 1];
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) x[k] -= tb.cpf[k] * x[k + 1];
+    fd = x[0] - tb.c * x[1];
+}
+
+// Back substitution once f (tile's first unknown) and fn (next tile's) are known.
+template <typename T, int M>
+__device__ __forceinline__ void const_tile_backsub(const ConstTab<T> &tb, T f, T fn, bool last,
+                                                   T (&x)[M]) {
+    const T lv = x[M - 1] - tb.la * f - (last ? T(0) : tb.lc) * fn;
+    x[0] = f;
+    x[M - 1] = lv;
+#pragma unroll
+    for (int k = 1; k < M - 1; ++k) x[k] = x[k] - tb.apb[k] * f - tb.cpb[k] * lv;
+}
+
+// ---------------------------------------------------------------- strided --
+// y / z lines: 64 lanes = 64 adjacent lines, wavefront w = tile w (uniform, so
+// every table read is a scalar load).  Block = 64 lines x P tiles.
+
+template <typename T, int M, class Epi>
+__global__ __launch_bounds__(64 * kConstMaxP) void k_strided_const(StridedGeom gm, ConstTab<T> tb,
+                                                                  const T *__restrict__ d, Epi epi) {
+    __shared__ T sfd[kConstMaxP * 64], sld[kConstMaxP * 64];
+    const int l = threadIdx.x & 63;
+    const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int P = tb.P;
+    const i64 blk = xcd_block_id();
+    const i64 ib = blk % gm.nib, ob = blk / gm.nib;
+    const i64 ii = ib * 64 + l;
+    const bool act = ii < gm.inner;
+    const i64 st = gm.inner;
+    const i64 base = ob * (i64)gm.n * st + (act ? ii : 0);
+    const int g0 = p * M;
+    const T *dp = d + base + (i64)g0 * st;
+    T x[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[k] = act ? dp[(i64)k * st] : T(0);
+    typename Epi::template Pre<M> pre;
+    epi.template prefetch<M>(pre, base, st, g0, gm.n, act);
+    T fd, ld;
+    const_tile_sweep<T, M>(tb, x, fd, ld);
+    sfd[p * 64 + l] = fd;
+    sld[p * 64 + l] = ld;
+    __syncthreads();
+    T f = T(0), fn = T(0);
+    const T *w1 = tb.w1 + p * kConstMaxP, *w2 = tb.w2 + p * kConstMaxP;
+#pragma unroll
+    for (int q = 0; q < kConstMaxP; ++q) {
+        if (q < P) {
+            const T vf = sfd[q * 64 + l], vl = sld[q * 64 + l];
+            f += w1[q] * vf + w2[q] * vl;
+            fn += w1[q + kConstMaxP] * vf + w2[q + kConstMaxP] * vl;  // row p+1 (zero past the end)
+        }
+    }
+    const_tile_backsub<T, M>(tb, f, fn, p == P - 1, x);
+    epi.template store<M>(pre, base, st, g0, gm.n, act, x);
+}
+
+// ----------------------------------------------------------------- staged --
+// x lines: L lines x P tiles per block, thread t -> tile p = t % P of line
+// l = t / P.  A source stages the block's right-hand sides into LDS (tiles
+// padded to M + 1 elements, against bank conflicts); results leave through the
+// same region with 16-byte stores.
+
+struct ConstStagedGeom {
+    i64 nlines;
+    int n, L, ls;
+};
+
+// Vector width (elements per 16-byte access).
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+    using type = double2;
+    static constexpr int n = 2;
+};
+template <>
+struct Vec<float> {
+    using type = float4;
+    static constexpr int n = 4;
+};
+
+template <typename T>
+__device__ __forceinline__ T vget(const typename Vec<T>::type &v, int j);
+template <>
+__device__ __forceinline__ double vget<double>(const double2 &v, int j) {
+    return j == 0 ? v.x : v.y;
+}
+template <>
+__device__ __forceinline__ float vget<float>(const float4 &v, int j) {
+    return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
+}
+
+// Plain right-hand side: copy d's block into LDS with 16-byte loads.
+template <typename T>
+struct CStgCopy {
+    const T *d;
+    template <int M>
+    __device__ __forceinline__ void stage(T *__restrict__ sh, const ConstStagedGeom &g, i64 o0, int nl,
+                                          int *) const {
+        using VT = typename Vec<T>::type;
+        constexpr int V = Vec<T>::n;
+        const int n = g.n, nc = nl * n / V, nt = blockDim.x;
+        const VT *src = reinterpret_cast<const VT *>(d + o0 * n);
+#pragma unroll
+        for (int k = 0; k < M / V; ++k) {
+            const int ch = threadIdx.x + k * nt;
+            if (ch < nc) {
+                const VT v = src[ch];
+                const int e = ch * V, ll = e / n, i = e - ll * n;
+                T *dst = sh + ll * g.ls + (i / M) * (M + 1) + (i % M);
+#pragma unroll
+                for (int j = 0; j < V; ++j) dst[j] = vget<T>(v, j);
+            }
+        }
+    }
+};
+
+// Right-hand side of the ADI step, d = 2 s0 (sum of neighbours - 2 NDIM u),
+// zero outside the mesh, computed while staging (16-byte loads of u; the x
+// neighbours across a vector boundary come from two scalar loads).
+template <typename T, int NDIM>
+struct CStgRhs {
+    const T *u;
+    T s2;  // 2 s0
+    int ny, nz;
+    template <int M>
+    __device__ __forceinline__ void stage(T *__restrict__ sh, const ConstStagedGeom &g, i64 o0, int nl,
+                                          int *flags) const {
+        using VT = typename Vec<T>::type;
+        constexpr int V = Vec<T>::n;
+        const int n = g.n, nc = nl * n / V, nt = blockDim.x;
+        for (int ll = threadIdx.x; ll < nl; ll += nt) {
+            const i64 o = o0 + ll;
+            const int j = (int)(o % ny);
+            const int k = (int)((o / ny) % nz);
+            flags[ll] = (j > 0 ? 1 : 0) | (j < ny - 1 ? 2 : 0) | (k > 0 ? 4 : 0) | (k < nz - 1 ? 8 : 0);
+        }
+        __syncthreads();
+        const T *ub = u + o0 * n;
+        const i64 sy = n, sz = (i64)ny * n;
+#pragma unroll
+        for (int k = 0; k < M / V; ++k) {
+            const int ch = threadIdx.x + k * nt;
+            if (ch < nc) {
+                const int e = ch * V, ll = e / n, i = e - ll * n;
+                const int f = flags[ll];
+                const T *q = ub + e;
+                const VT c = *reinterpret_cast<const VT *>(q);
+                VT acc = (f & 1) ? *reinterpret_cast<const VT *>(q - sy) : VT{};
+                if (f & 2) acc += *reinterpret_cast<const VT *>(q + sy);
+                if (NDIM == 3) {
+                    if (f & 4) acc += *reinterpret_cast<const VT *>(q - sz);
+                    if (f & 8) acc += *reinterpret_cast<const VT *>(q + sz);
+                }
+                const T left = i > 0 ? q[-1] : T(0);
+                const T right = i + V < n ? q[V] : T(0);
+                T *dst = sh + ll * g.ls + (i / M) * (M + 1) + (i % M);
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    const T xl = j == 0 ? left : vget<T>(c, j - 1);
+                    const T xr = j == V - 1 ? right : vget<T>(c, j + 1);
+                    dst[j] = s2 * (vget<T>(acc, j) + xl + xr - T(2 * NDIM) * vget<T>(c, j));
+                }
+            }
+        }
+    }
+};
+
+// ------------------------------------------------------ staged, DPP PCR --
+// x lines with P = n / M a power of two <= 16: the P tiles of a line are P
+// adjacent lanes inside one 16-lane DPP row, so the reduced system over the
+// tiles' first unknowns is solved by PCR (Alg. 2) with row shifts of the
+// wavefront (no LDS, no barrier).  Its coefficients do not depend on the line
+// and come tabulated per (level, tile); only right-hand sides move.
+
+constexpr int kDppMaxP = 16;
+constexpr int kDppLevels = 4;
+
+template <typename T>
+struct PcrTab {
+    T rr[kConstMaxM], am[kConstMaxM], cpf[kConstMaxM], apb[kConstMaxM], cpb[kConstMaxM];
+    T c, la, lc;
+    // G row of tile p: gd = rg fd - gA ld_{p-1} - gC ld_p (normalised, b = 1)
+    T rg[kDppMaxP], gA[kDppMaxP], gC[kDppMaxP];
+    // PCR level j (stride 2^j): d = pr d - pa d_{p-s} - pc d_{p+s}
+    T pr[kDppLevels][kDppMaxP], pa[kDppLevels][kDppMaxP], pc[kDppLevels][kDppMaxP];
+};
+
+template <typename T>
+bool make_pcr_tab(double a, double b, double c, int M, int P, PcrTab<T> *t);
+
+// Lane i receives lane i - S (SHR) or i + S (SHL) of its 16-lane row; lanes
+// whose source is outside the row receive 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <int S, typename T>
+__device__ __forceinline__ T row_from_lower(T v) {  // value of tile p - S
+    return dpp_move<0x110 + S>(v);
+}
+template <int S, typename T>
+__device__ __forceinline__ T row_from_upper(T v) {  // value of tile p + S
+    return dpp_move<0x100 + S>(v);
+}
+
+template <typename T, int P, int S>
+struct PcrLevels {
+    __device__ __forceinline__ static void run(const PcrTab<T> &tb, int p, T &d) {
+        if constexpr (S < P) {
+            constexpr int j = (S == 1) ? 0 : (S == 2) ? 1 : (S == 4) ? 2 : 3;
+            T dm = row_from_lower<S>(d);
+            T dn = row_from_upper<S>(d);
+            if (P < 16) {  // rows hold several lines: mask neighbours of other lines
+                dm = (p >= S) ? dm : T(0);
+                dn = (p + S < P) ? dn : T(0);
+            }
+            d = tb.pr[j][p] * d - tb.pa[j][p] * dm - tb.pc[j][p] * dn;
+            PcrLevels<T, P, 2 * S>::run(tb, p, d);
+        }
+    }
+};
+
+template <typename T, int M, int P, class Src>
+__global__ __launch_bounds__(256) void k_staged_dpp(ConstStagedGeom g, PcrTab<T> tb, Src src,
+                                                    T *__restrict__ out) {
+    static_assert(P >= 1 && P <= 16 && (P & (P - 1)) == 0, "P must be a power of two <= 16");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sh = reinterpret_cast<T *>(smem_raw);
+    const int L = g.L, n = g.n;
+    int *flags = reinterpret_cast<int *>(sh + L * g.ls);
+    const int t = threadIdx.x, p = t % P, l = t / P;
+    const i64 o0 = xcd_block_id() * L;
+    const int nl = (int)((g.nlines - o0) < (i64)L ? (g.nlines - o0) : (i64)L);
+    src.template stage<M>(sh, ConstStagedGeom{g.nlines, g.n, g.L, g.ls}, o0, nl, flags);
+    __syncthreads();
+    const bool act = l < nl;
+    const int pos = l * g.ls + p * (M + 1);
+    T x[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) x[k] = act ? sh[pos + k] : T(0);
+    T fd, ld;
+    const_tile_sweep<T, M>(tb, x, fd, ld);
+    T ldp = row_from_lower<1>(ld);
+    if (P < 16) ldp = (p >= 1) ? ldp : T(0);
+    T d = tb.rg[p] * fd - tb.gA[p] * ldp - tb.gC[p] * ld;
+    PcrLevels<T, P, 1>::run(tb, p, d);
+    const T f = d;
+    T fn = row_from_upper<1>(f);
+    if (P < 16) fn = (p + 1 < P) ? fn : T(0);
+    const T lv = x[M - 1] - tb.la * f - ((p == P - 1) ? T(0) : tb.lc) * fn;
+    x[0] = f;
+    x[M - 1] = lv;
+#pragma unroll
+    for (int k = 1; k < M - 1; ++k) x[k] = x[k] - tb.apb[k] * f - tb.cpb[k] * lv;
+#pragma unroll
+    for (int k = 0; k < M; ++k) sh[pos + k] = x[k];
+    __syncthreads();
+    using VT = typename Vec<T>::type;
+    constexpr int V = Vec<T>::n;
+    const int nc = nl * n / V;
+    VT *dst = reinterpret_cast<VT *>(out + o0 * n);
+#pragma unroll
+    for (int k = 0; k < M / V; ++k) {
+        const int ch = t + k * (int)blockDim.x;
+        if (ch < nc) {
+            const int e = ch * V, ll = e / n, i = e - ll * n;
+            const T *sp = sh + ll * g.ls + (i / M) * (M + 1) + (i % M);
+            VT v;
+            T *vp = reinterpret_cast<T *>(&v);
+#pragma unroll
+            for (int j = 0; j < V; ++j) vp[j] = sp[j];
+            dst[ch] = v;
+        }
+    }
+}
+
+}  // namespace trid

@@ -75,4 +75,12 @@ struct AdiReq {
 bool plan_rhs_x(const AdiReq &r, LinePlan *pl, std::string *err);
 hipError_t launch_rhs_x(const AdiReq &r, const LinePlan &pl, hipStream_t s);
 
+// Constant-row fast path (host-tabulated elimination).  *_M return the tile
+// size to use, or 0 when the request does not qualify (then the general
+// kernels run).
+int const_lines_M(const LineReq &r);
+hipError_t launch_const_lines(const LineReq &r, int M, hipStream_t s);
+int const_rhs_M(const AdiReq &r);
+hipError_t launch_const_rhs_x(const AdiReq &r, int M, hipStream_t s);
+
 }  // namespace trid

@@ -218,3 +218,30 @@ def test_s_adjoint_matches_oracle(trid, orc, dt, axis):
     assert _line_err(tg.cpu().numpy().astype(np.float64), lam, axis) <= TOL[dt]
     err = float(np.max(np.abs(tgs.cpu().numpy() - gs_ref)) / np.max(np.abs(gs_ref)))
     assert err <= TOL[dt] * 10
+
+
+# ------------------------------------------------ constant-row fast path ----
+
+CONST_GEOMS = [((64, 96, 32), 2, 0), ((64, 96, 32), 2, 1), ((64, 96, 32), 2, 2),
+               ((256, 3), 5, 0), ((100, 256), 1, 1), ((70, 3, 128), 1, 2), ((32,), 7, 0)]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("geom", CONST_GEOMS, ids=[str(g) for g in CONST_GEOMS])
+def test_const_fast_path_matches_oracle(trid, orc, dt, geom):
+    dims, batch, axis = geom
+    d = np.random.default_rng(31).standard_normal(gen.mesh_shape(dims, batch)).astype(dt)
+    ref = orc.gtsv_const(-0.2, 1.4, -0.2, d, axis)
+    td = _t(d)
+    trid.gtsv_const(-0.2, 1.4, -0.2, td, axis)
+    assert _line_err(td.cpu().numpy().astype(np.float64), ref, axis) <= TOL[dt]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("dims,batch", [((64, 96, 32), 2), ((256, 40, 24), 1), ((128, 70), 3)])
+def test_adi_const_fast_path_matches_oracle(trid, orc, dt, dims, batch):
+    u = gen.adi3d_field(dims, batch, seed=4).astype(dt)
+    ref = orc.adi_step(u, s0=0.2, nsteps=3)
+    tu = _t(u)
+    trid.adi_step(tu, s0=0.2, nsteps=3)
+    assert _field_err(tu.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
