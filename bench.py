@@ -200,6 +200,71 @@ def extra_workloads(trid):
     return out
 
 
+def pmc_copy_calibration():
+    """A plain device copy of known size (2 x 134,217,728 bytes moved), for counter scaling."""
+    import torch
+
+    src = torch.ones(COPY_ELEMS, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    sync()
+    del src, dst
+
+
+COPY_ELEMS = 1 << 24  # 128 MiB of float64
+
+
+def ingest_pmc(fetch_dir, write_dir):
+    """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per launch.
+
+    Each counter is scaled by the ratio of the known bytes of the calibration copy
+    (COPY_ELEMS float64 read and written once) to what the counter reports for it.
+    Writes TRAFFIC_FILE (tagged with the current source hash) and prints a table.
+    """
+    import csv
+    import glob
+
+    def read(d, counter):
+        per = {}
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as f:
+                for r in csv.DictReader(f):
+                    if r["Counter_Name"] != counter:
+                        continue
+                    per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return per
+
+    fetch, write = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+    known = COPY_ELEMS * 8.0
+
+    def copy_value(per):
+        cands = [v for k, v in per.items() if "trid::" not in k and ("copy" in k.lower() or "elementwise" in k.lower())]
+        vals = [x for v in cands for x in v if x > 0.5 * known]
+        return sum(vals) / len(vals)
+
+    kf, kw = known / copy_value(fetch), known / copy_value(write)
+    names = {"StgRhs": "adi_stencil_x", "EpiAdd": "adi_z_update", "EpiStore": "adi_y"}
+    rec = {"source_hash": kernel_source_hash(), "copy_scale_fetch": kf, "copy_scale_write": kw,
+           "copy_bytes": known, "kernels": {}}
+    rows = []
+    for k in sorted(fetch):
+        if "trid::" not in k:
+            continue
+        tag = next((v for key, v in names.items() if key in k), k.split("(")[0])
+        f = sum(fetch[k]) / len(fetch[k]) * kf
+        w = sum(write.get(k, [0.0])) / max(1, len(write.get(k, []))) * kw
+        rec["kernels"][tag] = {"fetch_bytes_per_launch": f, "write_bytes_per_launch": w,
+                               "hbm_bytes_per_launch": f + w, "name": k.split("(")[0]}
+        rows.append((tag, f, w))
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print("| kernel | FETCH (MB/launch) | WRITE (MB/launch) | total (MB) |")
+    print("|---|---|---|---|")
+    for tag, f, w in rows:
+        print("| %s | %.1f | %.1f | %.1f |" % (tag, f / 1e6, w / 1e6, (f + w) / 1e6))
+    print("copy calibration factors: fetch %.4f, write %.4f" % (kf, kw))
+
+
 def cpu_baseline(budget_s=12.0, max_steps=60):
     """The oracle (never tuned) on the same 256^3 FP64 workload, a bounded number of steps."""
     from oracle import oracle
@@ -225,7 +290,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extra", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--pmc-copy", action="store_true",
+                    help="run a plain copy of known size first (counter calibration)")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the HBM-traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc)
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only; --gpus %d is not supported "
               "(the multi-GPU sharding is described in DESIGN.md, not run)" % args.gpus, file=sys.stderr)
@@ -236,6 +308,8 @@ def main():
 
     trid.load_library()
     torch.cuda.init()
+    if args.pmc_copy:
+        pmc_copy_calibration()
     log("main workload: 256^3 FP64 ADI, %d warmup + %d timed steps" % (args.warmup, args.steps))
     main_run = adi_main(trid, args.steps, args.warmup)
     log("main done: %.3f ms/step" % (main_run["elapsed"] / args.steps * 1e3))

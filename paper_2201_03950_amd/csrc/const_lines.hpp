@@ -89,12 +89,13 @@ __global__ __launch_bounds__(64 * kConstMaxP) void k_strided_const(StridedGeom g
     const i64 st = gm.inner;
     const i64 base = ob * (i64)gm.n * st + (act ? ii : 0);
     const int g0 = p * M;
+    // rows of one tile lie within one slab of n * inner < 2^31 elements (planner):
+    // 32-bit offsets from the tile's first row
+    const unsigned sst = (unsigned)st;
     const T *dp = d + base + (i64)g0 * st;
     T x[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) x[k] = act ? dp[(i64)k * st] : T(0);
-    typename Epi::template Pre<M> pre;
-    epi.template prefetch<M>(pre, base, st, g0, gm.n, act);
+    for (int k = 0; k < M; ++k) x[k] = act ? dp[k * sst] : T(0);
     T fd, ld;
     const_tile_sweep<T, M>(tb, x, fd, ld);
     sfd[p * 64 + l] = fd;
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(64 * kConstMaxP) void k_strided_const(StridedGeom g
         }
     }
     const_tile_backsub<T, M>(tb, f, fn, p == P - 1, x);
-    epi.template store<M>(pre, base, st, g0, gm.n, act, x);
+    epi.template store_rows<M>(base + (i64)g0 * st, sst, act, x);
 }
 
 // ----------------------------------------------------------------- staged --
@@ -150,16 +151,31 @@ __device__ __forceinline__ float vget<float>(const float4 &v, int j) {
     return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
 }
 
+// DPP lane moves (row shifts within 16-lane rows, wave shifts by one lane);
+// lanes whose source is outside the row / wavefront receive 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
 // Plain right-hand side: copy d's block into LDS with 16-byte loads.
 template <typename T>
 struct CStgCopy {
     const T *d;
-    template <int M>
+    template <int M, int N>
     __device__ __forceinline__ void stage(T *__restrict__ sh, const ConstStagedGeom &g, i64 o0, int nl,
                                           int *) const {
         using VT = typename Vec<T>::type;
         constexpr int V = Vec<T>::n;
-        const int n = g.n, nc = nl * n / V, nt = blockDim.x;
+        constexpr int n = N;
+        const int nc = nl * n / V, nt = blockDim.x;
         const VT *src = reinterpret_cast<const VT *>(d + o0 * n);
 #pragma unroll
         for (int k = 0; k < M / V; ++k) {
@@ -176,51 +192,90 @@ struct CStgCopy {
 };
 
 // Right-hand side of the ADI step, d = 2 s0 (sum of neighbours - 2 NDIM u),
-// zero outside the mesh, computed while staging (16-byte loads of u; the x
-// neighbours across a vector boundary come from two scalar loads).
+// zero outside the mesh, computed while staging.  Thread t owns one 16-byte
+// column c = t % C (C = N / V vectors per line) of M / V consecutive lines, so
+//   - the y neighbours of its lines are its own previous / next line (a
+//     sliding window in registers; only the two halo lines are extra loads),
+//   - the x neighbours across a vector boundary come from the adjacent lanes
+//     (DPP wave shifts; lanes at a wavefront edge load theirs),
+//   - the z neighbours are two coalesced vector loads per vector.
+// The planner guarantees N = P * M, blockDim = 256 = L * P and M / V lines
+// per thread (so 256 / C thread groups cover the block's L lines).
+template <typename T>
+__device__ __forceinline__ T wave_from_lower_lane(T v) {  // lane i <- lane i - 1 (lane 0: 0)
+    return dpp_move<0x138>(v);
+}
+template <typename T>
+__device__ __forceinline__ T wave_from_upper_lane(T v) {  // lane i <- lane i + 1 (lane 63: 0)
+    return dpp_move<0x130>(v);
+}
+
 template <typename T, int NDIM>
 struct CStgRhs {
     const T *u;
     T s2;  // 2 s0
     int ny, nz;
-    template <int M>
+    template <int M, int N>
     __device__ __forceinline__ void stage(T *__restrict__ sh, const ConstStagedGeom &g, i64 o0, int nl,
-                                          int *flags) const {
+                                          int *) const {
         using VT = typename Vec<T>::type;
         constexpr int V = Vec<T>::n;
-        const int n = g.n, nc = nl * n / V, nt = blockDim.x;
-        for (int ll = threadIdx.x; ll < nl; ll += nt) {
-            const i64 o = o0 + ll;
-            const int j = (int)(o % ny);
-            const int k = (int)((o / ny) % nz);
-            flags[ll] = (j > 0 ? 1 : 0) | (j < ny - 1 ? 2 : 0) | (k > 0 ? 4 : 0) | (k < nz - 1 ? 8 : 0);
+        constexpr int C = N / V;   // vectors per line
+        constexpr int LG = M / V;  // lines per thread
+        const int t = threadIdx.x, c = t % C, grp = t / C;
+        const int lane = t & 63;
+        const int lfirst = grp * LG;  // first block line of this thread
+        // (j, k) of the block's first line: one uniform division per block
+        const unsigned o0u = (unsigned)o0;
+        const unsigned plane0 = __builtin_amdgcn_readfirstlane(o0u / (unsigned)ny);
+        int j = (int)(o0u - plane0 * (unsigned)ny) + lfirst, k = (int)(plane0 % (unsigned)nz);
+        while (j >= ny) {
+            j -= ny;
+            k = (k + 1 == nz) ? 0 : k + 1;
         }
-        __syncthreads();
-        const T *ub = u + o0 * n;
-        const i64 sy = n, sz = (i64)ny * n;
+        const int sz = ny * N;
+        const T *q0 = u + (o0 + lfirst) * N + c * V;  // this thread's column, first line
+        // sliding window over lines lfirst-1 .. lfirst+LG (y neighbours)
+        VT prev = VT{}, cur = VT{}, next = VT{};
+        if (lfirst < nl) {
+            cur = *reinterpret_cast<const VT *>(q0);
+            if (j > 0) prev = *reinterpret_cast<const VT *>(q0 - N);
+        }
 #pragma unroll
-        for (int k = 0; k < M / V; ++k) {
-            const int ch = threadIdx.x + k * nt;
-            if (ch < nc) {
-                const int e = ch * V, ll = e / n, i = e - ll * n;
-                const int f = flags[ll];
-                const T *q = ub + e;
-                const VT c = *reinterpret_cast<const VT *>(q);
-                VT acc = (f & 1) ? *reinterpret_cast<const VT *>(q - sy) : VT{};
-                if (f & 2) acc += *reinterpret_cast<const VT *>(q + sy);
-                if (NDIM == 3) {
-                    if (f & 4) acc += *reinterpret_cast<const VT *>(q - sz);
-                    if (f & 8) acc += *reinterpret_cast<const VT *>(q + sz);
-                }
-                const T left = i > 0 ? q[-1] : T(0);
-                const T right = i + V < n ? q[V] : T(0);
-                T *dst = sh + ll * g.ls + (i / M) * (M + 1) + (i % M);
+        for (int r = 0; r < LG; ++r) {
+            const int ll = lfirst + r;
+            const bool live = ll < nl;
+            const T *q = q0 + r * N;
+            const bool has_next = j < ny - 1;
+            next = (live && has_next) ? *reinterpret_cast<const VT *>(q + N) : VT{};
+            VT acc = (has_next ? next : VT{}) + (j > 0 ? prev : VT{});
+            if (NDIM == 3) {
+                if (live && k > 0) acc += *reinterpret_cast<const VT *>(q - sz);
+                if (live && k < nz - 1) acc += *reinterpret_cast<const VT *>(q + sz);
+            }
+            // x neighbours of the vector's first and last element
+            T left = wave_from_lower_lane<T>(vget<T>(cur, V - 1));
+            T right = wave_from_upper_lane<T>(vget<T>(cur, 0));
+            if (lane == 0) left = (live && c > 0) ? q[-1] : T(0);
+            if (lane == 63) right = (live && c < C - 1) ? q[V] : T(0);
+            if (c == 0) left = T(0);
+            if (c == C - 1) right = T(0);
+            if (live) {
+                T *dst = sh + ll * g.ls + ((c * V) / M) * (M + 1) + ((c * V) % M);
 #pragma unroll
-                for (int j = 0; j < V; ++j) {
-                    const T xl = j == 0 ? left : vget<T>(c, j - 1);
-                    const T xr = j == V - 1 ? right : vget<T>(c, j + 1);
-                    dst[j] = s2 * (vget<T>(acc, j) + xl + xr - T(2 * NDIM) * vget<T>(c, j));
+                for (int e = 0; e < V; ++e) {
+                    const T xl = e == 0 ? left : vget<T>(cur, e - 1);
+                    const T xr = e == V - 1 ? right : vget<T>(cur, e + 1);
+                    dst[e] = s2 * (vget<T>(acc, e) + xl + xr - T(2 * NDIM) * vget<T>(cur, e));
                 }
+            }
+            prev = cur;
+            cur = next;
+            if (++j == ny) {  // next line starts a new plane: its y-1 neighbour is outside
+                j = 0;
+                k = (k + 1 == nz) ? 0 : k + 1;
+                prev = VT{};
+                if (r + 1 < LG && ll + 1 < nl) cur = *reinterpret_cast<const VT *>(q + N);
             }
         }
     }
@@ -249,20 +304,6 @@ struct PcrTab {
 template <typename T>
 bool make_pcr_tab(double a, double b, double c, int M, int P, PcrTab<T> *t);
 
-// Lane i receives lane i - S (SHR) or i + S (SHL) of its 16-lane row; lanes
-// whose source is outside the row receive 0.
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
-                                                                 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
 template <int S, typename T>
 __device__ __forceinline__ T row_from_lower(T v) {  // value of tile p - S
     return dpp_move<0x110 + S>(v);
@@ -295,12 +336,13 @@ __global__ __launch_bounds__(256) void k_staged_dpp(ConstStagedGeom g, PcrTab<T>
     static_assert(P >= 1 && P <= 16 && (P & (P - 1)) == 0, "P must be a power of two <= 16");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sh = reinterpret_cast<T *>(smem_raw);
-    const int L = g.L, n = g.n;
+    constexpr int n = P * M;  // the planner only sends lines of exactly P tiles
+    const int L = g.L;
     int *flags = reinterpret_cast<int *>(sh + L * g.ls);
     const int t = threadIdx.x, p = t % P, l = t / P;
     const i64 o0 = xcd_block_id() * L;
     const int nl = (int)((g.nlines - o0) < (i64)L ? (g.nlines - o0) : (i64)L);
-    src.template stage<M>(sh, ConstStagedGeom{g.nlines, g.n, g.L, g.ls}, o0, nl, flags);
+    src.template stage<M, n>(sh, g, o0, nl, flags);
     __syncthreads();
     const bool act = l < nl;
     const int pos = l * g.ls + p * (M + 1);

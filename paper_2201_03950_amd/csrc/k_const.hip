@@ -178,7 +178,10 @@ hipError_t go_dpp(i64 nlines, int n, const PcrTab<T> &tb, Src src, T *out, hipSt
     ConstStagedGeom g;
     g.nlines = nlines;
     g.n = n;
-    g.L = 256 / P;
+    // 128-thread blocks for FP64 (measured faster than 256 on the 256^3 step),
+    // 256 for FP32; the staging needs threads >= n / vector width
+    const int nt = (sizeof(T) == 8 && n / 2 <= 128) ? 128 : 256;
+    g.L = nt / P;
     g.ls = P * (M + 1);
     const size_t shm = (size_t)g.L * g.ls * sizeof(T) + (size_t)g.L * sizeof(int);
     hipLaunchKernelGGL((k_staged_dpp<T, M, P, Src>), dim3((unsigned)cdiv(nlines, g.L)), dim3(g.L * P),
@@ -270,6 +273,7 @@ hipError_t rhs_typed(const AdiReq &r, int M, hipStream_t s) {
 int const_lines_M(const LineReq &r) {
     if (r.mode != Mode::Const || (r.out != Out::Store && r.out != Out::Add)) return 0;
     if (r.inner == 1 && r.out != Out::Store) return 0;
+    if (r.n * r.inner >= ((i64)1 << 31)) return 0;  // 32-bit row offsets within a slab
     const int M = r.inner == 1 ? const_staged_M(r.n, r.f64 ? 8 : 4, r.force_M) : const_M(r.n, r.force_M);
     if (!M) return 0;
     if (r.inner == 1) {
@@ -285,6 +289,7 @@ hipError_t launch_const_lines(const LineReq &r, int M, hipStream_t s) {
 
 int const_rhs_M(const AdiReq &r) {
     if (r.s) return 0;
+    if (r.nx * r.ny * r.nz * r.batch >= ((i64)1 << 31)) return 0;  // 32-bit line indices
     const int M = const_staged_M(r.nx, r.f64 ? 8 : 4, r.force_M);
     if (!M) return 0;
     const int V = r.f64 ? 2 : 4;

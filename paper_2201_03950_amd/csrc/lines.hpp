@@ -145,6 +145,14 @@ struct SrcST {  // transposed rows of the s operator: (-s_{g-1}, 1 + 2 s_g, -s_{
 template <typename T>
 struct EpiStore {  // x = solution
     T *x;
+    // all M rows valid, 32-bit row offsets from `off` (used by the constant-row kernels)
+    template <int M>
+    __device__ __forceinline__ void store_rows(i64 off, unsigned st, bool act, const T (&u)[M]) const {
+        if (!act) return;
+        T *px = x + off;
+#pragma unroll
+        for (int k = 0; k < M; ++k) px[k * st] = u[k];
+    }
     template <int M>
     struct Pre {};
     template <int M>
@@ -163,6 +171,24 @@ struct EpiStore {  // x = solution
 template <typename T>
 struct EpiAdd {  // u += solution (the update of Alg. 3, fused into the last solve)
     T *u;
+    // all M rows valid; u is read only now (not prefetched) and in groups of 8
+    // rows (the empty asm keeps the compiler from hoisting every load), which
+    // keeps VGPRs low enough for two blocks per CU
+    template <int M>
+    __device__ __forceinline__ void store_rows(i64 off, unsigned st, bool act, const T (&x)[M]) const {
+        if (!act) return;
+        T *pu = u + off;
+        constexpr int G = M < 8 ? M : 8;
+#pragma unroll
+        for (int c = 0; c < M; c += G) {
+            T v[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) v[k] = pu[(c + k) * st];
+#pragma unroll
+            for (int k = 0; k < G; ++k) pu[(c + k) * st] = v[k] + x[c + k];
+            asm volatile("" ::: "memory");
+        }
+    }
     template <int M>
     struct Pre {
         T v[M];

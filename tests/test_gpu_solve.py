@@ -238,7 +238,8 @@ def test_const_fast_path_matches_oracle(trid, orc, dt, geom):
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
-@pytest.mark.parametrize("dims,batch", [((64, 96, 32), 2), ((256, 40, 24), 1), ((128, 70), 3)])
+@pytest.mark.parametrize("dims,batch", [((64, 96, 32), 2), ((256, 40, 24), 1), ((128, 70), 3),
+                                         ((32, 3, 5), 2), ((64, 5, 7), 3), ((64, 1, 9), 1), ((32, 2), 5)])
 def test_adi_const_fast_path_matches_oracle(trid, orc, dt, dims, batch):
     u = gen.adi3d_field(dims, batch, seed=4).astype(dt)
     ref = orc.adi_step(u, s0=0.2, nsteps=3)
