@@ -37,6 +37,17 @@ PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_adi3d_256_f64.json")
 
 
+# Algorithmic words moved per row (each array read once / written once):
+# coefficient arrays a, b, c, d in and x out = 5; per-point s: s, d, x = 3;
+# constant rows: d in, x out = 2.
+ALG_WORDS = {"arrays": 5, "s": 3, "const": 2}
+
+
+def alg_bytes(mode, word_bytes, rows):
+    """Bytes a batched solve must move: the bandwidth convention of the paper's Table 1."""
+    return ALG_WORDS[mode] * word_bytes * rows
+
+
 def kernel_source_hash():
     """Hash of the HIP sources; a stored counter measurement is valid only for this hash."""
     h = hashlib.sha256()
@@ -142,7 +153,7 @@ def extra_workloads(trid):
         t = time_calls(lambda: trid.gtsv(ta, tb, tc, td, axis), 500, warm=20)
         out["sys1024x256_f64_%s" % lay] = {"us_per_call": round(t * 1e6, 2),
                                           "solves_per_s": round(1024 / t, 1),
-                                          "gbs": round(40 * 1024 * 256 / t / 1e9, 1)}
+                                          "gbs": round(alg_bytes("arrays", 8, 1024 * 256) / t / 1e9, 1)}
     # -- bandwidth variant: 262,144 systems of 256 rows (2.7 GB moved per call)
     nsys = 262144
     rng_a, rng_b, rng_c, rng_d = gen.dd_lines(nsys, 256, seed=10)
@@ -158,7 +169,7 @@ def extra_workloads(trid):
         trid.timing_enable(False)
         name, (cnt, ms) = next(iter(kt.items()))
         kern = ms / cnt * 1e-3
-        byts = 40 * nsys * 256
+        byts = alg_bytes("arrays", 8, nsys * 256)
         log("bandwidth variant %s layout done" % lay)
         out["sys262144x256_f64_%s" % lay] = {
             "ms_per_call": round(t * 1e3, 4), "kernel": name, "kernel_ms": round(kern * 1e3, 4),
@@ -192,7 +203,7 @@ def extra_workloads(trid):
 
         t = time_calls(xy, 5, warm=1)
         wb = 8 if dt == torch.float64 else 4
-        byts = 6 * wb * 64 * 1024 * 1024
+        byts = 2 * alg_bytes("s", wb, 64 * 1024 * 1024)
         out["adi2d_64x1024sq_xy_%s" % tag] = {"ms": round(t * 1e3, 4), "gbs": round(byts / t / 1e9, 1),
                                               "frac": round(byts / t / 1e9 / PEAK_GBS, 4)}
         del ts, d0, td

@@ -10,6 +10,7 @@
 #include "../../include/trid.h"
 #include "dispatch.hpp"
 #include "ext.hpp"
+#include "refine.hpp"
 
 namespace trid {
 
@@ -130,15 +131,55 @@ int trid_gtsv_batched_s_adjoint(trid_handle_t h, trid_dtype_t dt, const void *s,
     return trid::handle_run_lines(h, r);
 }
 
-int trid_gtsv_batched_refine(trid_handle_t h, trid_dtype_t, const float *, const float *,
-                             const float *, const void *, double *, int, const int64_t *, int,
-                             int64_t) {
-    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "refine: not in this build") : TRID_ERR_ARG;
+static int run_refine(trid_handle_t h, trid::RefineReq &r, const char *what) {
+    trid::ExtState &x = trid::handle_ext(h);
+    if (x.force_M == 16 || x.force_M == 32) r.force_M = x.force_M;
+    if (x.force_L) r.force_L = x.force_L;
+    trid::RefPlan pl;
+    std::string msg;
+    if (!trid::plan_refine(r, &pl, &msg)) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
+    hipStream_t st = trid::handle_stream(h);
+    hipError_t e = x.timer.time(pl.staged ? "refine_staged" : "refine_strided", st,
+                                [&] { return trid::launch_refine(r, pl, st); });
+    if (e != hipSuccess) return trid::handle_hip_fail(h, e, what);
+    return TRID_OK;
 }
 
-int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t, const float *, const void *, double *,
-                               int, const int64_t *, int, int64_t) {
-    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "refine: not in this build") : TRID_ERR_ARG;
+int trid_gtsv_batched_refine(trid_handle_t h, trid_dtype_t d_dt, const float *a, const float *b,
+                             const float *c, const void *d, double *x, int ndim, const int64_t *dims,
+                             int axis, int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (d_dt != TRID_F32 && d_dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype of d");
+    if (!a || !b || !c || !d || !x) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    if ((const void *)x == d) return trid::handle_fail(h, TRID_ERR_ARG, "x may not alias d");
+    trid::RefineReq r;
+    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    if (rc) return rc;
+    r.smode = false;
+    r.d_f64 = d_dt == TRID_F64;
+    r.src.a = a;
+    r.src.b = b;
+    r.src.c = c;
+    r.d = d;
+    r.x = x;
+    return run_refine(h, r, "refine launch");
+}
+
+int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t d_dt, const float *s, const void *d, double *x,
+                               int ndim, const int64_t *dims, int axis, int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (d_dt != TRID_F32 && d_dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype of d");
+    if (!s || !d || !x) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    if ((const void *)x == d) return trid::handle_fail(h, TRID_ERR_ARG, "x may not alias d");
+    trid::RefineReq r;
+    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    if (rc) return rc;
+    r.smode = true;
+    r.d_f64 = d_dt == TRID_F64;
+    r.src.s = s;
+    r.d = d;
+    r.x = x;
+    return run_refine(h, r, "refine launch");
 }
 
 int trid_gtsv_varlen(trid_handle_t h, trid_prec_t, const void *, const void *, const void *,

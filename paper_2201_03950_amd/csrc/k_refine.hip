@@ -1,0 +1,337 @@
+// k_refine.hip -- FP32 bulk solve with one FP64 residual and refinement sweep,
+// fused while each tile stays in registers:
+//   x32 = solve32(A32, fp32(d));  r = d - A x32 (FP64);  dx = solve32(A32, fp32(r));
+//   x = x32 + dx (FP64).
+// A is the matrix of record given by FP32 coefficients (a, b, c arrays, or s with
+// rows (-s, 1 + 2 s, -s)); its FP64 rows are exact promotions of them.  The
+// solves are the tiled modified Thomas of eq. (7) with the PCR reduced solve
+// (Section III-B), as in the plain kernels.  Not in the paper: the precision
+// scheme is an addition of this library.
+#include <algorithm>
+
+#include "dispatch.hpp"
+#include "lines.hpp"
+#include "refine.hpp"
+
+namespace trid {
+
+// FP32 coefficients of one tile, loaded once and reused by both solves.
+template <int M, bool SM>
+struct RefCoef;
+
+template <int M>
+struct RefCoef<M, true> {  // rows (-s, 1 + 2 s, -s)
+    float s[M];
+    int g0, n;
+    __device__ __forceinline__ void row32(int k, float &a, float &b, float &c) const {
+        const int g = g0 + k;
+        const bool v = g < n;
+        a = (v && g > 0) ? -s[k] : 0.f;
+        b = v ? 1.f + 2.f * s[k] : 1.f;
+        c = (v && g < n - 1) ? -s[k] : 0.f;
+    }
+    __device__ __forceinline__ void row64(int k, double &a, double &b, double &c) const {
+        const int g = g0 + k;
+        const bool v = g < n;
+        const double sv = (double)s[k];
+        a = (v && g > 0) ? -sv : 0.0;
+        b = v ? 1.0 + 2.0 * sv : 1.0;
+        c = (v && g < n - 1) ? -sv : 0.0;
+    }
+};
+
+template <int M>
+struct RefCoef<M, false> {  // per-point a, b, c
+    float a[M], b[M], c[M];
+    int g0, n;
+    __device__ __forceinline__ void row32(int k, float &ra, float &rb, float &rc) const {
+        const int g = g0 + k;
+        const bool v = g < n;
+        ra = (v && g > 0) ? a[k] : 0.f;
+        rb = v ? b[k] : 1.f;
+        rc = (v && g < n - 1) ? c[k] : 0.f;
+    }
+    __device__ __forceinline__ void row64(int k, double &ra, double &rb, double &rc) const {
+        float fa, fb, fc;
+        row32(k, fa, fb, fc);
+        ra = fa;
+        rb = fb;
+        rc = fc;
+    }
+};
+
+// Both solves and the residual for one tile; returns x = x32 + dx in `out`.
+// red: 6 S floats of PCR scratch; xb: 2 S doubles for the tile-boundary exchange.
+template <int M, bool SM>
+__device__ __forceinline__ void refine_tile(const RefCoef<M, SM> &cf, const double (&dd)[M],
+                                            float *__restrict__ red, double *__restrict__ xb, int S,
+                                            int P, int p, int slot, int pstride, double (&out)[M]) {
+    auto rows = [&](int k, float &a, float &b, float &c) { cf.row32(k, a, b, c); };
+    float rd[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) rd[k] = (float)dd[k];
+    float x32[M];
+    {
+        TileState<float, M> ts;
+        tile_eliminate_fn<float, M>(rows, rd, ts);
+        float f, lv;
+        reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv);
+        tile_backsub<float, M>(ts, f, lv, x32);
+    }
+    // neighbours of the tile's first and last rows for the residual
+    xb[slot] = x32[0];
+    xb[S + slot] = x32[M - 1];
+    __syncthreads();
+    const double xprev = (p > 0) ? xb[S + slot - pstride] : 0.0;
+    const double xnext = (p + 1 < P) ? xb[slot + pstride] : 0.0;
+    // r = d - A x32 in FP64 (A: FP64 promotion of the FP32 rows)
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        double a, b, c;
+        cf.row64(k, a, b, c);
+        const double xm = k > 0 ? (double)x32[k - 1] : xprev;
+        const double xp = k < M - 1 ? (double)x32[k + 1] : xnext;
+        rd[k] = (float)(dd[k] - (a * xm + b * (double)x32[k] + c * xp));
+    }
+    float dx[M];
+    {
+        TileState<float, M> ts;
+        tile_eliminate_fn<float, M>(rows, rd, ts);
+        float f, lv;
+        reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv);
+        tile_backsub<float, M>(ts, f, lv, dx);
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) out[k] = (double)x32[k] + (double)dx[k];
+}
+
+// ------------------------------------------------------------- strided --
+
+template <typename TD, int M, bool SM, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_refine_strided(StridedGeom gm, RefPtrs src, const TD *__restrict__ d,
+                                                         double *__restrict__ x) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int L = gm.L, P = gm.P, S = L * P;
+    double *xb = reinterpret_cast<double *>(smem_raw);
+    float *red = reinterpret_cast<float *>(xb + 2 * S);
+    const int t = threadIdx.x, l = t % L, p = t / L;
+    const i64 blk = xcd_block_id();
+    const i64 ib = blk % gm.nib, ob = blk / gm.nib;
+    const i64 ii = ib * L + l;
+    const bool act = ii < gm.inner;
+    const i64 st = gm.inner;
+    const i64 base = ob * (i64)gm.n * st + (act ? ii : 0);
+    const int g0 = p * M, n = gm.n;
+    RefCoef<M, SM> cf;
+    cf.g0 = g0;
+    cf.n = act ? n : 0;  // inactive lanes see identity rows only
+    double dd[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int g = g0 + k;
+        const bool v = act && g < n;
+        const i64 off = base + (i64)g * st;
+        if constexpr (SM) {
+            cf.s[k] = v ? src.s[off] : 0.f;
+        } else {
+            cf.a[k] = v ? src.a[off] : 0.f;
+            cf.b[k] = v ? src.b[off] : 1.f;
+            cf.c[k] = v ? src.c[off] : 0.f;
+        }
+        dd[k] = v ? (double)d[off] : 0.0;
+    }
+    double out[M];
+    refine_tile<M, SM>(cf, dd, red, xb, S, P, p, t, L, out);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int g = g0 + k;
+        if (act && g < n) x[base + (i64)g * st] = out[k];
+    }
+}
+
+// -------------------------------------------------------------- staged --
+// x lines: the block's coefficient arrays and d are staged into LDS (tiles
+// padded to M + 1 elements); the FP64 result leaves through the same LDS area.
+
+template <typename TD, int M, bool SM>
+__global__ __launch_bounds__(256) void k_refine_staged(StagedGeom gm, RefPtrs src, const TD *__restrict__ d,
+                                                       double *__restrict__ x) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int L = gm.L, P = gm.P, n = gm.n, ls = gm.ls, S = L * P;
+    const int reg = L * ls;
+    constexpr int NC = SM ? 1 : 3;
+    float *cst = reinterpret_cast<float *>(smem_raw);  // NC coefficient regions
+    // d region, 16-byte aligned (the planner reserves the padding)
+    const size_t doff = ((size_t)NC * reg * sizeof(float) + 15) & ~(size_t)15;
+    TD *dst = reinterpret_cast<TD *>(smem_raw + doff);
+    unsigned char *after = reinterpret_cast<unsigned char *>(dst + reg);
+    after += (16 - (reinterpret_cast<uintptr_t>(after) & 15)) & 15;
+    double *xb = reinterpret_cast<double *>(after);
+    float *red = reinterpret_cast<float *>(xb + 2 * S);
+    const int t = threadIdx.x, p = t % P, l = t / P;
+    const i64 o0 = xcd_block_id() * L;
+    const int nl = (int)((gm.nlines - o0) < (i64)L ? (gm.nlines - o0) : (i64)L);
+    const i64 off = o0 * n;
+    const int cnt = nl * n;
+    if constexpr (SM) {
+        stage_in<float, M>(cst, src.s + off, cnt, n, ls);
+    } else {
+        stage_in<float, M>(cst, src.a + off, cnt, n, ls);
+        stage_in<float, M>(cst + reg, src.b + off, cnt, n, ls);
+        stage_in<float, M>(cst + 2 * reg, src.c + off, cnt, n, ls);
+    }
+    stage_in<TD, M>(dst, d + off, cnt, n, ls);
+    __syncthreads();
+    const bool act = l < nl;
+    const int pos = l * ls + p * (M + 1);
+    RefCoef<M, SM> cf;
+    cf.g0 = p * M;
+    cf.n = act ? n : 0;
+    double dd[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const bool v = act && p * M + k < n;
+        if constexpr (SM) {
+            cf.s[k] = v ? cst[pos + k] : 0.f;
+        } else {
+            cf.a[k] = v ? cst[pos + k] : 0.f;
+            cf.b[k] = v ? cst[reg + pos + k] : 1.f;
+            cf.c[k] = v ? cst[2 * reg + pos + k] : 0.f;
+        }
+        dd[k] = v ? (double)dst[pos + k] : 0.0;
+    }
+    double out[M];
+    refine_tile<M, SM>(cf, dd, red, xb, S, P, p, t, 1, out);
+    // the staged inputs are dead (every thread passed refine_tile's barriers):
+    // reuse the area, viewed as doubles at the same staged positions
+    double *ost = reinterpret_cast<double *>(smem_raw);
+#pragma unroll
+    for (int k = 0; k < M; ++k) ost[pos + k] = out[k];
+    __syncthreads();
+    stage_out<double, M>(x + off, ost, cnt, n, ls);
+}
+
+// ---------------------------------------------------------------- host --
+
+namespace {
+
+i64 cdiv(i64 a, i64 b) { return (a + b - 1) / b; }
+
+int pow2_floor(i64 v) {
+    int p = 1;
+    while ((i64)p * 2 <= v) p *= 2;
+    return p;
+}
+
+int pow2_ceil(i64 v) {
+    int p = 1;
+    while ((i64)p < v) p *= 2;
+    return p;
+}
+
+// Block size bound from the per-thread register footprint (FP32 tile state,
+// FP32 coefficients, FP64 right-hand side).
+constexpr int refine_strided_maxt(int M, bool sm) {
+    return M <= 16 ? 512 : 256;
+}
+
+template <typename TD, int M, bool SM>
+hipError_t go_strided(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
+    StridedGeom g;
+    g.inner = r.inner;
+    g.nib = cdiv(r.inner, pl.L);
+    g.n = (int)r.n;
+    g.L = pl.L;
+    g.P = pl.P;
+    constexpr int MAXT = refine_strided_maxt(M, SM);
+    hipLaunchKernelGGL((k_refine_strided<TD, M, SM, MAXT>), dim3((unsigned)pl.nblocks), dim3(pl.L * pl.P),
+                       pl.shmem, s, g, r.src, static_cast<const TD *>(r.d), r.x);
+    return hipGetLastError();
+}
+
+template <typename TD, int M, bool SM>
+hipError_t go_staged(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
+    StagedGeom g;
+    g.nlines = r.outer;
+    g.n = (int)r.n;
+    g.L = pl.L;
+    g.P = pl.P;
+    g.ls = pl.ls;
+    hipLaunchKernelGGL((k_refine_staged<TD, M, SM>), dim3((unsigned)pl.nblocks), dim3(pl.L * pl.P),
+                       pl.shmem, s, g, r.src, static_cast<const TD *>(r.d), r.x);
+    return hipGetLastError();
+}
+
+template <typename TD, bool SM>
+hipError_t go_m(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
+    if (pl.staged) return pl.M == 32 ? go_staged<TD, 32, SM>(r, pl, s) : go_staged<TD, 16, SM>(r, pl, s);
+    return pl.M == 32 ? go_strided<TD, 32, SM>(r, pl, s) : go_strided<TD, 16, SM>(r, pl, s);
+}
+
+constexpr size_t kMaxShmem = 64 * 1024;
+
+}  // namespace
+
+bool plan_refine(const RefineReq &r, RefPlan *pl, std::string *err) {
+    RefPlan p;
+    const bool sm = r.smode;
+    int M = r.force_M ? r.force_M : (r.n > 512 ? 32 : 16);
+    if (M != 16 && M != 32) M = 16;
+    i64 P = cdiv(r.n, M);
+    if (P > 256 && M == 16) {
+        M = 32;
+        P = cdiv(r.n, M);
+    }
+    p.M = M;
+    p.P = (int)P;
+    const size_t dw = r.d_f64 ? 8 : 4;
+    if (r.inner == 1 && P <= 256) {
+        const int ls = (int)P * (M + 1);
+        const int nc = sm ? 1 : 3;
+        auto bytes = [&](int L) {
+            size_t in = (size_t)L * ls * (4 * nc + dw) + 16;  // + alignment of the d region
+            in = std::max(in, (size_t)L * ls * 8) + 16;
+            return in + 2 * (size_t)L * P * 8 + 6 * (size_t)L * P * 4;
+        };
+        int L = r.force_L ? r.force_L : std::max(1, 256 / (int)P);
+        L = std::max(1, std::min(L, pow2_ceil(r.outer)));
+        while (L > 1 && bytes(L) > kMaxShmem) L /= 2;
+        if (bytes(L) <= kMaxShmem && (i64)L * P <= 256) {
+            p.staged = true;
+            p.L = L;
+            p.ls = ls;
+            p.shmem = bytes(L);
+            p.nblocks = cdiv(r.outer, L);
+            *pl = p;
+            return true;
+        }
+    }
+    const int maxt = refine_strided_maxt(M, sm);
+    if (P > maxt) {
+        *err = "line too long for the refinement kernels";
+        return false;
+    }
+    int L = r.force_L ? r.force_L : std::min(64, pow2_floor(maxt / P));
+    if (!r.force_L && r.inner < L) L = std::max(1, pow2_ceil(r.inner));
+    if ((i64)L * P > maxt) {
+        *err = "refinement plan exceeds the block size";
+        return false;
+    }
+    p.staged = false;
+    p.L = L;
+    p.shmem = 2 * (size_t)L * P * 8 + 6 * (size_t)L * P * 4;
+    p.nblocks = cdiv(r.inner, L) * r.outer;
+    if (p.nblocks >= (i64)1 << 31) {
+        *err = "too many blocks";
+        return false;
+    }
+    *pl = p;
+    return true;
+}
+
+hipError_t launch_refine(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
+    if (r.d_f64) return r.smode ? go_m<double, true>(r, pl, s) : go_m<double, false>(r, pl, s);
+    return r.smode ? go_m<float, true>(r, pl, s) : go_m<float, false>(r, pl, s);
+}
+
+}  // namespace trid

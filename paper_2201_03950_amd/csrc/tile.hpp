@@ -75,6 +75,41 @@ __device__ __forceinline__ void tile_eliminate(const T (&ra)[M], const T (&rb)[M
     s.fd = rd[0] - rc[0] * s.dp[1];
 }
 
+// Same sweep with rows produced on demand by rows(k, a, b, c) (so a caller that
+// solves twice need not keep the rows in registers); rd holds the rhs.
+template <typename T, int M, class Rows>
+__device__ __forceinline__ void tile_eliminate_fn(const Rows &rows, const T (&rd)[M], TileState<T, M> &s) {
+    static_assert(M >= 3, "tiles need at least three rows");
+    T a, b, c;
+    rows(1, a, b, c);
+    const T r1 = T(1) / b;
+    s.ap[1] = a * r1;
+    s.cp[1] = c * r1;
+    s.dp[1] = rd[1] * r1;
+#pragma unroll
+    for (int k = 2; k < M; ++k) {
+        rows(k, a, b, c);
+        const T r = T(1) / (b - a * s.cp[k - 1]);
+        s.ap[k] = -r * a * s.ap[k - 1];
+        s.cp[k] = r * c;
+        s.dp[k] = r * (rd[k] - a * s.dp[k - 1]);
+    }
+    s.la = s.ap[M - 1];
+    s.lc = s.cp[M - 1];
+    s.ld = s.dp[M - 1];
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) {
+        s.dp[k] -= s.cp[k] * s.dp[k + 1];
+        s.ap[k] -= s.cp[k] * s.ap[k + 1];
+        s.cp[k] = -s.cp[k] * s.cp[k + 1];
+    }
+    rows(0, a, b, c);
+    s.fa = a;
+    s.fb = b - c * s.ap[1];
+    s.fc = -c * s.cp[1];
+    s.fd = rd[0] - c * s.dp[1];
+}
+
 // Reduced solve of one line across its P tiles.
 //   sh      : LDS scratch of 6*S elements, S = number of threads of the block
 //   slot    : this thread's slot in [0, S)
