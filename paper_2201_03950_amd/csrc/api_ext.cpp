@@ -187,10 +187,93 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t, const void *, const void *, c
     return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "varlen: not in this build") : TRID_ERR_ARG;
 }
 
-int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t, const void *, const void *, void *, void *,
-                          int, const int64_t *, int64_t) {
-    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "ADI adjoint: not in this build")
-             : TRID_ERR_ARG;
+int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s, void *u_bar,
+                          void *s_bar, int ndim, const int64_t *dims, int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!u_t || !s || !u_bar || !s_bar) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    if (ndim != 2 && ndim != 3) return trid::handle_fail(h, TRID_ERR_ARG, "ADI needs ndim 2 or 3");
+    trid::i64 inner[3], n[3], outer[3];
+    for (int ax = 0; ax < ndim; ++ax) {
+        int rc = trid::handle_check_mesh(h, ndim, dims, ax, batch, &inner[ax], &n[ax], &outer[ax]);
+        if (rc) return rc;
+    }
+    const bool f64 = dt == TRID_F64;
+    const trid::i64 nx = dims[0], ny = dims[1], nz = ndim == 3 ? dims[2] : 1;
+    const size_t bytes = (size_t)(nx * ny * nz * batch) * (f64 ? 8 : 4);
+    const size_t slot = (bytes + 255) & ~(size_t)255;
+    void *ws = nullptr;
+    int rc = trid::handle_workspace2(h, 4 * slot, &ws);
+    if (rc) return rc;
+    char *wb = static_cast<char *>(ws);
+    void *W[5] = {nullptr, wb, wb + slot, wb + 2 * slot, wb + 3 * slot};  // W[1..3]: forward outputs, W[4]: lambda
+    trid::ExtState &x = trid::handle_ext(h);
+    hipStream_t st = trid::handle_stream(h);
+    std::string msg;
+    // recompute the forward step from the checkpoint: W1 = X^-1 (2 s L u_t), W[k+1] = A_k^-1 W[k]
+    trid::AdiReq ar;
+    ar.f64 = f64;
+    ar.ndim = ndim;
+    ar.u = u_t;
+    ar.s = s;
+    ar.d = W[1];
+    ar.nx = nx;
+    ar.ny = ny;
+    ar.nz = nz;
+    ar.batch = batch;
+    trid::LinePlan pl;
+    if (!trid::plan_rhs_x(ar, &pl, &msg)) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
+    hipError_t e = x.timer.time("adj_rhs_x", st, [&] { return trid::launch_rhs_x(ar, pl, st); });
+    if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI adjoint: stencil + x launch");
+    for (int k = 1; k < ndim; ++k) {
+        trid::LineReq r;
+        r.f64 = f64;
+        r.mode = trid::Mode::S;
+        r.out = trid::Out::Store;
+        r.s = s;
+        r.d = W[k];
+        r.x = W[k + 1];
+        r.inner = inner[k];
+        r.n = n[k];
+        r.outer = outer[k];
+        if (!trid::plan_lines(r, &pl, &msg)) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
+        e = x.timer.time("adj_fwd_solve", st, [&] { return trid::launch_lines(r, pl, st); });
+        if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI adjoint: forward solve launch");
+    }
+    // reverse sweep: lambda = A_k^-T lambda, sbar += lambda * (second difference of A_k's output)
+    for (int k = ndim - 1; k >= 0; --k) {
+        trid::LineReq r;
+        r.f64 = f64;
+        r.mode = trid::Mode::ST;
+        r.out = trid::Out::AdjS;
+        r.s = s;
+        r.xf = W[k + 1];
+        r.d = (k == ndim - 1) ? u_bar : W[4];
+        r.g = W[4];
+        r.gs = s_bar;
+        r.inner = inner[k];
+        r.n = n[k];
+        r.outer = outer[k];
+        if (!trid::plan_lines(r, &pl, &msg)) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
+        e = x.timer.time("adj_solve", st, [&] { return trid::launch_lines(r, pl, st); });
+        if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI adjoint: transposed solve launch");
+    }
+    // lambda is now dLoss/d(rhs): stencil adjoint into u_bar and s_bar
+    trid::StencilAdjReq sa;
+    sa.f64 = f64;
+    sa.ndim = ndim;
+    sa.u = u_t;
+    sa.s = s;
+    sa.rbar = W[4];
+    sa.ubar = u_bar;
+    sa.sbar = s_bar;
+    sa.nx = nx;
+    sa.ny = ny;
+    sa.nz = nz;
+    sa.batch = batch;
+    e = x.timer.time("adj_stencil", st, [&] { return trid::launch_stencil_adjoint(sa, st); });
+    if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI adjoint: stencil adjoint launch");
+    return TRID_OK;
 }
 
 int trid_plan_load(trid_handle_t h, const char *) {

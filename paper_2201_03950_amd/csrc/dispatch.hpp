@@ -42,6 +42,7 @@ struct LineReq {
     bool f64 = true;
     Mode mode = Mode::Arrays;
     Out out = Out::Store;
+    // d: right-hand side (adjoint epilogues: optional out-of-place rhs; NULL = g)
     const void *a = nullptr, *b = nullptr, *c = nullptr, *s = nullptr, *d = nullptr;
     double ca = 0, cb = 0, cc = 0;
     void *x = nullptr;         // Store / Add target
@@ -82,5 +83,16 @@ int const_lines_M(const LineReq &r);
 hipError_t launch_const_lines(const LineReq &r, int M, hipStream_t s);
 int const_rhs_M(const AdiReq &r);
 hipError_t launch_const_rhs_x(const AdiReq &r, int M, hipStream_t s);
+
+// Adjoint of the ADI right-hand side d = 2 s L u (per-point s), pointwise:
+//   sbar += 2 rbar (L u);   ubar += 2 L (s rbar)   (L symmetric, zero ghosts).
+struct StencilAdjReq {
+    bool f64 = true;
+    int ndim = 3;
+    const void *u = nullptr, *s = nullptr, *rbar = nullptr;
+    void *ubar = nullptr, *sbar = nullptr;
+    i64 nx = 1, ny = 1, nz = 1, batch = 1;
+};
+hipError_t launch_stencil_adjoint(const StencilAdjReq &r, hipStream_t s);
 
 }  // namespace trid

@@ -188,14 +188,16 @@ hipError_t launch_typed(const LineReq &r, const LinePlan &pl, hipStream_t s) {
         }
     }
     const T *xf = static_cast<const T *>(r.xf);
+    // adjoint right-hand side: r.d if given (out of place), else g itself
+    const T *grhs = r.d ? d : static_cast<const T *>(r.g);
     if (r.out == Out::AdjArrays && r.mode == Mode::ArraysT) {
         EpiAdjArrays<T> e{xf, static_cast<T *>(r.g), static_cast<T *>(r.ga), static_cast<T *>(r.gb),
                           static_cast<T *>(r.gc)};
-        return strided_M<T>(r, pl, SrcArraysT<T>{a, b, c, static_cast<const T *>(r.g)}, e, s);
+        return strided_M<T>(r, pl, SrcArraysT<T>{a, b, c, grhs}, e, s);
     }
     if (r.out == Out::AdjS && r.mode == Mode::ST) {
         EpiAdjS<T> e{xf, static_cast<T *>(r.g), static_cast<T *>(r.gs)};
-        return strided_M<T>(r, pl, SrcST<T>{sp, static_cast<const T *>(r.g)}, e, s);
+        return strided_M<T>(r, pl, SrcST<T>{sp, grhs}, e, s);
     }
     return hipErrorInvalidValue;
 }
