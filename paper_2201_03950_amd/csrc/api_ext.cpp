@@ -1,16 +1,21 @@
 // api_ext.cpp -- extern "C" entry points beyond the plain solves: tile-plan
-// control, line-solve adjoints, and the entry points not yet available on this
-// build (which return TRID_ERR_UNSUPPORTED).
+// control and timing, refinement, line-solve and ADI-step adjoints, the uneven
+// batch (schedule cache, autotuner, graph replay) and the plan cache.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <sstream>
 #include <string>
 
 #include "../../include/trid.h"
 #include "dispatch.hpp"
 #include "ext.hpp"
 #include "refine.hpp"
+#include "varlen.hpp"
 
 namespace trid {
 
@@ -19,6 +24,13 @@ void ExtState::release() {
     if (ws2) hipFree(ws2);
     ws2 = nullptr;
     ws2_bytes = 0;
+    for (auto &kv : varlen) {
+        varlen_free(kv.second);
+        delete kv.second;
+    }
+    varlen.clear();
+    if (capture_stream) hipStreamDestroy(capture_stream);
+    capture_stream = nullptr;
 }
 
 int handle_workspace2(trid_handle_t h, size_t bytes, void **ptr) {
@@ -182,9 +194,177 @@ int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t d_dt, const float *
     return run_refine(h, r, "refine launch");
 }
 
-int trid_gtsv_varlen(trid_handle_t h, trid_prec_t, const void *, const void *, const void *,
-                     const void *, void *, const int64_t *, int64_t) {
-    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "varlen: not in this build") : TRID_ERR_ARG;
+namespace {
+
+// Plan-cache key of an uneven batch: precision, count and a log2 histogram of lengths.
+std::string varlen_plan_key(const int64_t *off, int64_t nsys, int prec) {
+    int hist[64] = {0};
+    for (int64_t k = 0; k < nsys; ++k) {
+        int64_t len = off[k + 1] - off[k];
+        int b = 0;
+        while ((int64_t)1 << (b + 1) <= len) ++b;
+        ++hist[b];
+    }
+    std::ostringstream os;
+    os << "varlen/p" << prec << "/n" << nsys << "/h";
+    bool first = true;
+    for (int b = 0; b < 64; ++b)
+        if (hist[b]) {
+            os << (first ? "" : ",") << b << ":" << hist[b];
+            first = false;
+        }
+    return os.str();
+}
+
+// Exact identity of an offsets array (FNV-1a) for the schedule cache.
+std::string varlen_sched_key(const int64_t *off, int64_t nsys, int prec) {
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t k = 0; k <= nsys; ++k) {
+        uint64_t v = (uint64_t)off[k];
+        for (int byte = 0; byte < 8; ++byte) {
+            h ^= (v >> (8 * byte)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    }
+    char buf[64];
+    snprintf(buf, sizeof buf, "%d/%lld/%016llx", prec, (long long)nsys, (unsigned long long)h);
+    return buf;
+}
+
+bool autotune_requested() {
+    const char *v = std::getenv("TRID_AUTOTUNE");
+    return v && v[0] == '1';
+}
+
+// Time one schedule: one warm-up and three timed launches on stream st.
+hipError_t time_schedule(const trid::VarlenSchedule &sc, const void *a, const void *b, const void *c,
+                         const void *d, void *x, hipStream_t st, float *us) {
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        hipEventDestroy(e0);
+        return e;
+    }
+    e = trid::varlen_launch(sc, a, b, c, d, x, st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = trid::varlen_launch(sc, a, b, c, d, x, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    *us = ms * 1000.f / 3.f;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return e;
+}
+
+}  // namespace
+
+int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const void *b, const void *c,
+                     const void *d, void *x, const int64_t *off, int64_t nsys) {
+    if (!h) return TRID_ERR_ARG;
+    if (prec != TRID_PREC_F64 && prec != TRID_PREC_F32 && prec != TRID_PREC_F32_REFINE64)
+        return trid::handle_fail(h, TRID_ERR_ARG, "bad precision");
+    if (!a || !b || !c || !d || !x || !off) return trid::handle_fail(h, TRID_ERR_ARG, "NULL pointer");
+    if (nsys < 1 || nsys > ((int64_t)1 << 30)) return trid::handle_fail(h, TRID_ERR_ARG, "nsys out of range");
+    if (prec == TRID_PREC_F32_REFINE64 && d == x) return trid::handle_fail(h, TRID_ERR_ARG, "x may not alias d");
+    if (off[0] != 0) return trid::handle_fail(h, TRID_ERR_ARG, "offsets[0] must be 0");
+    int64_t maxlen = 0;
+    for (int64_t k = 0; k < nsys; ++k) {
+        const int64_t len = off[k + 1] - off[k];
+        if (len < 1) return trid::handle_fail(h, TRID_ERR_ARG, "every system needs at least one row");
+        if (len > TRID_MAX_LINE) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "system longer than TRID_MAX_LINE");
+        maxlen = std::max(maxlen, len);
+    }
+    trid::ExtState &xs = trid::handle_ext(h);
+    hipStream_t st = trid::handle_stream(h);
+    const int p = (int)prec;
+    const std::string skey = varlen_sched_key(off, nsys, p);
+    auto it = xs.varlen.find(skey);
+    if (it == xs.varlen.end()) {
+        const std::string pkey = varlen_plan_key(off, nsys, p);
+        std::vector<trid::VarlenVariant> cands;
+        for (const auto &v : trid::varlen_variants(p))
+            if (trid::varlen_variant_fits(v, maxlen)) cands.push_back(v);
+        if (cands.empty()) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "no tile plan fits the longest system");
+        auto tuned = xs.tuned.find(pkey);
+        const bool tune = autotune_requested() && cands.size() > 1;
+        trid::VarlenSchedule *best = nullptr;
+        if (tune) {
+            for (const auto &v : cands) {
+                auto *sc = new trid::VarlenSchedule();
+                hipError_t e = trid::varlen_build(off, nsys, p, v, sc);
+                float us = 0.f;
+                if (e == hipSuccess) e = time_schedule(*sc, a, b, c, d, x, st, &us);
+                if (e != hipSuccess) {
+                    trid::varlen_free(sc);
+                    delete sc;
+                    if (best) {
+                        trid::varlen_free(best);
+                        delete best;
+                    }
+                    return trid::handle_hip_fail(h, e, "uneven batch: autotune");
+                }
+                sc->tuned_us = us;
+                if (!best || us < best->tuned_us) {
+                    if (best) {
+                        trid::varlen_free(best);
+                        delete best;
+                    }
+                    best = sc;
+                } else {
+                    trid::varlen_free(sc);
+                    delete sc;
+                }
+            }
+            xs.tuned[pkey] = {best->M, best->NT};
+        } else {
+            trid::VarlenVariant v = cands.front();
+            if (tuned != xs.tuned.end())
+                for (const auto &c2 : cands)
+                    if (c2.M == tuned->second.first && c2.NT == tuned->second.second) v = c2;
+            best = new trid::VarlenSchedule();
+            hipError_t e = trid::varlen_build(off, nsys, p, v, best);
+            if (e != hipSuccess) {
+                trid::varlen_free(best);
+                delete best;
+                return trid::handle_hip_fail(h, e, "uneven batch: schedule");
+            }
+        }
+        it = xs.varlen.emplace(skey, best).first;
+    }
+    trid::VarlenSchedule &sc = *it->second;
+    // one persistent launch, replayed from a captured graph per (pointers, stream)
+    auto gkey = std::make_tuple(a, b, c, d, x, st);
+    auto git = sc.graphs.find(gkey);
+    hipError_t e;
+    if (git == sc.graphs.end()) {
+        if (!xs.capture_stream) {
+            e = hipStreamCreateWithFlags(&xs.capture_stream, hipStreamNonBlocking);
+            if (e != hipSuccess) {
+                xs.capture_stream = nullptr;
+                return trid::handle_hip_fail(h, e, "hipStreamCreate");
+            }
+        }
+        e = hipStreamBeginCapture(xs.capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return trid::handle_hip_fail(h, e, "hipStreamBeginCapture");
+        hipError_t el = trid::varlen_launch(sc, a, b, c, d, x, xs.capture_stream);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(xs.capture_stream, &graph);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (graph) hipGraphDestroy(graph);
+            return trid::handle_hip_fail(h, el != hipSuccess ? el : e, "uneven batch: capture");
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) return trid::handle_hip_fail(h, e, "hipGraphInstantiate");
+        git = sc.graphs.emplace(gkey, exec).first;
+    }
+    e = xs.timer.time("varlen", st, [&] { return hipGraphLaunch(git->second, st); });
+    if (e != hipSuccess) return trid::handle_hip_fail(h, e, "uneven batch: launch");
+    return TRID_OK;
 }
 
 int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s, void *u_bar,
@@ -276,12 +456,47 @@ int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, con
     return TRID_OK;
 }
 
-int trid_plan_load(trid_handle_t h, const char *) {
-    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "plan cache: not in this build") : TRID_ERR_ARG;
+static std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    return a.substr(0, a.find(':'));
 }
 
-int trid_plan_save(trid_handle_t h, const char *) {
-    return h ? trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "plan cache: not in this build") : TRID_ERR_ARG;
+int trid_plan_save(trid_handle_t h, const char *path) {
+    if (!h) return TRID_ERR_ARG;
+    if (!path) return trid::handle_fail(h, TRID_ERR_ARG, "path is NULL");
+    std::ofstream f(path);
+    if (!f) return trid::handle_fail(h, TRID_ERR_ARG, std::string("cannot write ") + path);
+    trid::ExtState &x = trid::handle_ext(h);
+    f << "{\n \"arch\": \"" << device_arch() << "\",\n \"plans\": {\n";
+    size_t i = 0;
+    for (auto &kv : x.tuned) {
+        f << "  \"" << kv.first << "\": {\"M\": " << kv.second.first << ", \"NT\": " << kv.second.second << "}"
+          << (++i < x.tuned.size() ? "," : "") << "\n";
+    }
+    f << " }\n}\n";
+    return f.good() ? TRID_OK : trid::handle_fail(h, TRID_ERR_ARG, "write failed");
+}
+
+int trid_plan_load(trid_handle_t h, const char *path) {
+    if (!h) return TRID_ERR_ARG;
+    if (!path) return trid::handle_fail(h, TRID_ERR_ARG, "path is NULL");
+    std::ifstream f(path);
+    if (!f) return trid::handle_fail(h, TRID_ERR_ARG, std::string("cannot read ") + path);
+    trid::ExtState &x = trid::handle_ext(h);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t mpos = line.find("\"M\":"), npos = line.find("\"NT\":");
+        const size_t q0 = line.find('"'), q1 = q0 == std::string::npos ? q0 : line.find('"', q0 + 1);
+        if (mpos == std::string::npos || npos == std::string::npos || q1 == std::string::npos) continue;
+        const std::string key = line.substr(q0 + 1, q1 - q0 - 1);
+        const int M = std::atoi(line.c_str() + mpos + 4), NT = std::atoi(line.c_str() + npos + 5);
+        if (key.rfind("varlen/", 0) != 0 || M <= 0 || NT <= 0) continue;  // unknown keys are ignored
+        x.tuned[key] = {M, NT};
+    }
+    return TRID_OK;
 }
 
 }  // extern "C"

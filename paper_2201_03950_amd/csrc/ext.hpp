@@ -87,6 +87,7 @@ struct ExtState {
     void *ws2 = nullptr;
     size_t ws2_bytes = 0;
     KernelTimer timer;
+    hipStream_t capture_stream = nullptr;  // graph capture of the uneven-batch launch
 
     void apply_overrides(LineReq *r) const {
         if (force_M) r->force_M = force_M;
@@ -97,7 +98,8 @@ struct ExtState {
         if (force_L) r->force_L = force_L;
     }
     bool has_device_state() const {
-        return ws2 != nullptr || !varlen.empty() || !timer.pool.empty() || !timer.pending.empty();
+        return ws2 != nullptr || !varlen.empty() || !timer.pool.empty() || !timer.pending.empty() ||
+               capture_stream != nullptr;
     }
     void release();
 };

@@ -114,11 +114,15 @@ __device__ __forceinline__ void tile_eliminate_fn(const Rows &rows, const T (&rd
 //   sh      : LDS scratch of 6*S elements, S = number of threads of the block
 //   slot    : this thread's slot in [0, S)
 //   pstride : slot distance between tiles p and p+1 of the same line
-// Every thread of the block must call this (it contains barriers); P is
-// uniform over the block.  Returns f (tile's first unknown) and lv (its last).
+// Every thread of the block must call this (it contains barriers).  P is the
+// number of tiles of this thread's line; Pu >= P is a bound uniform over the
+// block (it sets the number of PCR levels and barriers; lines of different
+// lengths may share a block).  Returns f (tile's first unknown) and lv (its last).
 template <typename T, int M>
 __device__ __forceinline__ void reduced_pcr(const TileState<T, M> &ts, T *__restrict__ sh, int S,
-                                            int P, int p, int slot, int pstride, T &f, T &lv) {
+                                            int P, int p, int slot, int pstride, T &f, T &lv,
+                                            int Pu = 0) {
+    if (Pu < P) Pu = P;
     T *b0a = sh, *b0c = sh + S, *b0d = sh + 2 * S;
     T *b1a = sh + 3 * S, *b1c = sh + 4 * S, *b1d = sh + 5 * S;
     // 1. each tile publishes its last row (through buffer 1, first used by level 2)
@@ -142,7 +146,7 @@ __device__ __forceinline__ void reduced_pcr(const TileState<T, M> &ts, T *__rest
     T a = gsub * rg, c = gsup * rg, d = grhs * rg;
     // 3. PCR (Alg. 2) over the P rows, double-buffered: one barrier per level
     int lev = 0;
-    for (int s = 1; s < P; s <<= 1, ++lev) {
+    for (int s = 1; s < Pu; s <<= 1, ++lev) {
         T *ba = (lev & 1) ? b1a : b0a;
         T *bc = (lev & 1) ? b1c : b0c;
         T *bd = (lev & 1) ? b1d : b0d;
@@ -174,7 +178,7 @@ __device__ __forceinline__ void reduced_pcr(const TileState<T, M> &ts, T *__rest
     f = d;
     // 4. last unknown of the tile from its last row; needs f_{p+1}
     T fn = T(0);
-    if (P > 1) {
+    if (Pu > 1) {
         T *bx = (lev & 1) ? b1d : b0d;  // last read at level lev-2: free
         bx[slot] = f;
         __syncthreads();

@@ -1,0 +1,43 @@
+// varlen.hpp -- host-side schedule of the uneven-batch persistent solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <tuple>
+#include <vector>
+
+namespace trid {
+
+using i64 = int64_t;
+
+// A compiled tile plan: M rows per tile, NT threads (tiles) per work item.
+struct VarlenVariant {
+    int M, NT;
+};
+
+struct VarlenSchedule {
+    int prec = 0;  // 0: FP64, 1: FP32, 2: FP32 + FP64 refinement
+    int M = 16, NT = 512;
+    i64 nsys = 0;
+    int nitems = 0, nblocks = 0;
+    void *dev = nullptr;  // single device allocation holding the arrays below
+    i64 *off = nullptr;
+    int *order = nullptr, *tstart = nullptr, *item_begin = nullptr, *item_pmax = nullptr;
+    int *counter = nullptr;
+    float tuned_us = 0.f;  // measured time when chosen by the autotuner
+    // captured launches keyed by (a, b, c, d, x, stream)
+    std::map<std::tuple<const void *, const void *, const void *, const void *, void *, hipStream_t>,
+             hipGraphExec_t>
+        graphs;
+};
+
+const std::vector<VarlenVariant> &varlen_variants(int prec);
+bool varlen_variant_fits(const VarlenVariant &v, i64 maxlen);
+hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const VarlenVariant &v, VarlenSchedule *sc);
+hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b, const void *c, const void *d,
+                         void *x, hipStream_t s);
+void varlen_free(VarlenSchedule *sc);
+
+}  // namespace trid

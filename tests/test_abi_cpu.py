@@ -114,3 +114,26 @@ def test_set_stream_and_error_text(lib, h):
     assert lib.trid_set_stream(None, None) == 1
     assert lib.trid_gtsv_batched(h, 1, FAKE, FAKE, FAKE, FAKE, 5, _dims(1), 0, 1) == 1
     assert b"ndim" in lib.trid_last_error(h)
+
+
+def test_varlen_argument_checks(lib, h):
+    off = (ctypes.c_int64 * 4)(0, 3, 3, 7)  # a zero-length system
+    assert lib.trid_gtsv_varlen(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, off, 3) == 1
+    off = (ctypes.c_int64 * 3)(1, 3, 7)  # offsets[0] != 0
+    assert lib.trid_gtsv_varlen(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, off, 2) == 1
+    off = (ctypes.c_int64 * 2)(0, 9000)  # longer than TRID_MAX_LINE
+    assert lib.trid_gtsv_varlen(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, off, 1) == 4
+    off = (ctypes.c_int64 * 2)(0, 10)
+    assert lib.trid_gtsv_varlen(h, 9, FAKE, FAKE, FAKE, FAKE, FAKE, off, 1) == 1  # bad precision
+    assert lib.trid_gtsv_varlen(h, 2, FAKE, FAKE, FAKE, FAKE, FAKE, off, 1) == 1  # x aliases d (refine)
+    assert lib.trid_gtsv_varlen(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, None, 1) == 1
+
+
+def test_refine_and_adjoint_argument_checks(lib, h):
+    d = _dims(8, 8)
+    assert lib.trid_gtsv_batched_refine(h, 1, FAKE, FAKE, FAKE, FAKE, FAKE, 2, d, 0, 1) == 1  # x aliases d
+    assert lib.trid_gtsv_batched_s_refine(h, 5, FAKE, FAKE, ctypes.c_void_p(0x2000), 2, d, 0, 1) == 1
+    assert lib.trid_adi_step_adjoint(h, 1, FAKE, None, FAKE, FAKE, 3, _dims(8, 8, 8), 1) == 1
+    assert lib.trid_adi_step_adjoint(h, 1, FAKE, FAKE, FAKE, FAKE, 1, _dims(8), 1) == 1
+    assert lib.trid_plan_load(h, None) == 1
+    assert lib.trid_plan_load(h, b"/nonexistent/plans.json") == 1
