@@ -190,25 +190,150 @@ def extra_workloads(trid):
             "frac": round(words[k] * 4 * pts / (ms / cnt * 1e-3) / 1e9 / PEAK_GBS, 4)}
         for k, (cnt, ms) in kt.items()}}
     del u
-    # -- 64 meshes of 1024^2: x then y solves with per-point s
+    for name, fn in (("adi2d_64x1024sq_xy", extra_2d), ("varlen_20000", extra_varlen),
+                     ("diff_adi3d_128_20steps", extra_gradient)):
+        log("extra: " + name)
+        try:
+            out.update(fn(trid))
+        except Exception as exc:  # keep the main line even if one extra fails
+            out[name + "_error"] = repr(exc)
+        torch.cuda.empty_cache()
+    return out
+
+
+def _err_vs(ref, x):
+    import numpy as np
+
+    return float(np.max(np.abs(x - ref)) / np.max(np.abs(ref)))
+
+
+def extra_2d(trid):
+    """64 meshes of 1024^2: x then y solves with per-point s; FP64, FP32, FP32 + FP64 refinement."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle
+    from workloads import gen
+
+    out = {}
     s32, d32 = gen.adi2d_varcoef((1024, 1024), 64, seed=2)
+    ref = oracle.adi_xy(s32[:2].astype(np.float64), d32[:2].astype(np.float64))  # error sample: 2 meshes
+    pts = 64 * 1024 * 1024
+    res = {}
     for tag, dt in (("f64", torch.float64), ("f32", torch.float32)):
         ts = torch.from_numpy(s32).cuda().to(dt)
         d0 = torch.from_numpy(d32).cuda().to(dt)
         td = d0.clone()
 
         def xy():
+            td.copy_(d0)
             trid.gtsv_s(ts, td, 0)
             trid.gtsv_s(ts, td, 1)
 
         t = time_calls(xy, 5, warm=1)
+        err = _err_vs(ref, td[:2].double().cpu().numpy())  # td holds the last x-then-y result
+        t -= time_calls(lambda: td.copy_(d0), 5, warm=1)  # the reset copy is not solver time
         wb = 8 if dt == torch.float64 else 4
-        byts = 2 * alg_bytes("s", wb, 64 * 1024 * 1024)
-        out["adi2d_64x1024sq_xy_%s" % tag] = {"ms": round(t * 1e3, 4), "gbs": round(byts / t / 1e9, 1),
-                                              "frac": round(byts / t / 1e9 / PEAK_GBS, 4)}
+        byts = 2 * alg_bytes("s", wb, pts)
+        res[tag] = {"ms": round(t * 1e3, 4), "gbs": round(byts / t / 1e9, 1),
+                    "frac": round(byts / t / 1e9 / PEAK_GBS, 4), "err_vs_oracle": err}
         del ts, d0, td
         torch.cuda.empty_cache()
+    ts = torch.from_numpy(s32).cuda()
+    td = torch.from_numpy(d32).cuda()
+    mid = torch.empty(s32.shape, dtype=torch.float64, device="cuda")
+    xo = torch.empty_like(mid)
+
+    def xy_ref():
+        trid.gtsv_s_refine(ts, td, mid, 0)
+        trid.gtsv_s_refine(ts, mid, xo, 1)
+
+    t = time_calls(xy_ref, 5, warm=1)
+    byts = (4 + 4 + 8) * pts + (4 + 8 + 8) * pts  # x: s32, d32 -> x64; y: s32, x64 -> out64
+    res["f32_refine64"] = {"ms": round(t * 1e3, 4), "gbs": round(byts / t / 1e9, 1),
+                           "frac": round(byts / t / 1e9 / PEAK_GBS, 4),
+                           "err_vs_oracle": _err_vs(ref, xo[:2].cpu().numpy())}
+    res["refine_time_vs_f64"] = round(res["f32_refine64"]["ms"] / res["f64"]["ms"], 3)
+    out["adi2d_64x1024sq_xy"] = res
     return out
+
+
+def extra_varlen(trid):
+    """20,000 systems with lengths log-uniform in [32, 8192] in one persistent launch."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle
+    from workloads import gen
+
+    a32, b32, c32, d64, off = gen.varlen_batch()
+    rows = int(off[-1])
+    ref = oracle.gtsv_varlen(a32, b32, c32, d64, off)
+    res = {"systems": int(len(off) - 1), "rows": rows}
+    ta, tb, tc, td = (torch.from_numpy(v).cuda() for v in (a32, b32, c32, d64))
+    x = torch.empty_like(td)
+    trid.timing_enable(True)
+    t = time_calls(lambda: trid.gtsv_varlen(trid.PREC_F32_REFINE64, ta, tb, tc, td, x, off), 10)
+    kt = trid.timing_read()
+    trid.timing_enable(False)
+    cnt, ms = kt["varlen"]
+    kern = ms / cnt * 1e-3
+    num = np.maximum.reduceat(np.abs(x.cpu().numpy() - ref), off[:-1])
+    den = np.maximum.reduceat(np.abs(ref), off[:-1])
+    e = num / den
+    byts = 28 * rows
+    res["f32_refine64"] = {"ms": round(kern * 1e3, 4), "solves_per_s": round((len(off) - 1) / kern, 1),
+                           "gbs": round(byts / kern / 1e9, 1), "frac": round(byts / kern / 1e9 / PEAK_GBS, 4),
+                           "err_max": float(e.max()), "err_median": float(np.median(e))}
+    a64, b64, c64 = (v.double() for v in (ta, tb, tc))
+    x64 = torch.empty_like(td)
+    trid.timing_enable(True)
+    time_calls(lambda: trid.gtsv_varlen(trid.PREC_F64, a64, b64, c64, td, x64, off), 10)
+    kt = trid.timing_read()
+    trid.timing_enable(False)
+    cnt, ms = kt["varlen"]
+    kern = ms / cnt * 1e-3
+    byts = alg_bytes("arrays", 8, rows)
+    res["f64"] = {"ms": round(kern * 1e3, 4), "solves_per_s": round((len(off) - 1) / kern, 1),
+                  "gbs": round(byts / kern / 1e9, 1), "frac": round(byts / kern / 1e9 / PEAK_GBS, 4)}
+    return {"varlen_20000": res}
+
+
+def extra_gradient(trid):
+    """Differentiable 3D ADI, 128^3, 20 steps, s = 0.2 kappa: forward vs forward+backward."""
+    import numpy as np
+    import torch
+
+    from paper_2201_03950_amd import autograd
+    from workloads import gen
+
+    kappa, u0, kstar = gen.diffusion3d((128, 128, 128))
+    steps, s0 = 20, 0.2
+    tk, tu, tks = (torch.from_numpy(v).cuda() for v in (kappa, u0, kstar))
+    with torch.no_grad():
+        target = autograd.adi(tu, s0 * tks, steps)
+
+    def fwd():
+        with torch.no_grad():
+            uT = autograd.adi(tu, s0 * tk, steps)
+            return torch.sum((uT.double() - target.double()) ** 2)
+
+    def fwd_bwd():
+        k = tk.clone().requires_grad_(True)
+        u = tu.clone().requires_grad_(True)
+        uT = autograd.adi(u, s0 * k, steps)
+        loss = torch.sum((uT.double() - target.double()) ** 2)
+        loss.backward()
+        return k.grad
+
+    tf = time_calls(fwd, 3, warm=1)
+    tb = time_calls(fwd_bwd, 3, warm=1)
+    u64 = tu.double()
+    k64 = tk.double()
+    tf64 = time_calls(lambda: autograd.adi(u64, s0 * k64, steps), 3, warm=1)
+    return {"diff_adi3d_128_20steps": {"fwd_ms_f32": round(tf * 1e3, 3), "fwd_bwd_ms_f32": round(tb * 1e3, 3),
+                                       "fwd_bwd_over_fwd": round(tb / tf, 3),
+                                       "fwd_ms_f64": round(tf64 * 1e3, 3)}}
 
 
 def pmc_copy_calibration():

@@ -10,9 +10,9 @@
 
 namespace trid {
 
-// Staged source of the fused RHS.  Region 0 receives d, region 1 (per-point s
-// only) receives s.  NDIM = 3: 7-point stencil; NDIM = 2: 5-point stencil; zero
-// values outside the mesh.
+// Staged source of the fused RHS (per-point s or constant s0).  Region 0 is
+// d = 2 s L u computed while staging (7-point stencil in 3D, 5-point in 2D,
+// zero outside the mesh); region 1 (per-point s only) is s itself.
 template <typename T, bool PP, int NDIM>
 struct StgRhs {
     static constexpr int kRegions = PP ? 2 : 1;
@@ -22,8 +22,12 @@ struct StgRhs {
     int ny, nz;  // lines of one mesh = ny * nz (nz = 1 in 2D)
 
     template <int M>
-    __device__ __forceinline__ void stage(T *__restrict__ sh, int reg, i64 o0, int nl, int n,
-                                          int ls, void *scratch) const {
+    __device__ __forceinline__ void stage(int r, T *__restrict__ sh, i64 o0, int nl, int n, int ls,
+                                          void *scratch) const {
+        if (r == 1) {
+            stage_in<T, M>(sh, s + o0 * n, nl * n, n, ls);
+            return;
+        }
         // neighbour-existence flags of the block's lines: bit0 y-1, bit1 y+1, bit2 z-1, bit3 z+1
         int *flags = static_cast<int *>(scratch);
         for (int ll = threadIdx.x; ll < nl; ll += blockDim.x) {
@@ -51,9 +55,7 @@ struct StgRhs {
                 if (f & 8) sum += u[q + sz];
             }
             const T sv = PP ? s[q] : s0;
-            const int pos = staged_pos<M>(ll, i, ls);
-            sh[pos] = T(2) * sv * (sum - T(2 * NDIM) * uc);
-            if (PP) sh[reg + pos] = sv;
+            sh[staged_pos<M>(ll, i, ls)] = T(2) * sv * (sum - T(2 * NDIM) * uc);
             ll += dl;
             i += di;
             if (i >= n) {
@@ -64,18 +66,26 @@ struct StgRhs {
     }
 
     template <int M>
-    __device__ __forceinline__ void rows(const T *__restrict__ sh, int reg, int pos, int g0, int n,
-                                         bool act, T (&ra)[M], T (&rb)[M], T (&rc)[M],
-                                         T (&rd)[M]) const {
+    __device__ __forceinline__ void take(int r, const T *__restrict__ sh, int pos, int g0, int n, bool act,
+                                         T (&ra)[M], T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const int g = g0 + k;
             const bool v = act && g < n;
-            const T sv = v ? (PP ? sh[reg + pos + k] : s0) : T(0);
-            ra[k] = (g > 0) ? -sv : T(0);
-            rb[k] = T(1) + T(2) * sv;
-            rc[k] = (g < n - 1) ? -sv : T(0);
-            rd[k] = v ? sh[pos + k] : T(0);
+            if (r == 0) {
+                rd[k] = v ? sh[pos + k] : T(0);
+                if (!PP) {
+                    const T sv = v ? s0 : T(0);
+                    ra[k] = (g > 0) ? -sv : T(0);
+                    rb[k] = T(1) + T(2) * sv;
+                    rc[k] = (g < n - 1) ? -sv : T(0);
+                }
+            } else {
+                const T sv = v ? sh[pos + k] : T(0);
+                ra[k] = (g > 0) ? -sv : T(0);
+                rb[k] = T(1) + T(2) * sv;
+                rc[k] = (g < n - 1) ? -sv : T(0);
+            }
         }
     }
 };
@@ -134,12 +144,11 @@ bool plan_rhs_x(const AdiReq &r, LinePlan *pl, std::string *err) {
         *err = "x lines too long for the fused stencil + x solve";
         return false;
     }
-    const int regions = r.s ? 2 : 1;
     const int ls = (int)P * (M + 1);
     int L = r.force_L ? r.force_L : std::max(1, kMaxThreads / (int)P);
     auto bytes = [&](int LL) {
-        // staged regions + reduced-solve scratch (which also holds L ints of flags)
-        return (size_t)regions * LL * ls * w + std::max((size_t)6 * LL * P * w, (size_t)LL * 4);
+        // one staging region + reduced-solve scratch (which also holds L ints of flags)
+        return (size_t)LL * ls * w + std::max((size_t)6 * LL * P * w, (size_t)LL * 4);
     };
     while (bytes(L) > kMaxShmem && L > 1) L /= 2;
     if (bytes(L) > kMaxShmem || (i64)L * P > kMaxThreads) {

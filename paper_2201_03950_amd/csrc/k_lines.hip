@@ -73,8 +73,8 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
         int L = r.force_L ? r.force_L : std::max(1, kStagedMaxThreads / (int)P);
         L = std::max(1, std::min(L, pow2_ceil(r.outer)));
         const int ls = (int)P * (M + 1);
-        auto bytes = [&](int LL) {
-            return (size_t)regions * LL * ls * w + (size_t)6 * LL * P * w;
+        auto bytes = [&](int LL) {  // one staging region + reduced-solve scratch
+            return (size_t)LL * ls * w + (size_t)6 * LL * P * w;
         };
         while (bytes(L) > kMaxShmem && L > 1) L /= 2;
         if (bytes(L) <= kMaxShmem && L * P <= kStagedMaxThreads) {

@@ -364,37 +364,36 @@ __device__ __forceinline__ void stage_out(T *__restrict__ dst, const T *__restri
     }
 }
 
-// Staged sources: stage(regions, ..., scratch) fills LDS regions from global
-// memory for lines [o0, o0 + nl) (scratch: the reduced-solve LDS area, free
-// until the first barrier after staging); rows(...) builds the raw rows of one
-// tile from LDS.
+// Staged sources stage their arrays one at a time through ONE LDS region of
+// L * ls elements (so a block's LDS does not grow with the number of arrays):
+//   stage<M>(r, sh, o0, nl, n, ls, scratch): fill the region with array r of
+//       lines [o0, o0 + nl) (coalesced); scratch is the reduced-solve LDS area,
+//       free during staging;
+//   take<M>(r, sh, pos, g0, n, act, ra, rb, rc, rd): move this thread's tile
+//       of array r from LDS into the raw rows.
+// The kernel runs stage(r), barrier, take(r), barrier for r = 0..kRegions-1.
 
 template <typename T>
 struct StgArrays {
     static constexpr int kRegions = 4;
     const T *a, *b, *c, *d;
     template <int M>
-    __device__ __forceinline__ void stage(T *__restrict__ sh, int reg, i64 o0, int nl, int n,
-                                          int ls, void *) const {
-        const i64 off = o0 * n;
-        const int cnt = nl * n;
-        stage_in<T, M>(sh, a + off, cnt, n, ls);
-        stage_in<T, M>(sh + reg, b + off, cnt, n, ls);
-        stage_in<T, M>(sh + 2 * reg, c + off, cnt, n, ls);
-        stage_in<T, M>(sh + 3 * reg, d + off, cnt, n, ls);
+    __device__ __forceinline__ void stage(int r, T *__restrict__ sh, i64 o0, int nl, int n, int ls,
+                                          void *) const {
+        const T *src = r == 0 ? a : (r == 1 ? b : (r == 2 ? c : d));
+        stage_in<T, M>(sh, src + o0 * n, nl * n, n, ls);
     }
     template <int M>
-    __device__ __forceinline__ void rows(const T *__restrict__ sh, int reg, int pos, int g0, int n,
-                                         bool act, T (&ra)[M], T (&rb)[M], T (&rc)[M],
-                                         T (&rd)[M]) const {
+    __device__ __forceinline__ void take(int r, const T *__restrict__ sh, int pos, int g0, int n, bool act,
+                                         T (&ra)[M], T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const int g = g0 + k;
             const bool v = act && g < n;
-            ra[k] = (v && g > 0) ? sh[pos + k] : T(0);
-            rb[k] = v ? sh[reg + pos + k] : T(1);
-            rc[k] = (v && g < n - 1) ? sh[2 * reg + pos + k] : T(0);
-            rd[k] = v ? sh[3 * reg + pos + k] : T(0);
+            if (r == 0) ra[k] = (v && g > 0) ? sh[pos + k] : T(0);
+            if (r == 1) rb[k] = v ? sh[pos + k] : T(1);
+            if (r == 2) rc[k] = (v && g < n - 1) ? sh[pos + k] : T(0);
+            if (r == 3) rd[k] = v ? sh[pos + k] : T(0);
         }
     }
 };
@@ -405,14 +404,13 @@ struct StgConst {
     T a, b, c;
     const T *d;
     template <int M>
-    __device__ __forceinline__ void stage(T *__restrict__ sh, int, i64 o0, int nl, int n,
-                                          int ls, void *) const {
+    __device__ __forceinline__ void stage(int, T *__restrict__ sh, i64 o0, int nl, int n, int ls,
+                                          void *) const {
         stage_in<T, M>(sh, d + o0 * n, nl * n, n, ls);
     }
     template <int M>
-    __device__ __forceinline__ void rows(const T *__restrict__ sh, int, int pos, int g0, int n,
-                                         bool act, T (&ra)[M], T (&rb)[M], T (&rc)[M],
-                                         T (&rd)[M]) const {
+    __device__ __forceinline__ void take(int, const T *__restrict__ sh, int pos, int g0, int n, bool act,
+                                         T (&ra)[M], T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const int g = g0 + k;
@@ -430,24 +428,25 @@ struct StgS {
     static constexpr int kRegions = 2;
     const T *s, *d;
     template <int M>
-    __device__ __forceinline__ void stage(T *__restrict__ sh, int reg, i64 o0, int nl, int n,
-                                          int ls, void *) const {
-        stage_in<T, M>(sh, s + o0 * n, nl * n, n, ls);
-        stage_in<T, M>(sh + reg, d + o0 * n, nl * n, n, ls);
+    __device__ __forceinline__ void stage(int r, T *__restrict__ sh, i64 o0, int nl, int n, int ls,
+                                          void *) const {
+        stage_in<T, M>(sh, (r == 0 ? s : d) + o0 * n, nl * n, n, ls);
     }
     template <int M>
-    __device__ __forceinline__ void rows(const T *__restrict__ sh, int reg, int pos, int g0, int n,
-                                         bool act, T (&ra)[M], T (&rb)[M], T (&rc)[M],
-                                         T (&rd)[M]) const {
+    __device__ __forceinline__ void take(int r, const T *__restrict__ sh, int pos, int g0, int n, bool act,
+                                         T (&ra)[M], T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const int g = g0 + k;
             const bool v = act && g < n;
-            const T sv = v ? sh[pos + k] : T(0);
-            ra[k] = (g > 0) ? -sv : T(0);
-            rb[k] = T(1) + T(2) * sv;
-            rc[k] = (g < n - 1) ? -sv : T(0);
-            rd[k] = v ? sh[reg + pos + k] : T(0);
+            if (r == 0) {
+                const T sv = v ? sh[pos + k] : T(0);
+                ra[k] = (g > 0) ? -sv : T(0);
+                rb[k] = T(1) + T(2) * sv;
+                rc[k] = (g < n - 1) ? -sv : T(0);
+            } else {
+                rd[k] = v ? sh[pos + k] : T(0);
+            }
         }
     }
 };
@@ -469,22 +468,25 @@ __global__ __launch_bounds__(MAXT) void k_staged(StagedGeom gm, Src src, Out out
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sh = reinterpret_cast<T *>(smem_raw);
     const int L = gm.L, P = gm.P, n = gm.n, ls = gm.ls;
-    const int reg = L * ls;
     const int S = L * P;
-    T *red = sh + Src::kRegions * reg;  // reduced-solve scratch (6 S elements)
+    T *red = sh + L * ls;  // reduced-solve scratch (6 S elements)
     const int t = threadIdx.x, p = t % P, l = t / P;
     const i64 o0 = xcd_block_id() * L;
     const int nl = (int)((gm.nlines - o0) < (i64)L ? (gm.nlines - o0) : (i64)L);
-    src.template stage<M>(sh, reg, o0, nl, n, ls, red);
-    __syncthreads();
     const bool act = l < nl;
     const int pos = l * ls + p * (M + 1);
     T ra[M], rb[M], rc[M], rd[M];
-    src.template rows<M>(sh, reg, pos, p * M, n, act, ra, rb, rc, rd);
+#pragma unroll
+    for (int r = 0; r < Src::kRegions; ++r) {
+        if (r > 0) __syncthreads();  // every thread has taken region r - 1
+        src.template stage<M>(r, sh, o0, nl, n, ls, red);
+        __syncthreads();
+        src.template take<M>(r, sh, pos, p * M, n, act, ra, rb, rc, rd);
+    }
     T u[M];
     tile_solve<T, M>(ra, rb, rc, rd, red, S, P, p, t, 1, u);
-    // region 0 is dead once every thread has read its rows (they all passed
-    // the barriers inside tile_solve): overwrite own positions with results
+    // the staging region is dead once every thread has taken its rows (they all
+    // passed the barriers inside tile_solve): overwrite own positions with results
 #pragma unroll
     for (int k = 0; k < M; ++k) sh[pos + k] = u[k];
     __syncthreads();

@@ -32,6 +32,22 @@ __device__ __forceinline__ i64 xcd_block_id() {
     return (x < r) ? (i64)x * (q + 1) + idx : (i64)r * (q + 1) + (i64)(x - r) * q + idx;
 }
 
+// Reciprocal for the elimination pivots.  FP32: the hardware reciprocal
+// (about 1 ulp), well inside the FP32 tolerance.  FP64: the hardware estimate
+// refined by two Newton-Raphson steps r <- r + r (1 - x r), each of which
+// roughly squares the relative error, giving a result within an ulp or two.
+// Pivots of the diagonally dominant systems solved here are far from zero,
+// infinity and the denormal range, so the scaling steps of a full IEEE divide
+// are not needed.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
 // Result of the per-tile sweep (eq. (7)).
 //   first row: fa*l_{p-1} + fb*f_p + fc*l_p = fd   (f_p, l_p: tile's first/last unknown)
 //   last row:  la*f_p + l_p + lc*f_{p+1} = ld
@@ -49,13 +65,13 @@ template <typename T, int M>
 __device__ __forceinline__ void tile_eliminate(const T (&ra)[M], const T (&rb)[M], const T (&rc)[M],
                                                const T (&rd)[M], TileState<T, M> &s) {
     static_assert(M >= 3, "tiles need at least three rows");
-    const T r1 = T(1) / rb[1];
+    const T r1 = fast_rcp(rb[1]);
     s.ap[1] = ra[1] * r1;
     s.cp[1] = rc[1] * r1;
     s.dp[1] = rd[1] * r1;
 #pragma unroll
     for (int k = 2; k < M; ++k) {
-        const T r = T(1) / (rb[k] - ra[k] * s.cp[k - 1]);
+        const T r = fast_rcp(rb[k] - ra[k] * s.cp[k - 1]);
         s.ap[k] = -r * ra[k] * s.ap[k - 1];
         s.cp[k] = r * rc[k];
         s.dp[k] = r * (rd[k] - ra[k] * s.dp[k - 1]);
@@ -82,14 +98,14 @@ __device__ __forceinline__ void tile_eliminate_fn(const Rows &rows, const T (&rd
     static_assert(M >= 3, "tiles need at least three rows");
     T a, b, c;
     rows(1, a, b, c);
-    const T r1 = T(1) / b;
+    const T r1 = fast_rcp(b);
     s.ap[1] = a * r1;
     s.cp[1] = c * r1;
     s.dp[1] = rd[1] * r1;
 #pragma unroll
     for (int k = 2; k < M; ++k) {
         rows(k, a, b, c);
-        const T r = T(1) / (b - a * s.cp[k - 1]);
+        const T r = fast_rcp(b - a * s.cp[k - 1]);
         s.ap[k] = -r * a * s.ap[k - 1];
         s.cp[k] = r * c;
         s.dp[k] = r * (rd[k] - a * s.dp[k - 1]);
@@ -142,7 +158,7 @@ __device__ __forceinline__ void reduced_pcr(const TileState<T, M> &ts, T *__rest
     const T gdia = ts.fb - ts.fa * pc - ts.fc * ts.la;
     const T gsup = -ts.fc * ts.lc;
     const T grhs = ts.fd - ts.fa * pd - ts.fc * ts.ld;
-    const T rg = T(1) / gdia;
+    const T rg = fast_rcp(gdia);
     T a = gsub * rg, c = gsup * rg, d = grhs * rg;
     // 3. PCR (Alg. 2) over the P rows, double-buffered: one barrier per level
     int lev = 0;
@@ -167,7 +183,7 @@ __device__ __forceinline__ void reduced_pcr(const TileState<T, M> &ts, T *__rest
             cn = bc[q];
             dn = bd[q];
         }
-        const T r = T(1) / (T(1) - a * cm - c * an);
+        const T r = fast_rcp(T(1) - a * cm - c * an);
         const T na = -r * (a * am);
         const T nc = -r * (c * cn);
         const T nd = r * (d - a * dm - c * dn);
