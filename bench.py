@@ -268,6 +268,7 @@ def extra_varlen(trid):
 
     a32, b32, c32, d64, off = gen.varlen_batch()
     rows = int(off[-1])
+    os.environ["TRID_AUTOTUNE"] = "1"  # the first call times every tile plan on this batch
     ref = oracle.gtsv_varlen(a32, b32, c32, d64, off)
     res = {"systems": int(len(off) - 1), "rows": rows}
     ta, tb, tc, td = (torch.from_numpy(v).cuda() for v in (a32, b32, c32, d64))
@@ -327,13 +328,22 @@ def extra_gradient(trid):
         return k.grad
 
     tf = time_calls(fwd, 3, warm=1)
+    trid.timing_enable(True)
+    fwd()
+    fwd_kernels = {k: round(ms / c * 1e3, 2) for k, (c, ms) in trid.timing_read().items()}  # us per launch
+    trid.timing_enable(False)
     tb = time_calls(fwd_bwd, 3, warm=1)
+    trid.timing_enable(True)
+    fwd_bwd()
+    all_kernels = {k: [c, round(ms / c * 1e3, 2)] for k, (c, ms) in trid.timing_read().items()}
+    trid.timing_enable(False)
     u64 = tu.double()
     k64 = tk.double()
     tf64 = time_calls(lambda: autograd.adi(u64, s0 * k64, steps), 3, warm=1)
     return {"diff_adi3d_128_20steps": {"fwd_ms_f32": round(tf * 1e3, 3), "fwd_bwd_ms_f32": round(tb * 1e3, 3),
                                        "fwd_bwd_over_fwd": round(tb / tf, 3),
-                                       "fwd_ms_f64": round(tf64 * 1e3, 3)}}
+                                       "fwd_ms_f64": round(tf64 * 1e3, 3),
+                                       "fwd_kernel_us": fwd_kernels, "fwd_bwd_kernels_count_us": all_kernels}}
 
 
 def pmc_copy_calibration():

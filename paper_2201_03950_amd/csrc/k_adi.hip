@@ -41,27 +41,42 @@ struct StgRhs {
         const i64 sy = n, sz = (i64)ny * n;
         const int cnt = nl * n;
         const int nt = blockDim.x;
+        // each thread handles at most M elements (see stage_in): gather all
+        // loads first so they are in flight together
+        T uc[M], sum[M], sv[M];
         int ll = threadIdx.x / n, i = threadIdx.x % n;
         const int dl = nt / n, di = nt % n;
-        for (int e = threadIdx.x; e < cnt; e += nt) {
+        int lls[M], is[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            lls[k] = ll;
+            is[k] = i;
+            const int e = threadIdx.x + k * nt;
+            const bool v = e < cnt;
             const i64 q = off + e;
-            const T uc = u[q];
-            T sum = (i > 0 ? u[q - 1] : T(0)) + (i < n - 1 ? u[q + 1] : T(0));
-            const int f = flags[ll];
-            if (f & 1) sum += u[q - sy];
-            if (f & 2) sum += u[q + sy];
+            const int f = v ? flags[ll] : 0;
+            uc[k] = v ? u[q] : T(0);
+            T acc = (v && i > 0) ? u[q - 1] : T(0);
+            acc += (v && i < n - 1) ? u[q + 1] : T(0);
+            if (f & 1) acc += u[q - sy];
+            if (f & 2) acc += u[q + sy];
             if (NDIM == 3) {
-                if (f & 4) sum += u[q - sz];
-                if (f & 8) sum += u[q + sz];
+                if (f & 4) acc += u[q - sz];
+                if (f & 8) acc += u[q + sz];
             }
-            const T sv = PP ? s[q] : s0;
-            sh[staged_pos<M>(ll, i, ls)] = T(2) * sv * (sum - T(2 * NDIM) * uc);
+            sum[k] = acc;
+            sv[k] = PP ? (v ? s[q] : T(0)) : s0;
             ll += dl;
             i += di;
             if (i >= n) {
                 i -= n;
                 ++ll;
             }
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int e = threadIdx.x + k * nt;
+            if (e < cnt) sh[staged_pos<M>(lls[k], is[k], ls)] = T(2) * sv[k] * (sum[k] - T(2 * NDIM) * uc[k]);
         }
     }
 

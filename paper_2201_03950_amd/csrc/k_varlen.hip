@@ -37,11 +37,13 @@ struct VarlenArgs {
     int nitems;
 };
 
-// Block-local assignment of threads to (system, tile) for one work item.
-// Returns, per thread: system id (or -1), tile p, tile count P, row count n, row offset.
+// Block-local assignment of threads to (system, tile) for one work item, and
+// per-tile row ranges published in LDS for the staging passes:
+//   s_base[t]: element offset of tile t's first row, s_cnt[t]: its valid rows.
+// Returns, per thread: system id (or -1), tile p, tile count P, row count n.
 template <int M, int NT>
-__device__ __forceinline__ void varlen_assign(const VarlenArgs &g, int item, short *s_sys, short *s_p, int &sys,
-                                              int &p, int &P, int &n, i64 &base) {
+__device__ __forceinline__ void varlen_assign(const VarlenArgs &g, int item, short *s_sys, short *s_p,
+                                             i64 *s_base, int *s_cnt, int &sys, int &p, int &P, int &n) {
     const int t = threadIdx.x;
     const int ib = g.item_begin[item], ie = g.item_begin[item + 1];
     s_sys[t] = -1;
@@ -58,6 +60,7 @@ __device__ __forceinline__ void varlen_assign(const VarlenArgs &g, int item, sho
     }
     __syncthreads();
     const int j = s_sys[t];
+    i64 base = 0;
     if (j >= 0) {
         sys = g.order[ib + j];
         base = g.off[sys];
@@ -66,14 +69,42 @@ __device__ __forceinline__ void varlen_assign(const VarlenArgs &g, int item, sho
         p = s_p[t];
     } else {
         sys = -1;
-        base = 0;
         n = 0;
         P = 1;
         p = 0;
     }
+    const int cnt = n - p * M;
+    s_base[t] = base + (i64)p * M;
+    s_cnt[t] = cnt < 0 ? 0 : (cnt > M ? M : cnt);
+    __syncthreads();
 }
 
-// Last block out resets the work counters (vector atomics and stores only).
+// Coalesced copy of one packed array into the staging region: consecutive
+// lanes take consecutive (tile, row) positions, i.e. consecutive elements of
+// the same system.  Tile t's row k lands at t * (M + 1) + k.
+template <typename E, int M, int NT>
+__device__ __forceinline__ void varlen_stage_in(E *__restrict__ reg, const E *__restrict__ src,
+                                                const i64 *s_base, const int *s_cnt) {
+#pragma unroll 4
+    for (int i = 0; i < M; ++i) {
+        const int e = threadIdx.x + i * NT;
+        const int tau = e / M, k = e % M;
+        if (k < s_cnt[tau]) reg[tau * (M + 1) + k] = src[s_base[tau] + k];
+    }
+}
+
+template <typename E, int M, int NT>
+__device__ __forceinline__ void varlen_stage_out(E *__restrict__ dst, const E *__restrict__ reg,
+                                                 const i64 *s_base, const int *s_cnt) {
+#pragma unroll 4
+    for (int i = 0; i < M; ++i) {
+        const int e = threadIdx.x + i * NT;
+        const int tau = e / M, k = e % M;
+        if (k < s_cnt[tau]) dst[s_base[tau] + k] = reg[tau * (M + 1) + k];
+    }
+}
+
+// Last block out resets the work counters (vector atomics only).
 __device__ __forceinline__ void varlen_finish(int *counter) {
     if (threadIdx.x == 0) {
         __threadfence();
@@ -85,34 +116,51 @@ __device__ __forceinline__ void varlen_finish(int *counter) {
     }
 }
 
+// Dynamic LDS of the uneven-batch kernels: staging region of NT (M + 1)
+// elements of `Big` bytes, then tile ranges, then the solver scratch.
+template <int M, int NT>
+constexpr size_t varlen_lds_bytes(size_t big, size_t red_bytes) {
+    return ((size_t)NT * (M + 1) * big + 15) / 16 * 16 + (size_t)NT * (8 + 4) + red_bytes;
+}
+
 template <typename T, int M, int NT>
 __global__ __launch_bounds__(NT) void k_varlen_plain(VarlenArgs g) {
     __shared__ int s_item;
     __shared__ short s_sys[NT], s_p[NT];
-    __shared__ T red[6 * NT];
-    const T *a = static_cast<const T *>(g.a), *b = static_cast<const T *>(g.b);
-    const T *c = static_cast<const T *>(g.c), *d = static_cast<const T *>(g.d);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *reg = reinterpret_cast<T *>(smem_raw);
+    i64 *s_base = reinterpret_cast<i64 *>(smem_raw + ((size_t)NT * (M + 1) * sizeof(T) + 15) / 16 * 16);
+    int *s_cnt = reinterpret_cast<int *>(s_base + NT);
+    T *red = reinterpret_cast<T *>(s_cnt + NT);
+    const T *arr[4] = {static_cast<const T *>(g.a), static_cast<const T *>(g.b), static_cast<const T *>(g.c),
+                       static_cast<const T *>(g.d)};
     T *x = static_cast<T *>(g.x);
     const int t = threadIdx.x;
+    const int pos = t * (M + 1);
     for (;;) {
         if (t == 0) s_item = atomicAdd(&g.counter[0], 1);
         __syncthreads();
         const int item = s_item;
         if (item >= g.nitems) break;
         int sys, p, P, n;
-        i64 base;
-        varlen_assign<M, NT>(g, item, s_sys, s_p, sys, p, P, n, base);
+        varlen_assign<M, NT>(g, item, s_sys, s_p, s_base, s_cnt, sys, p, P, n);
         const bool act = sys >= 0;
         T ra[M], rb[M], rc[M], rd[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int r = p * M + k;
-            const bool v = act && r < n;
-            const i64 o = base + r;
-            ra[k] = (v && r > 0) ? a[o] : T(0);
-            rb[k] = v ? b[o] : T(1);
-            rc[k] = (v && r < n - 1) ? c[o] : T(0);
-            rd[k] = v ? d[o] : T(0);
+        for (int r = 0; r < 4; ++r) {
+            varlen_stage_in<T, M, NT>(reg, arr[r], s_base, s_cnt);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int row = p * M + k;
+                const bool v = act && row < n;
+                const T val = reg[pos + k];
+                if (r == 0) ra[k] = (v && row > 0) ? val : T(0);
+                if (r == 1) rb[k] = v ? val : T(1);
+                if (r == 2) rc[k] = (v && row < n - 1) ? val : T(0);
+                if (r == 3) rd[k] = v ? val : T(0);
+            }
+            __syncthreads();
         }
         TileState<T, M> ts;
         tile_eliminate<T, M>(ra, rb, rc, rd, ts);
@@ -121,11 +169,10 @@ __global__ __launch_bounds__(NT) void k_varlen_plain(VarlenArgs g) {
         T u[M];
         tile_backsub<T, M>(ts, f, lv, u);
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int r = p * M + k;
-            if (act && r < n) x[base + r] = u[k];
-        }
-        __syncthreads();  // s_item, s_sys and red are reused by the next item
+        for (int k = 0; k < M; ++k) reg[pos + k] = u[k];
+        __syncthreads();
+        varlen_stage_out<T, M, NT>(x, reg, s_base, s_cnt);
+        __syncthreads();  // s_item, s_sys, the staging region and red are reused by the next item
     }
     varlen_finish(g.counter);
 }
@@ -134,43 +181,56 @@ template <int M, int NT>
 __global__ __launch_bounds__(NT) void k_varlen_refine(VarlenArgs g) {
     __shared__ int s_item;
     __shared__ short s_sys[NT], s_p[NT];
-    __shared__ double xb[2 * NT];
-    __shared__ float red[6 * NT];
-    const float *a = static_cast<const float *>(g.a), *b = static_cast<const float *>(g.b);
-    const float *c = static_cast<const float *>(g.c);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *reg = reinterpret_cast<double *>(smem_raw);
+    float *regf = reinterpret_cast<float *>(smem_raw);
+    i64 *s_base = reinterpret_cast<i64 *>(smem_raw + ((size_t)NT * (M + 1) * 8 + 15) / 16 * 16);
+    int *s_cnt = reinterpret_cast<int *>(s_base + NT);
+    double *xb = reinterpret_cast<double *>(s_cnt + NT);
+    float *red = reinterpret_cast<float *>(xb + 2 * NT);
+    const float *arr[3] = {static_cast<const float *>(g.a), static_cast<const float *>(g.b),
+                           static_cast<const float *>(g.c)};
     const double *d = static_cast<const double *>(g.d);
     double *x = static_cast<double *>(g.x);
     const int t = threadIdx.x;
+    const int pos = t * (M + 1);
     for (;;) {
         if (t == 0) s_item = atomicAdd(&g.counter[0], 1);
         __syncthreads();
         const int item = s_item;
         if (item >= g.nitems) break;
         int sys, p, P, n;
-        i64 base;
-        varlen_assign<M, NT>(g, item, s_sys, s_p, sys, p, P, n, base);
+        varlen_assign<M, NT>(g, item, s_sys, s_p, s_base, s_cnt, sys, p, P, n);
         const bool act = sys >= 0;
         RefCoef<M, false> cf;
         cf.g0 = p * M;
         cf.n = act ? n : 0;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            varlen_stage_in<float, M, NT>(regf, arr[r], s_base, s_cnt);
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const bool v = act && p * M + k < n;
+                const float val = regf[pos + k];
+                if (r == 0) cf.a[k] = v ? val : 0.f;
+                if (r == 1) cf.b[k] = v ? val : 1.f;
+                if (r == 2) cf.c[k] = v ? val : 0.f;
+            }
+            __syncthreads();
+        }
+        varlen_stage_in<double, M, NT>(reg, d, s_base, s_cnt);
+        __syncthreads();
         double dd[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int r = p * M + k;
-            const bool v = act && r < n;
-            const i64 o = base + r;
-            cf.a[k] = v ? a[o] : 0.f;
-            cf.b[k] = v ? b[o] : 1.f;
-            cf.c[k] = v ? c[o] : 0.f;
-            dd[k] = v ? d[o] : 0.0;
-        }
+        for (int k = 0; k < M; ++k) dd[k] = (act && p * M + k < n) ? reg[pos + k] : 0.0;
         double out[M];
         refine_tile<M, false>(cf, dd, red, xb, NT, P, p, t, 1, out, g.item_pmax[item]);
+        // every thread read its d before refine_tile's first barrier: reuse the region
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int r = p * M + k;
-            if (act && r < n) x[base + r] = out[k];
-        }
+        for (int k = 0; k < M; ++k) reg[pos + k] = out[k];
+        __syncthreads();
+        varlen_stage_out<double, M, NT>(x, reg, s_base, s_cnt);
         __syncthreads();
     }
     varlen_finish(g.counter);
@@ -181,9 +241,10 @@ __global__ __launch_bounds__(NT) void k_varlen_refine(VarlenArgs g) {
 namespace {
 
 template <class K>
-int occupancy_blocks(K kernel, int nt) {
+int occupancy_blocks(K kernel, int nt, size_t lds) {
+    hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || per_cu < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, lds) != hipSuccess || per_cu < 1)
         per_cu = 1;
     int dev = 0, cus = 0;
     hipGetDevice(&dev);
@@ -192,8 +253,9 @@ int occupancy_blocks(K kernel, int nt) {
 }
 
 template <typename K>
-hipError_t launch_persistent(K kernel, int nt, const VarlenSchedule &sc, const VarlenArgs &g, hipStream_t s) {
-    hipLaunchKernelGGL(kernel, dim3((unsigned)sc.nblocks), dim3(nt), 0, s, g);
+hipError_t launch_persistent(K kernel, int nt, size_t lds, const VarlenSchedule &sc, const VarlenArgs &g,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(kernel, dim3((unsigned)sc.nblocks), dim3(nt), lds, s, g);
     return hipGetLastError();
 }
 
@@ -201,28 +263,36 @@ hipError_t launch_persistent(K kernel, int nt, const VarlenSchedule &sc, const V
 
 // The (M, NT) variants compiled for each precision.
 const std::vector<VarlenVariant> &varlen_variants(int prec) {
-    static const std::vector<VarlenVariant> f64 = {{16, 512}, {8, 1024}, {32, 256}};
-    static const std::vector<VarlenVariant> f32 = {{16, 512}, {32, 256}, {8, 1024}};
-    static const std::vector<VarlenVariant> ref = {{16, 512}, {32, 256}};
+    static const std::vector<VarlenVariant> f64 = {{8, 1024}, {16, 512}, {32, 256}};
+    static const std::vector<VarlenVariant> f32 = {{8, 1024}, {16, 512}, {32, 256}};
+    static const std::vector<VarlenVariant> ref = {{8, 1024}, {16, 512}, {32, 256}};
     return prec == 0 ? f64 : (prec == 1 ? f32 : ref);
 }
 
 namespace {
 
+// Calls f(kernel, threads, dynamic LDS bytes) for the compiled variant (prec, M, NT).
 template <class F>
-auto with_kernel(int prec, int M, int NT, F &&f) -> decltype(f(k_varlen_refine<16, 512>, 512)) {
+auto with_kernel(int prec, int M, int NT, F &&f) -> decltype(f(k_varlen_refine<16, 512>, 512, size_t(0))) {
     if (prec == 2) {
-        if (M == 16 && NT == 512) return f(k_varlen_refine<16, 512>, 512);
-        return f(k_varlen_refine<32, 256>, 256);
+        if (M == 8 && NT == 1024)
+            return f(k_varlen_refine<8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 1024 * (16 + 24)));
+        if (M == 16 && NT == 512)
+            return f(k_varlen_refine<16, 512>, 512, varlen_lds_bytes<16, 512>(8, 512 * (16 + 24)));
+        return f(k_varlen_refine<32, 256>, 256, varlen_lds_bytes<32, 256>(8, 256 * (16 + 24)));
     }
     if (prec == 0) {
-        if (M == 16 && NT == 512) return f(k_varlen_plain<double, 16, 512>, 512);
-        if (M == 8 && NT == 1024) return f(k_varlen_plain<double, 8, 1024>, 1024);
-        return f(k_varlen_plain<double, 32, 256>, 256);
+        if (M == 16 && NT == 512)
+            return f(k_varlen_plain<double, 16, 512>, 512, varlen_lds_bytes<16, 512>(8, 6 * 512 * 8));
+        if (M == 8 && NT == 1024)
+            return f(k_varlen_plain<double, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 6 * 1024 * 8));
+        return f(k_varlen_plain<double, 32, 256>, 256, varlen_lds_bytes<32, 256>(8, 6 * 256 * 8));
     }
-    if (M == 16 && NT == 512) return f(k_varlen_plain<float, 16, 512>, 512);
-    if (M == 8 && NT == 1024) return f(k_varlen_plain<float, 8, 1024>, 1024);
-    return f(k_varlen_plain<float, 32, 256>, 256);
+    if (M == 16 && NT == 512)
+        return f(k_varlen_plain<float, 16, 512>, 512, varlen_lds_bytes<16, 512>(4, 6 * 512 * 4));
+    if (M == 8 && NT == 1024)
+        return f(k_varlen_plain<float, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(4, 6 * 1024 * 4));
+    return f(k_varlen_plain<float, 32, 256>, 256, varlen_lds_bytes<32, 256>(4, 6 * 256 * 4));
 }
 
 }  // namespace
@@ -286,7 +356,7 @@ hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const V
     if ((e = hipMemcpy(sc->item_begin, item_begin.data(), b_ib, hipMemcpyHostToDevice)) != hipSuccess) return e;
     if ((e = hipMemcpy(sc->item_pmax, item_pmax.data(), b_ip, hipMemcpyHostToDevice)) != hipSuccess) return e;
     if ((e = hipMemset(sc->counter, 0, 2 * sizeof(int))) != hipSuccess) return e;
-    sc->nblocks = with_kernel(prec, v.M, v.NT, [&](auto k, int nt) { return occupancy_blocks(k, nt); });
+    sc->nblocks = with_kernel(prec, v.M, v.NT, [&](auto k, int nt, size_t lds) { return occupancy_blocks(k, nt, lds); });
     sc->nblocks = std::max(1, std::min(sc->nblocks, sc->nitems));
     return hipSuccess;
 }
@@ -306,7 +376,8 @@ hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b,
     g.item_pmax = sc.item_pmax;
     g.counter = sc.counter;
     g.nitems = sc.nitems;
-    return with_kernel(sc.prec, sc.M, sc.NT, [&](auto k, int nt) { return launch_persistent(k, nt, sc, g, s); });
+    return with_kernel(sc.prec, sc.M, sc.NT,
+                       [&](auto k, int nt, size_t lds) { return launch_persistent(k, nt, lds, sc, g, s); });
 }
 
 void varlen_free(VarlenSchedule *sc) {

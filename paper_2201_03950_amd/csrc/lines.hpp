@@ -329,15 +329,26 @@ __device__ __forceinline__ int staged_pos(int ll, int i, int ls) {
 }
 
 // Cooperative coalesced copy of `cnt` contiguous elements from global `src`
-// into staged positions of region `dst` (line length n).
+// into staged positions of region `dst` (line length n).  cnt <= blockDim * M
+// (a block holds at most P * M >= n rows per line and L * P threads), so each
+// thread handles at most M elements: the loop is unrolled and its loads issue
+// together.
 template <typename T, int M>
 __device__ __forceinline__ void stage_in(T *__restrict__ dst, const T *__restrict__ src, int cnt,
                                          int n, int ls) {
     const int nt = blockDim.x;
     int ll = threadIdx.x / n, i = threadIdx.x % n;
     const int dl = nt / n, di = nt % n;
-    for (int e = threadIdx.x; e < cnt; e += nt) {
-        dst[staged_pos<M>(ll, i, ls)] = src[e];
+    T v[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int e = threadIdx.x + k * nt;
+        v[k] = e < cnt ? src[e] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int e = threadIdx.x + k * nt;
+        if (e < cnt) dst[staged_pos<M>(ll, i, ls)] = v[k];
         ll += dl;
         i += di;
         if (i >= n) {
@@ -353,8 +364,10 @@ __device__ __forceinline__ void stage_out(T *__restrict__ dst, const T *__restri
     const int nt = blockDim.x;
     int ll = threadIdx.x / n, i = threadIdx.x % n;
     const int dl = nt / n, di = nt % n;
-    for (int e = threadIdx.x; e < cnt; e += nt) {
-        dst[e] = src[staged_pos<M>(ll, i, ls)];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int e = threadIdx.x + k * nt;
+        if (e < cnt) dst[e] = src[staged_pos<M>(ll, i, ls)];
         ll += dl;
         i += di;
         if (i >= n) {
