@@ -177,15 +177,20 @@ struct CStgCopy {
         constexpr int n = N;
         const int nc = nl * n / V, nt = blockDim.x;
         const VT *src = reinterpret_cast<const VT *>(d + o0 * n);
+        VT v[M / V];
+#pragma unroll
+        for (int k = 0; k < M / V; ++k) {
+            const int ch = threadIdx.x + k * nt;
+            v[k] = load_if(src, ch, ch < nc, nc - 1);
+        }
 #pragma unroll
         for (int k = 0; k < M / V; ++k) {
             const int ch = threadIdx.x + k * nt;
             if (ch < nc) {
-                const VT v = src[ch];
                 const int e = ch * V, ll = e / n, i = e - ll * n;
                 T *dst = sh + ll * g.ls + (i / M) * (M + 1) + (i % M);
 #pragma unroll
-                for (int j = 0; j < V; ++j) dst[j] = vget<T>(v, j);
+                for (int j = 0; j < V; ++j) dst[j] = vget<T>(v[k], j);
             }
         }
     }
@@ -234,33 +239,39 @@ struct CStgRhs {
             k = (k + 1 == nz) ? 0 : k + 1;
         }
         const int sz = ny * N;
-        const T *q0 = u + (o0 + lfirst) * N + c * V;  // this thread's column, first line
-        // sliding window over lines lfirst-1 .. lfirst+LG (y neighbours)
-        VT prev = VT{}, cur = VT{}, next = VT{};
-        if (lfirst < nl) {
-            cur = *reinterpret_cast<const VT *>(q0);
-            if (j > 0) prev = *reinterpret_cast<const VT *>(q0 - N);
-        }
+        const T *qb = u + o0 * N + c * V;  // this thread's column of the block's first line
+        const T *q0 = qb + lfirst * N;
+        const int last = (nl - 1) * N;     // offset of the block's last line: in bounds for every lane
+        const bool live0 = lfirst < nl;
+        // sliding window over lines lfirst-1 .. lfirst+LG (y neighbours); every
+        // load below is branch-free (idle lanes read the last line) so they issue together
+        VT cur = load_if(reinterpret_cast<const VT *>(qb), lfirst * N / V, live0, last / V);
+        VT prev = load_if(reinterpret_cast<const VT *>(qb), (lfirst - 1) * N / V, live0 && j > 0, last / V);
 #pragma unroll
         for (int r = 0; r < LG; ++r) {
             const int ll = lfirst + r;
             const bool live = ll < nl;
-            const T *q = q0 + r * N;
+            const int qo = (ll * N) / V;  // vector offset of this line from qb
             const bool has_next = j < ny - 1;
-            next = (live && has_next) ? *reinterpret_cast<const VT *>(q + N) : VT{};
-            VT acc = (has_next ? next : VT{}) + (j > 0 ? prev : VT{});
+            // the next line (y+1 neighbour, or the next plane's first line)
+            const bool nxt_in = live && (ll + 1 < nl || o0 + nl < g.nlines);
+            const VT nxt = load_if(reinterpret_cast<const VT *>(qb), qo + N / V, nxt_in, last / V);
+            VT acc = (has_next ? nxt : VT{}) + (j > 0 ? prev : VT{});
             if (NDIM == 3) {
-                if (live && k > 0) acc += *reinterpret_cast<const VT *>(q - sz);
-                if (live && k < nz - 1) acc += *reinterpret_cast<const VT *>(q + sz);
+                acc += load_if(reinterpret_cast<const VT *>(q0), r * N / V - sz / V, live && k > 0, (last - lfirst * N) / V);
+                acc += load_if(reinterpret_cast<const VT *>(q0), r * N / V + sz / V, live && k < nz - 1, (last - lfirst * N) / V);
             }
             // x neighbours of the vector's first and last element
             T left = wave_from_lower_lane<T>(vget<T>(cur, V - 1));
             T right = wave_from_upper_lane<T>(vget<T>(cur, 0));
-            if (lane == 0) left = (live && c > 0) ? q[-1] : T(0);
-            if (lane == 63) right = (live && c < C - 1) ? q[V] : T(0);
+            const T el = load_if(qb, ll * N - 1, live && lane == 0 && c > 0, last);
+            const T er = load_if(qb, ll * N + V, live && lane == 63 && c < C - 1, last);
+            if (lane == 0) left = el;
+            if (lane == 63) right = er;
             if (c == 0) left = T(0);
             if (c == C - 1) right = T(0);
-            if (live) {
+            {  // ll < L always (the thread groups tile the block's L lines): rows
+               // past nl are written but never read, so the store needs no branch
                 T *dst = sh + ll * g.ls + ((c * V) / M) * (M + 1) + ((c * V) % M);
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
@@ -270,12 +281,11 @@ struct CStgRhs {
                 }
             }
             prev = cur;
-            cur = next;
+            cur = nxt;
             if (++j == ny) {  // next line starts a new plane: its y-1 neighbour is outside
                 j = 0;
                 k = (k + 1 == nz) ? 0 : k + 1;
                 prev = VT{};
-                if (r + 1 < LG && ll + 1 < nl) cur = *reinterpret_cast<const VT *>(q + N);
             }
         }
     }

@@ -3,6 +3,12 @@
 // d = 2 s L u is formed while staging the block's x lines into LDS, the rows
 // (-s, 1 + 2 s, -s) are generated in-kernel (Section IV-A: coefficient
 // generation fused into the solver), and only d is written.
+//
+// The block's L x lines are consecutive lines of the mesh, so their y
+// neighbours are the lines themselves plus one line on each side: the window
+// of lines o0 - 1 .. o0 + L is copied into LDS with 16-byte loads, and the x
+// and y neighbours of every point are read from there.  Only the two z
+// neighbours (3D) and s come from global memory, once per point each.
 #include <algorithm>
 
 #include "dispatch.hpp"
@@ -10,62 +16,84 @@
 
 namespace trid {
 
-// Staged source of the fused RHS (per-point s or constant s0).  Region 0 is
-// d = 2 s L u computed while staging (7-point stencil in 3D, 5-point in 2D,
-// zero outside the mesh); region 1 (per-point s only) is s itself.
-template <typename T, bool PP, int NDIM>
-struct StgRhs {
-    static constexpr int kRegions = PP ? 2 : 1;
-    const T *u;
-    const T *s;
-    T s0;
+struct RhsGeom {
+    i64 nlines;  // x lines of all meshes = ny * nz * batch
+    int n;       // x line length
+    int L, P, ls;
     int ny, nz;  // lines of one mesh = ny * nz (nz = 1 in 2D)
+    int uoff;    // LDS element offset of the u window (later: staged s)
+    int roff;    // LDS element offset of the reduced-solve scratch (first: line flags)
+};
 
-    template <int M>
-    __device__ __forceinline__ void stage(int r, T *__restrict__ sh, i64 o0, int nl, int n, int ls,
-                                          void *scratch) const {
-        if (r == 1) {
-            stage_in<T, M>(sh, s + o0 * n, nl * n, n, ls);
-            return;
+// Contiguous copy of cnt elements global -> LDS by the whole block, 16-byte
+// vectors when both sides are aligned.  The first K * blockDim vectors go in
+// one unrolled batch (all loads issued before the first LDS store); any rest
+// follows in a plain loop.
+template <typename T, int K>
+__device__ __forceinline__ void copy_to_lds(T *__restrict__ dst, const T *__restrict__ src, int cnt) {
+    constexpr int V = 16 / sizeof(T);
+    using VT = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
+    const int nt = blockDim.x, t = threadIdx.x;
+    const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
+    int done = 0;
+    if (vec) {
+        const int nv = cnt / V;
+        const VT *s4 = reinterpret_cast<const VT *>(src);
+        VT *d4 = reinterpret_cast<VT *>(dst);
+        if (nv > 0) {
+            VT v[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = load_if(s4, t + k * nt, t + k * nt < nv, nv - 1);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (t + k * nt < nv) d4[t + k * nt] = v[k];
         }
-        // neighbour-existence flags of the block's lines: bit0 y-1, bit1 y+1, bit2 z-1, bit3 z+1
-        int *flags = static_cast<int *>(scratch);
-        for (int ll = threadIdx.x; ll < nl; ll += blockDim.x) {
-            const i64 o = o0 + ll;
-            const int j = (int)(o % ny);
-            const int k = (int)((o / ny) % nz);
-            flags[ll] = (j > 0 ? 1 : 0) | (j < ny - 1 ? 2 : 0) | (k > 0 ? 4 : 0) | (k < nz - 1 ? 8 : 0);
-        }
-        __syncthreads();
-        const i64 off = o0 * n;
-        const i64 sy = n, sz = (i64)ny * n;
-        const int cnt = nl * n;
-        const int nt = blockDim.x;
-        // each thread handles at most M elements (see stage_in): gather all
-        // loads first so they are in flight together
-        T uc[M], sum[M], sv[M];
-        int ll = threadIdx.x / n, i = threadIdx.x % n;
+        for (int e = K * nt + t; e < nv; e += nt) d4[e] = s4[e];
+        done = nv * V;
+    }
+    for (int e = done + t; e < cnt; e += nt) dst[e] = src[e];
+}
+
+template <typename T, int M, bool PP, int NDIM>
+__global__ __launch_bounds__(256) void k_rhs_x(RhsGeom g, const T *__restrict__ u, const T *__restrict__ s,
+                                               T s0, T *__restrict__ x) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sh = reinterpret_cast<T *>(smem_raw);  // staged RHS, then the solution
+    T *uw = sh + g.uoff;                      // u window, then staged s
+    T *red = sh + g.roff;
+    int *flags = reinterpret_cast<int *>(red);
+    const int L = g.L, P = g.P, n = g.n, ls = g.ls;
+    const int t = threadIdx.x, nt = blockDim.x, p = t % P, l = t / P;
+    const i64 o0 = xcd_block_id() * L;
+    const int nl = (int)((g.nlines - o0) < (i64)L ? (g.nlines - o0) : (i64)L);
+    const bool act = l < nl;
+    const int pos = l * ls + p * (M + 1);
+
+    const i64 off = o0 * n;
+    const i64 sz = (i64)g.ny * n;
+    const i64 total = g.nlines * n;
+    const int cnt = nl * n;
+    // z neighbours and s of the thread's points go out first (they need no
+    // LDS): a z neighbour is loaded whenever it is inside the array and masked
+    // by the line flags below, so every load of the block is in flight at once
+    T zl[M], zr[M], sv[M];
+    int lls[M], is[M];
+    {
+        int ll = t / n, i = t % n;
         const int dl = nt / n, di = nt % n;
-        int lls[M], is[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             lls[k] = ll;
             is[k] = i;
-            const int e = threadIdx.x + k * nt;
+            const int e = t + k * nt;
             const bool v = e < cnt;
             const i64 q = off + e;
-            const int f = v ? flags[ll] : 0;
-            uc[k] = v ? u[q] : T(0);
-            T acc = (v && i > 0) ? u[q - 1] : T(0);
-            acc += (v && i < n - 1) ? u[q + 1] : T(0);
-            if (f & 1) acc += u[q - sy];
-            if (f & 2) acc += u[q + sy];
+            const i64 qs = off + (v ? e : cnt - 1);  // in-bounds stand-in for idle lanes
             if (NDIM == 3) {
-                if (f & 4) acc += u[q - sz];
-                if (f & 8) acc += u[q + sz];
+                zl[k] = load_if(u, q - sz, v && q >= sz, qs);
+                zr[k] = load_if(u, q + sz, v && q + sz < total, qs);
             }
-            sum[k] = acc;
-            sv[k] = PP ? (v ? s[q] : T(0)) : s0;
+            if (PP) sv[k] = load_if(s, q, v, qs);
             ll += dl;
             i += di;
             if (i >= n) {
@@ -73,58 +101,121 @@ struct StgRhs {
                 ++ll;
             }
         }
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int e = threadIdx.x + k * nt;
-            if (e < cnt) sh[staged_pos<M>(lls[k], is[k], ls)] = T(2) * sv[k] * (sum[k] - T(2 * NDIM) * uc[k]);
-        }
     }
+    // window row r holds line o0 - 1 + r; rows outside the line range stay unread
+    // (a line's y-1 / y+1 neighbour exists only inside its own plane)
+    {
+        const i64 w0 = o0 > 0 ? o0 - 1 : 0;
+        const i64 w1 = (o0 + nl + 1) < g.nlines ? (o0 + nl + 1) : g.nlines;
+        copy_to_lds<T, (2 * M * sizeof(T) + 15) / 16 + 1>(uw + (w0 - (o0 - 1)) * n, u + w0 * n, (int)(w1 - w0) * n);
+    }
+    // neighbour-existence flags of the block's lines: bit0 y-1, bit1 y+1, bit2 z-1, bit3 z+1
+    for (int ll = t; ll < nl; ll += nt) {
+        const i64 o = o0 + ll;
+        const int j = (int)(o % g.ny);
+        const int k = (int)((o / g.ny) % g.nz);
+        flags[ll] = (j > 0 ? 1 : 0) | (j < g.ny - 1 ? 2 : 0) | (k > 0 ? 4 : 0) | (k < g.nz - 1 ? 8 : 0);
+    }
+    __syncthreads();
 
-    template <int M>
-    __device__ __forceinline__ void take(int r, const T *__restrict__ sh, int pos, int g0, int n, bool act,
-                                         T (&ra)[M], T (&rb)[M], T (&rc)[M], T (&rd)[M]) const {
+    // RHS of every point: x, y neighbours from the window
+    T dv[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int g = g0 + k;
-            const bool v = act && g < n;
-            if (r == 0) {
-                rd[k] = v ? sh[pos + k] : T(0);
-                if (!PP) {
-                    const T sv = v ? s0 : T(0);
-                    ra[k] = (g > 0) ? -sv : T(0);
-                    rb[k] = T(1) + T(2) * sv;
-                    rc[k] = (g < n - 1) ? -sv : T(0);
-                }
-            } else {
-                const T sv = v ? sh[pos + k] : T(0);
-                ra[k] = (g > 0) ? -sv : T(0);
-                rb[k] = T(1) + T(2) * sv;
-                rc[k] = (g < n - 1) ? -sv : T(0);
-            }
+    for (int k = 0; k < M; ++k) {
+        const int ll = lls[k], i = is[k];
+        const bool v = t + k * nt < cnt;
+        const int f = v ? flags[ll] : 0;
+        const T *ur = uw + (ll + 1) * n + i;
+        const T c = v ? ur[0] : T(0);
+        T acc = T(0);
+        if (NDIM == 3) {
+            acc += (f & 4) ? zl[k] : T(0);
+            acc += (f & 8) ? zr[k] : T(0);
+        }
+        acc += (v && i > 0) ? ur[-1] : T(0);
+        acc += (v && i < n - 1) ? ur[1] : T(0);
+        if (f & 1) acc += ur[-n];
+        if (f & 2) acc += ur[n];
+        const T sk = PP ? sv[k] : s0;
+        dv[k] = T(2) * sk * (acc - T(2 * NDIM) * c);
+    }
+    __syncthreads();  // every window read is done: the window becomes the s region
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        if (t + k * nt < cnt) {
+            const int q = staged_pos<M>(lls[k], is[k], ls);
+            sh[q] = dv[k];
+            if (PP) uw[q] = sv[k];
         }
     }
-};
+    __syncthreads();
+    T ra[M], rb[M], rc[M], rd[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int gi = p * M + k;
+        const bool v = act && gi < n;
+        rd[k] = v ? sh[pos + k] : T(0);
+        const T sk = v ? (PP ? uw[pos + k] : s0) : T(0);
+        ra[k] = (gi > 0) ? -sk : T(0);
+        rb[k] = T(1) + T(2) * sk;
+        rc[k] = (gi < n - 1) ? -sk : T(0);
+    }
+    T uu[M];
+    tile_solve<T, M>(ra, rb, rc, rd, red, L * P, P, p, t, 1, uu);
+    // each thread overwrites only the positions it took (all passed the
+    // barriers inside tile_solve)
+#pragma unroll
+    for (int k = 0; k < M; ++k) sh[pos + k] = uu[k];
+    __syncthreads();
+    stage_out<T, M>(x + off, sh, cnt, n, ls);
+}
 
 namespace {
 
 constexpr int kMaxThreads = 256;
-constexpr size_t kMaxShmem = 64 * 1024;
+constexpr size_t kMaxShmem = 160 * 1024;
 
 i64 cdiv(i64 a, i64 b) { return (a + b - 1) / b; }
 
+// LDS layout (elements): [staged RHS L*ls][u window (L+2)*n, >= L*ls with
+// per-point s][reduced scratch 6*L*P, >= L ints of flags], regions 16-byte aligned.
+size_t rhs_layout(int L, int P, int ls, int n, bool pp, int w, int *uoff, int *roff) {
+    const int q = 16 / w;
+    auto up = [&](i64 v) { return (v + q - 1) / q * q; };
+    i64 win = (i64)(L + 2) * n;
+    if (pp) win = std::max(win, (i64)L * ls);
+    const i64 u0 = up((i64)L * ls);
+    const i64 r0 = up(u0 + win);
+    const i64 red = std::max((i64)6 * L * P, cdiv((i64)L * 4, w));
+    if (uoff) *uoff = (int)u0;
+    if (roff) *roff = (int)r0;
+    return (size_t)(r0 + red) * w;
+}
+
 template <typename T, int M, bool PP, int NDIM>
 hipError_t go(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
-    StagedGeom g;
+    RhsGeom g;
     g.nlines = r.ny * r.nz * r.batch;
     g.n = (int)r.nx;
     g.L = pl.L;
     g.P = pl.P;
     g.ls = pl.ls;
-    StgRhs<T, PP, NDIM> src{static_cast<const T *>(r.u), static_cast<const T *>(r.s), (T)r.s0,
-                            (int)r.ny, (int)r.nz};
-    StgOut<T> out{static_cast<T *>(r.d)};
-    hipLaunchKernelGGL((k_staged<T, M, kMaxThreads, StgRhs<T, PP, NDIM>, StgOut<T>>),
-                       dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g, src, out);
+    g.ny = (int)r.ny;
+    g.nz = (int)r.nz;
+    rhs_layout(pl.L, pl.P, pl.ls, g.n, PP, (int)sizeof(T), &g.uoff, &g.roff);
+    auto kern = k_rhs_x<T, M, PP, NDIM>;
+    if (pl.shmem > 64 * 1024) {
+        static bool raised = false;  // one attribute call per instantiation
+        if (!raised) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)kMaxShmem);
+            if (e != hipSuccess) return e;
+            raised = true;
+        }
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g,
+                       static_cast<const T *>(r.u), static_cast<const T *>(r.s), (T)r.s0,
+                       static_cast<T *>(r.d));
     return hipGetLastError();
 }
 
@@ -161,10 +252,8 @@ bool plan_rhs_x(const AdiReq &r, LinePlan *pl, std::string *err) {
     }
     const int ls = (int)P * (M + 1);
     int L = r.force_L ? r.force_L : std::max(1, kMaxThreads / (int)P);
-    auto bytes = [&](int LL) {
-        // one staging region + reduced-solve scratch (which also holds L ints of flags)
-        return (size_t)LL * ls * w + std::max((size_t)6 * LL * P * w, (size_t)LL * 4);
-    };
+    const bool pp = r.s != nullptr;
+    auto bytes = [&](int LL) { return rhs_layout(LL, (int)P, ls, (int)r.nx, pp, w, nullptr, nullptr); };
     while (bytes(L) > kMaxShmem && L > 1) L /= 2;
     if (bytes(L) > kMaxShmem || (i64)L * P > kMaxThreads) {
         *err = "fused stencil + x solve does not fit in LDS";

@@ -48,6 +48,16 @@ __device__ __forceinline__ double fast_rcp(double x) {
     return __builtin_fma(r, e, r);
 }
 
+// Guarded load without a branch: every lane loads (a lane with !ok from the
+// in-bounds index `safe`) and the value is selected afterwards.  A load inside
+// a divergent branch makes the compiler wait for it where the branches join,
+// which serialises a thread's loads; in this form they stay in flight together.
+template <typename U, typename I>
+__device__ __forceinline__ U load_if(const U *p, I i, bool ok, I safe) {
+    const U v = p[ok ? i : safe];
+    return ok ? v : U{};
+}
+
 // Result of the per-tile sweep (eq. (7)).
 //   first row: fa*l_{p-1} + fb*f_p + fc*l_p = fd   (f_p, l_p: tile's first/last unknown)
 //   last row:  la*f_p + l_p + lc*f_{p+1} = ld
