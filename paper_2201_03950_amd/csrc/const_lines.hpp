@@ -243,35 +243,62 @@ struct CStgRhs {
         const T *q0 = qb + lfirst * N;
         const int last = (nl - 1) * N;     // offset of the block's last line: in bounds for every lane
         const bool live0 = lfirst < nl;
-        // sliding window over lines lfirst-1 .. lfirst+LG (y neighbours); every
-        // load below is branch-free (idle lanes read the last line) so they issue together
-        VT cur = load_if(reinterpret_cast<const VT *>(qb), lfirst * N / V, live0, last / V);
-        VT prev = load_if(reinterpret_cast<const VT *>(qb), (lfirst - 1) * N / V, live0 && j > 0, last / V);
+        // neighbour existence of the thread's lines (no loads involved)
+        bool jp[LG], jn[LG], kp[LG], kn[LG];
+        {
+            int jj = j, kk = k;
 #pragma unroll
-        for (int r = 0; r < LG; ++r) {
-            const int ll = lfirst + r;
-            const bool live = ll < nl;
-            const int qo = (ll * N) / V;  // vector offset of this line from qb
-            const bool has_next = j < ny - 1;
-            // the next line (y+1 neighbour, or the next plane's first line)
-            const bool nxt_in = live && (ll + 1 < nl || o0 + nl < g.nlines);
-            const VT nxt = load_if(reinterpret_cast<const VT *>(qb), qo + N / V, nxt_in, last / V);
-            VT acc = (has_next ? nxt : VT{}) + (j > 0 ? prev : VT{});
-            if (NDIM == 3) {
-                acc += load_if(reinterpret_cast<const VT *>(q0), r * N / V - sz / V, live && k > 0, (last - lfirst * N) / V);
-                acc += load_if(reinterpret_cast<const VT *>(q0), r * N / V + sz / V, live && k < nz - 1, (last - lfirst * N) / V);
+            for (int r = 0; r < LG; ++r) {
+                jp[r] = jj > 0;
+                jn[r] = jj < ny - 1;
+                kp[r] = kk > 0;
+                kn[r] = kk < nz - 1;
+                if (++jj == ny) {  // the next line starts a new plane
+                    jj = 0;
+                    kk = (kk + 1 == nz) ? 0 : kk + 1;
+                }
             }
-            // x neighbours of the vector's first and last element
-            T left = wave_from_lower_lane<T>(vget<T>(cur, V - 1));
-            T right = wave_from_upper_lane<T>(vget<T>(cur, 0));
-            const T el = load_if(qb, ll * N - 1, live && lane == 0 && c > 0, last);
-            const T er = load_if(qb, ll * N + V, live && lane == 63 && c < C - 1, last);
-            if (lane == 0) left = el;
-            if (lane == 63) right = er;
-            if (c == 0) left = T(0);
-            if (c == C - 1) right = T(0);
-            {  // ll < L always (the thread groups tile the block's L lines): rows
-               // past nl are written but never read, so the store needs no branch
+        }
+        // sliding window over lines lfirst-1 .. lfirst+LG (y neighbours).  The
+        // rows go in chunks of CH: all loads of a chunk are issued (branch-free:
+        // idle lanes read the block's last line) before any of its arithmetic.
+        const VT *vb = reinterpret_cast<const VT *>(qb);
+        VT cur = load_if(vb, lfirst * N / V, live0, last / V);
+        VT prev = load_if(vb, (lfirst - 1) * N / V, live0 && jp[0], last / V);
+        constexpr int CH = LG < 4 ? LG : 4;
+#pragma unroll
+        for (int c0 = 0; c0 < LG; c0 += CH) {
+            VT nx[CH], zm[CH], zp[CH];
+            T el[CH], er[CH];
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int ll = lfirst + c0 + i;
+                const bool live = ll < nl;
+                const int qo = (ll * N) / V;  // vector offset of this line from qb
+                // the next line (y+1 neighbour, or the next plane's first line)
+                nx[i] = load_if(vb, qo + N / V, live && (ll + 1 < nl || o0 + nl < g.nlines), last / V);
+                if (NDIM == 3) {
+                    zm[i] = load_if(vb, qo - sz / V, live && kp[c0 + i], last / V);
+                    zp[i] = load_if(vb, qo + sz / V, live && kn[c0 + i], last / V);
+                }
+                el[i] = load_if(qb, ll * N - 1, live && lane == 0 && c > 0, last);
+                er[i] = load_if(qb, ll * N + V, live && lane == 63 && c < C - 1, last);
+            }
+            asm volatile("" ::: "memory");  // the chunk's loads stay above its arithmetic
+#pragma unroll
+            for (int i = 0; i < CH; ++i) {
+                const int r = c0 + i, ll = lfirst + r;
+                VT acc = (jn[r] ? nx[i] : VT{}) + (jp[r] ? prev : VT{});
+                if (NDIM == 3) acc += zm[i] + zp[i];
+                // x neighbours of the vector's first and last element
+                T left = wave_from_lower_lane<T>(vget<T>(cur, V - 1));
+                T right = wave_from_upper_lane<T>(vget<T>(cur, 0));
+                if (lane == 0) left = el[i];
+                if (lane == 63) right = er[i];
+                if (c == 0) left = T(0);
+                if (c == C - 1) right = T(0);
+                // ll < L always (the thread groups tile the block's L lines): rows
+                // past nl are written but never read, so the store needs no branch
                 T *dst = sh + ll * g.ls + ((c * V) / M) * (M + 1) + ((c * V) % M);
 #pragma unroll
                 for (int e = 0; e < V; ++e) {
@@ -279,13 +306,8 @@ struct CStgRhs {
                     const T xr = e == V - 1 ? right : vget<T>(cur, e + 1);
                     dst[e] = s2 * (vget<T>(acc, e) + xl + xr - T(2 * NDIM) * vget<T>(cur, e));
                 }
-            }
-            prev = cur;
-            cur = nxt;
-            if (++j == ny) {  // next line starts a new plane: its y-1 neighbour is outside
-                j = 0;
-                k = (k + 1 == nz) ? 0 : k + 1;
-                prev = VT{};
+                prev = cur;
+                cur = nx[i];
             }
         }
     }
@@ -358,7 +380,10 @@ __global__ __launch_bounds__(256) void k_staged_dpp(ConstStagedGeom g, PcrTab<T>
     const int pos = l * g.ls + p * (M + 1);
     T x[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) x[k] = act ? sh[pos + k] : T(0);
+    for (int k = 0; k < M; ++k) {
+        const T val = sh[pos + k];  // own tile slot: always inside the region
+        x[k] = act ? val : T(0);
+    }
     T fd, ld;
     const_tile_sweep<T, M>(tb, x, fd, ld);
     T ldp = row_from_lower<1>(ld);

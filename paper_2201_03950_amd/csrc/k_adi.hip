@@ -154,8 +154,10 @@ __global__ __launch_bounds__(256) void k_rhs_x(RhsGeom g, const T *__restrict__ 
     for (int k = 0; k < M; ++k) {
         const int gi = p * M + k;
         const bool v = act && gi < n;
-        rd[k] = v ? sh[pos + k] : T(0);
-        const T sk = v ? (PP ? uw[pos + k] : s0) : T(0);
+        const T dk = sh[pos + k];  // own tile slots: always inside the regions
+        const T sl = PP ? uw[pos + k] : s0;
+        rd[k] = v ? dk : T(0);
+        const T sk = v ? sl : T(0);
         ra[k] = (gi > 0) ? -sk : T(0);
         rb[k] = T(1) + T(2) * sk;
         rc[k] = (gi < n - 1) ? -sk : T(0);

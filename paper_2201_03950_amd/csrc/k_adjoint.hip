@@ -3,9 +3,12 @@
 // zero values outside the mesh.  Given rbar = dLoss/dd:
 //   sbar += 2 rbar (L u)
 //   ubar += 2 L (s rbar)        (L is symmetric)
-// One thread per mesh point; neighbours are read through the caches.  The
-// transposed line solves of the step's reverse pass are the adjoint epilogues of
-// the line-solve kernels (lines.hpp).
+// One thread per mesh point, one block per chunk of an x line (so the line's
+// y/z position is one scalar division per block); neighbours are read through
+// the caches with branch-free loads.  The transposed line solves of the step's
+// reverse pass are the adjoint epilogues of the line-solve kernels (lines.hpp).
+#include <algorithm>
+
 #include "dispatch.hpp"
 #include "tile.hpp"
 
@@ -14,42 +17,54 @@ namespace trid {
 template <typename T, int NDIM>
 __global__ __launch_bounds__(256) void k_stencil_adjoint(const T *__restrict__ u, const T *__restrict__ s,
                                                          const T *__restrict__ rbar, T *__restrict__ ubar,
-                                                         T *__restrict__ sbar, int nx, int ny, int nz, i64 total) {
-    const i64 q = (i64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= total) return;
-    const i64 line = q / nx;
-    const int i = (int)(q - line * nx);
+                                                         T *__restrict__ sbar, int nx, int ny, int nz, int cpl) {
+    const i64 b = blockIdx.x;
+    const i64 line = b / cpl;  // uniform: scalar unit
+    const int i = (int)(b - line * cpl) * (int)blockDim.x + (int)threadIdx.x;
     const int j = (int)(line % ny);
     const int k = (int)((line / ny) % nz);
+    const bool v = i < nx;
+    const i64 q = line * nx + (v ? i : nx - 1);  // idle lanes stand in for the line's last point
     const i64 sy = nx, sz = (i64)nx * ny;
-    const T sr = s[q] * rbar[q];
-    T lu = -T(2 * NDIM) * u[q];
-    T lw = -T(2 * NDIM) * sr;
-    auto nb = [&](i64 o) {
-        lu += u[o];
-        lw += s[o] * rbar[o];
-    };
-    if (i > 0) nb(q - 1);
-    if (i < nx - 1) nb(q + 1);
-    if (j > 0) nb(q - sy);
-    if (j < ny - 1) nb(q + sy);
-    if (NDIM == 3) {
-        if (k > 0) nb(q - sz);
-        if (k < nz - 1) nb(q + sz);
+    const T uq = u[q], rq = rbar[q];
+    const T wq = s[q] * rq;
+    // neighbours (zero outside the mesh), all loads issued before any use
+    const bool ok[6] = {v && i > 0, v && i < nx - 1, j > 0, j < ny - 1, NDIM == 3 && k > 0,
+                        NDIM == 3 && k < nz - 1};
+    const i64 off[6] = {-1, 1, -sy, sy, -sz, sz};
+    T un[6], sn[6], rn[6];
+#pragma unroll
+    for (int m = 0; m < (NDIM == 3 ? 6 : 4); ++m) {
+        un[m] = load_if(u, q + off[m], ok[m], q);
+        sn[m] = load_if(s, q + off[m], ok[m], q);
+        rn[m] = load_if(rbar, q + off[m], ok[m], q);
     }
-    sbar[q] += T(2) * rbar[q] * lu;
-    ubar[q] += T(2) * lw;
+    const T sb = sbar[q], ub = ubar[q];
+    T lu = -T(2 * NDIM) * uq;
+    T lw = -T(2 * NDIM) * wq;
+#pragma unroll
+    for (int m = 0; m < (NDIM == 3 ? 6 : 4); ++m) {
+        lu += un[m];
+        lw += sn[m] * rn[m];
+    }
+    if (v) {
+        sbar[q] = sb + T(2) * rq * lu;
+        ubar[q] = ub + T(2) * lw;
+    }
 }
 
 namespace {
 
 template <typename T, int NDIM>
 hipError_t go(const StencilAdjReq &r, hipStream_t st) {
-    const i64 total = r.nx * r.ny * r.nz * r.batch;
-    const unsigned nb = (unsigned)((total + 255) / 256);
-    hipLaunchKernelGGL((k_stencil_adjoint<T, NDIM>), dim3(nb), dim3(256), 0, st, static_cast<const T *>(r.u),
-                       static_cast<const T *>(r.s), static_cast<const T *>(r.rbar), static_cast<T *>(r.ubar),
-                       static_cast<T *>(r.sbar), (int)r.nx, (int)r.ny, (int)r.nz, total);
+    const i64 lines = r.ny * r.nz * r.batch;
+    const int bd = (int)std::min<i64>(256, (r.nx + 63) / 64 * 64);
+    const int cpl = (int)((r.nx + bd - 1) / bd);
+    const i64 nb = lines * cpl;
+    if (nb >= ((i64)1 << 31)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_stencil_adjoint<T, NDIM>), dim3((unsigned)nb), dim3(bd), 0, st,
+                       static_cast<const T *>(r.u), static_cast<const T *>(r.s), static_cast<const T *>(r.rbar),
+                       static_cast<T *>(r.ubar), static_cast<T *>(r.sbar), (int)r.nx, (int)r.ny, (int)r.nz, cpl);
     return hipGetLastError();
 }
 

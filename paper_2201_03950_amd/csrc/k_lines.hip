@@ -15,9 +15,12 @@ constexpr int kStagedMaxThreads = 256;
 
 // Largest strided block for a tile of M rows of w-byte words: a thread keeps
 // about 3M words of tile state plus its raw rows in VGPRs, so bigger tiles get
-// fewer threads per block (and more VGPRs per thread) to avoid spills.
-constexpr int strided_max_threads(int M, int w) {
-    return M * w <= 64 ? 1024 : (M * w <= 128 ? 512 : 256);
+// fewer threads per block (and more VGPRs per thread) to avoid spills.  Wide
+// epilogues (the update and the adjoints) keep more words per row in flight,
+// so they drop one step earlier.
+constexpr int strided_max_threads(int M, int w, bool wide = false) {
+    const int b = wide ? 2 * M * w : M * w;
+    return b <= 64 ? 1024 : (b <= 128 ? 512 : 256);
 }
 constexpr size_t kMaxShmem = 64 * 1024;
 
@@ -54,12 +57,13 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
         *err = "tile size must be 8, 16 or 32";
         return false;
     }
+    const bool wide = r.out != Out::Store;
     i64 P = cdiv(r.n, M);
-    while (!r.force_M && P > strided_max_threads(M, w) / 2 && M < 32) {
+    while (!r.force_M && P > strided_max_threads(M, w, wide) / 2 && M < 32) {
         M *= 2;
         P = cdiv(r.n, M);
     }
-    const int maxt = strided_max_threads(M, w);
+    const int maxt = strided_max_threads(M, w, wide);
     if (P > maxt) {
         *err = "line too long for one workgroup";
         return false;
@@ -115,7 +119,7 @@ hipError_t go_strided(const LineReq &r, const LinePlan &pl, Src src, Epi epi, hi
     g.n = (int)r.n;
     g.L = pl.L;
     g.P = pl.P;
-    constexpr int MAXT = strided_max_threads(M, (int)sizeof(T));
+    constexpr int MAXT = strided_max_threads(M, (int)sizeof(T), Epi::kWide);
     hipLaunchKernelGGL((k_strided<T, M, MAXT, Src, Epi>), dim3((unsigned)pl.nblocks),
                        dim3(pl.threads()), pl.shmem, s, g, src, epi);
     return hipGetLastError();

@@ -41,15 +41,15 @@ __global__ __launch_bounds__(MAXT) void k_refine_strided(StridedGeom gm, RefPtrs
     for (int k = 0; k < M; ++k) {
         const int g = g0 + k;
         const bool v = act && g < n;
-        const i64 off = base + (i64)g * st;
+        const i64 off = base + (i64)g * st;  // base itself is in bounds for every lane
         if constexpr (SM) {
-            cf.s[k] = v ? src.s[off] : 0.f;
+            cf.s[k] = load_if(src.s, off, v, base);
         } else {
-            cf.a[k] = v ? src.a[off] : 0.f;
-            cf.b[k] = v ? src.b[off] : 1.f;
-            cf.c[k] = v ? src.c[off] : 0.f;
+            cf.a[k] = load_if(src.a, off, v, base);
+            cf.b[k] = v ? load_if(src.b, off, v, base) : 1.f;
+            cf.c[k] = load_if(src.c, off, v, base);
         }
-        dd[k] = v ? (double)d[off] : 0.0;
+        dd[k] = (double)load_if(d, off, v, base);
     }
     double out[M];
     refine_tile<M, SM>(cf, dd, red, xb, S, P, p, t, L, out);

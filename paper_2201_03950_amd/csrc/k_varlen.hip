@@ -79,17 +79,30 @@ __device__ __forceinline__ void varlen_assign(const VarlenArgs &g, int item, sho
     __syncthreads();
 }
 
-// Coalesced copy of one packed array into the staging region: consecutive
-// lanes take consecutive (tile, row) positions, i.e. consecutive elements of
-// the same system.  Tile t's row k lands at t * (M + 1) + k.
+// Staging of one packed array, in two halves so that the loads of the next
+// array can be in flight while this one moves through LDS:
+//   varlen_load : consecutive lanes take consecutive (tile, row) positions, i.e.
+//                 consecutive elements of the same system; rows past a tile's
+//                 count load element 0 instead (branch-free) and are zeroed;
+//   varlen_put  : tile t's row k lands at t * (M + 1) + k (every slot is
+//                 written; slots past a tile's count hold 0 and are never used).
 template <typename E, int M, int NT>
-__device__ __forceinline__ void varlen_stage_in(E *__restrict__ reg, const E *__restrict__ src,
-                                                const i64 *s_base, const int *s_cnt) {
-#pragma unroll 4
+__device__ __forceinline__ void varlen_load(E (&v)[M], const E *__restrict__ src, const i64 *s_base,
+                                            const int *s_cnt) {
+#pragma unroll
     for (int i = 0; i < M; ++i) {
         const int e = threadIdx.x + i * NT;
         const int tau = e / M, k = e % M;
-        if (k < s_cnt[tau]) reg[tau * (M + 1) + k] = src[s_base[tau] + k];
+        v[i] = load_if(src, s_base[tau] + k, k < s_cnt[tau], (i64)0);
+    }
+}
+
+template <typename E, int M, int NT>
+__device__ __forceinline__ void varlen_put(E *__restrict__ reg, const E (&v)[M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        const int e = threadIdx.x + i * NT;
+        reg[(e / M) * (M + 1) + e % M] = v[i];
     }
 }
 
@@ -146,9 +159,19 @@ __global__ __launch_bounds__(NT) void k_varlen_plain(VarlenArgs g) {
         varlen_assign<M, NT>(g, item, s_sys, s_p, s_base, s_cnt, sys, p, P, n);
         const bool act = sys >= 0;
         T ra[M], rb[M], rc[M], rd[M];
+        // with small tiles the next array's loads are issued before this one
+        // is staged (registers allow it); otherwise one array at a time
+        constexpr bool pipe = M * sizeof(T) <= 64;
+        T vn[M];
+        varlen_load<T, M, NT>(vn, arr[0], s_base, s_cnt);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            varlen_stage_in<T, M, NT>(reg, arr[r], s_base, s_cnt);
+            T vc[M];
+            if (!pipe && r > 0) varlen_load<T, M, NT>(vn, arr[r], s_base, s_cnt);
+#pragma unroll
+            for (int k = 0; k < M; ++k) vc[k] = vn[k];
+            if (pipe && r < 3) varlen_load<T, M, NT>(vn, arr[r + 1], s_base, s_cnt);
+            varlen_put<T, M, NT>(reg, vc);
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < M; ++k) {
@@ -205,21 +228,27 @@ __global__ __launch_bounds__(NT) void k_varlen_refine(VarlenArgs g) {
         RefCoef<M, false> cf;
         cf.g0 = p * M;
         cf.n = act ? n : 0;
+        float v[M];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
-            varlen_stage_in<float, M, NT>(regf, arr[r], s_base, s_cnt);
+            varlen_load<float, M, NT>(v, arr[r], s_base, s_cnt);
+            varlen_put<float, M, NT>(regf, v);
             __syncthreads();
 #pragma unroll
             for (int k = 0; k < M; ++k) {
-                const bool v = act && p * M + k < n;
+                const bool ok = act && p * M + k < n;
                 const float val = regf[pos + k];
-                if (r == 0) cf.a[k] = v ? val : 0.f;
-                if (r == 1) cf.b[k] = v ? val : 1.f;
-                if (r == 2) cf.c[k] = v ? val : 0.f;
+                if (r == 0) cf.a[k] = ok ? val : 0.f;
+                if (r == 1) cf.b[k] = ok ? val : 1.f;
+                if (r == 2) cf.c[k] = ok ? val : 0.f;
             }
             __syncthreads();
         }
-        varlen_stage_in<double, M, NT>(reg, d, s_base, s_cnt);
+        {
+            double vd[M];
+            varlen_load<double, M, NT>(vd, d, s_base, s_cnt);
+            varlen_put<double, M, NT>(reg, vd);
+        }
         __syncthreads();
         double dd[M];
 #pragma unroll

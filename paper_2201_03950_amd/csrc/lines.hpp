@@ -46,10 +46,11 @@ struct SrcArrays {  // per-point a, b, c arrays; rhs from d
             const int g = g0 + k;
             const bool v = act && g < n;
             const i64 off = base + (i64)g * st;
-            ra[k] = (v && g > 0) ? a[off] : T(0);
-            rb[k] = v ? b[off] : T(1);
-            rc[k] = (v && g < n - 1) ? c[off] : T(0);
-            rd[k] = v ? d[off] : T(0);
+            ra[k] = load_if(a, off, v && g > 0, base);
+            const T bv = load_if(b, off, v, base);
+            rb[k] = v ? bv : T(1);
+            rc[k] = load_if(c, off, v && g < n - 1, base);
+            rd[k] = load_if(d, off, v, base);
         }
     }
 };
@@ -68,7 +69,7 @@ struct SrcConst {  // the same (a, b, c) on every row, generated in-kernel
             ra[k] = (v && g > 0) ? a : T(0);
             rb[k] = v ? b : T(1);
             rc[k] = (v && g < n - 1) ? c : T(0);
-            rd[k] = v ? d[base + (i64)g * st] : T(0);
+            rd[k] = load_if(d, base + (i64)g * st, v, base);
         }
     }
 };
@@ -84,11 +85,11 @@ struct SrcS {  // rows (-s, 1 + 2 s, -s) from a per-point s array
             const int g = g0 + k;
             const bool v = act && g < n;
             const i64 off = base + (i64)g * st;
-            const T sv = v ? s[off] : T(0);
+            const T sv = load_if(s, off, v, base);
             ra[k] = (g > 0) ? -sv : T(0);
             rb[k] = T(1) + T(2) * sv;
             rc[k] = (g < n - 1) ? -sv : T(0);
-            rd[k] = v ? d[off] : T(0);
+            rd[k] = load_if(d, off, v, base);
         }
     }
 };
@@ -106,10 +107,11 @@ struct SrcArraysT {
             const int g = g0 + k;
             const bool v = act && g < n;
             const i64 off = base + (i64)g * st;
-            ra[k] = (v && g > 0) ? c[off - st] : T(0);
-            rb[k] = v ? b[off] : T(1);
-            rc[k] = (v && g < n - 1) ? a[off + st] : T(0);
-            rd[k] = v ? d[off] : T(0);
+            ra[k] = load_if(c, off - st, v && g > 0, base);
+            const T bv = load_if(b, off, v, base);
+            rb[k] = v ? bv : T(1);
+            rc[k] = load_if(a, off + st, v && g < n - 1, base);
+            rd[k] = load_if(d, off, v, base);
         }
     }
 };
@@ -124,7 +126,7 @@ struct SrcST {  // transposed rows of the s operator: (-s_{g-1}, 1 + 2 s_g, -s_{
 #pragma unroll
         for (int k = 0; k < M + 2; ++k) {
             const int g = g0 + k - 1;
-            sv[k] = (act && g >= 0 && g < n) ? s[base + (i64)g * st] : T(0);
+            sv[k] = load_if(s, base + (i64)g * st, act && g >= 0 && g < n, base);
         }
 #pragma unroll
         for (int k = 0; k < M; ++k) {
@@ -133,7 +135,7 @@ struct SrcST {  // transposed rows of the s operator: (-s_{g-1}, 1 + 2 s_g, -s_{
             ra[k] = (g > 0) ? -sv[k] : T(0);
             rb[k] = T(1) + T(2) * sv[k + 1];
             rc[k] = (g < n - 1) ? -sv[k + 2] : T(0);
-            rd[k] = v ? d[base + (i64)g * st] : T(0);
+            rd[k] = load_if(d, base + (i64)g * st, v, base);
         }
     }
 };
@@ -144,6 +146,7 @@ struct SrcST {  // transposed rows of the s operator: (-s_{g-1}, 1 + 2 s_g, -s_{
 
 template <typename T>
 struct EpiStore {  // x = solution
+    static constexpr bool kWide = false;  // keeps no extra words per row
     T *x;
     // all M rows valid, 32-bit row offsets from `off` (used by the constant-row kernels)
     template <int M>
@@ -170,6 +173,7 @@ struct EpiStore {  // x = solution
 
 template <typename T>
 struct EpiAdd {  // u += solution (the update of Alg. 3, fused into the last solve)
+    static constexpr bool kWide = true;  // keeps the M prefetched values of u
     T *u;
     // all M rows valid; u is read only now (not prefetched) and in groups of 8
     // rows (the empty asm keeps the compiler from hoisting every load), which
@@ -199,7 +203,7 @@ struct EpiAdd {  // u += solution (the update of Alg. 3, fused into the last sol
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const int g = g0 + k;
-            pre.v[k] = (act && g < n) ? u[base + (i64)g * st] : T(0);
+            pre.v[k] = load_if(u, base + (i64)g * st, act && g < n, base);
         }
     }
     template <int M>
@@ -217,6 +221,7 @@ struct EpiAdd {  // u += solution (the update of Alg. 3, fused into the last sol
 // gc = -lambda x_{g+1} (0 at the ignored a_0 / c_{N-1}).
 template <typename T>
 struct EpiAdjArrays {
+    static constexpr bool kWide = true;  // keeps the forward solution and its neighbours
     const T *x;
     T *g, *ga, *gb, *gc;
     template <int M>
@@ -229,7 +234,7 @@ struct EpiAdjArrays {
 #pragma unroll
         for (int k = 0; k < M + 2; ++k) {
             const int gg = g0 + k - 1;
-            pre.xv[k] = (act && gg >= 0 && gg < n) ? x[base + (i64)gg * st] : T(0);
+            pre.xv[k] = load_if(x, base + (i64)gg * st, act && gg >= 0 && gg < n, base);
         }
     }
     template <int M>
@@ -252,6 +257,7 @@ struct EpiAdjArrays {
 // Adjoint epilogue, s form: lambda -> g; gs += lambda (x_{g-1} - 2 x_g + x_{g+1}).
 template <typename T>
 struct EpiAdjS {
+    static constexpr bool kWide = true;  // keeps the forward solution and its neighbours
     const T *x;
     T *g, *gs;
     template <int M>
@@ -265,12 +271,12 @@ struct EpiAdjS {
 #pragma unroll
         for (int k = 0; k < M + 2; ++k) {
             const int gg = g0 + k - 1;
-            pre.xv[k] = (act && gg >= 0 && gg < n) ? x[base + (i64)gg * st] : T(0);
+            pre.xv[k] = load_if(x, base + (i64)gg * st, act && gg >= 0 && gg < n, base);
         }
 #pragma unroll
         for (int k = 0; k < M; ++k) {
             const int gg = g0 + k;
-            pre.sv[k] = (act && gg < n) ? gs[base + (i64)gg * st] : T(0);
+            pre.sv[k] = load_if(gs, base + (i64)gg * st, act && gg < n, base);
         }
     }
     template <int M>
@@ -307,6 +313,9 @@ __global__ __launch_bounds__(MAXT) void k_strided(StridedGeom gm, Src src, Epi e
     src.template load<M>(base, st, g0, gm.n, act, ra, rb, rc, rd);
     typename Epi::template Pre<M> pre;
     epi.template prefetch<M>(pre, base, st, g0, gm.n, act);
+    // keep the scheduler from sinking loads into the elimination: every load
+    // of the tile is issued before the first arithmetic waits on one
+    asm volatile("" ::: "memory");
     T u[M];
     tile_solve<T, M>(ra, rb, rc, rd, sh, L * P, P, p, t, L, u);
     epi.template store<M>(pre, base, st, g0, gm.n, act, u);
@@ -343,7 +352,7 @@ __device__ __forceinline__ void stage_in(T *__restrict__ dst, const T *__restric
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int e = threadIdx.x + k * nt;
-        v[k] = e < cnt ? src[e] : T(0);
+        v[k] = load_if(src, e, e < cnt, cnt - 1);
     }
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -403,10 +412,11 @@ struct StgArrays {
         for (int k = 0; k < M; ++k) {
             const int g = g0 + k;
             const bool v = act && g < n;
-            if (r == 0) ra[k] = (v && g > 0) ? sh[pos + k] : T(0);
-            if (r == 1) rb[k] = v ? sh[pos + k] : T(1);
-            if (r == 2) rc[k] = (v && g < n - 1) ? sh[pos + k] : T(0);
-            if (r == 3) rd[k] = v ? sh[pos + k] : T(0);
+            const T val = sh[pos + k];  // own tile slot: always inside the region
+            if (r == 0) ra[k] = (v && g > 0) ? val : T(0);
+            if (r == 1) rb[k] = v ? val : T(1);
+            if (r == 2) rc[k] = (v && g < n - 1) ? val : T(0);
+            if (r == 3) rd[k] = v ? val : T(0);
         }
     }
 };
@@ -431,7 +441,8 @@ struct StgConst {
             ra[k] = (v && g > 0) ? a : T(0);
             rb[k] = v ? b : T(1);
             rc[k] = (v && g < n - 1) ? c : T(0);
-            rd[k] = v ? sh[pos + k] : T(0);
+            const T val = sh[pos + k];
+            rd[k] = v ? val : T(0);
         }
     }
 };
@@ -453,12 +464,14 @@ struct StgS {
             const int g = g0 + k;
             const bool v = act && g < n;
             if (r == 0) {
-                const T sv = v ? sh[pos + k] : T(0);
+                const T val = sh[pos + k];
+                const T sv = v ? val : T(0);
                 ra[k] = (g > 0) ? -sv : T(0);
                 rb[k] = T(1) + T(2) * sv;
                 rc[k] = (g < n - 1) ? -sv : T(0);
             } else {
-                rd[k] = v ? sh[pos + k] : T(0);
+                const T val = sh[pos + k];
+                rd[k] = v ? val : T(0);
             }
         }
     }
