@@ -242,7 +242,9 @@ hipError_t go_t(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
 bool plan_rhs_x(const AdiReq &r, LinePlan *pl, std::string *err) {
     const int w = r.f64 ? 8 : 4;
     LinePlan p;
-    int M = r.force_M ? r.force_M : (r.f64 ? 8 : 16);
+    // 8-row tiles: the block then holds few enough lines that several blocks
+    // share a CU (measured faster than 16 rows in both precisions)
+    int M = r.force_M ? r.force_M : (cdiv(r.nx, 8) <= kMaxThreads ? 8 : 16);
     if (M != 8 && M != 16) {
         *err = "fused stencil + x solve supports tiles of 8 or 16 rows";
         return false;

@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "dispatch.hpp"
+#include "adj_staged.hpp"
 #include "lines.hpp"
 
 namespace trid {
@@ -52,7 +53,11 @@ int staged_regions(Mode m) {
 bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
     const int w = r.f64 ? 8 : 4;
     LinePlan p;
-    int M = r.force_M ? r.force_M : (r.f64 ? 8 : 16);
+    const bool adj_s = r.mode == Mode::ST && r.out == Out::AdjS;  // transposed s solve
+    // the staged transposed solve keeps more arrays in flight: 8-row tiles
+    // whenever a block can hold the line that way
+    const bool adj_x = adj_s && r.inner == 1 && !r.force_strided && cdiv(r.n, 8) <= kStagedMaxThreads;
+    int M = r.force_M ? r.force_M : ((r.f64 || adj_x) ? 8 : 16);
     if (M != 8 && M != 16 && M != 32) {
         *err = "tile size must be 8, 16 or 32";
         return false;
@@ -71,7 +76,8 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
     p.M = M;
     p.P = (int)P;
     const int regions = staged_regions(r.mode);
-    const bool want_staged = r.inner == 1 && !r.force_strided && regions > 0 && r.out == Out::Store &&
+    const bool want_staged = r.inner == 1 && !r.force_strided &&
+                             ((regions > 0 && r.out == Out::Store) || (adj_s && M <= 16)) &&
                              P <= kStagedMaxThreads;
     if (want_staged) {
         int L = r.force_L ? r.force_L : std::max(1, kStagedMaxThreads / (int)P);
@@ -159,12 +165,34 @@ hipError_t staged_M(const LineReq &r, const LinePlan &pl, Src src, hipStream_t s
     }
 }
 
+template <typename T, int M>
+hipError_t go_staged_adj_s(const LineReq &r, const LinePlan &pl, hipStream_t s) {
+    StagedGeom g;
+    g.nlines = r.outer;
+    g.n = (int)r.n;
+    g.L = pl.L;
+    g.P = pl.P;
+    g.ls = pl.ls;
+    const T *grhs = static_cast<const T *>(r.d ? r.d : r.g);
+    hipLaunchKernelGGL((k_staged_adj_s<T, M>), dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g,
+                       static_cast<const T *>(r.s), grhs, static_cast<const T *>(r.xf), static_cast<T *>(r.g),
+                       static_cast<T *>(r.gs));
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_typed(const LineReq &r, const LinePlan &pl, hipStream_t s) {
     const T *a = static_cast<const T *>(r.a), *b = static_cast<const T *>(r.b);
     const T *c = static_cast<const T *>(r.c), *sp = static_cast<const T *>(r.s);
     const T *d = static_cast<const T *>(r.d);
     T *x = static_cast<T *>(r.x);
+    if (pl.staged && r.out == Out::AdjS) {
+        switch (pl.M) {
+            case 8: return go_staged_adj_s<T, 8>(r, pl, s);
+            case 16: return go_staged_adj_s<T, 16>(r, pl, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (pl.staged) {
         switch (r.mode) {
             case Mode::Arrays: return staged_M<T>(r, pl, StgArrays<T>{a, b, c, d}, s);

@@ -340,20 +340,25 @@ __device__ __forceinline__ int staged_pos(int ll, int i, int ls) {
 // Cooperative coalesced copy of `cnt` contiguous elements from global `src`
 // into staged positions of region `dst` (line length n).  cnt <= blockDim * M
 // (a block holds at most P * M >= n rows per line and L * P threads), so each
-// thread handles at most M elements: the loop is unrolled and its loads issue
-// together.
+// thread handles at most M elements, in two halves that may be split apart:
+//   stage_load: the thread's M elements into registers (all loads in flight
+//               together; branch-free, idle slots read element cnt - 1),
+//   stage_put : those registers into their staged LDS positions.
 template <typename T, int M>
-__device__ __forceinline__ void stage_in(T *__restrict__ dst, const T *__restrict__ src, int cnt,
-                                         int n, int ls) {
+__device__ __forceinline__ void stage_load(T (&v)[M], const T *__restrict__ src, int cnt) {
     const int nt = blockDim.x;
-    int ll = threadIdx.x / n, i = threadIdx.x % n;
-    const int dl = nt / n, di = nt % n;
-    T v[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int e = threadIdx.x + k * nt;
         v[k] = load_if(src, e, e < cnt, cnt - 1);
     }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void stage_put(T *__restrict__ dst, const T (&v)[M], int cnt, int n, int ls) {
+    const int nt = blockDim.x;
+    int ll = threadIdx.x / n, i = threadIdx.x % n;
+    const int dl = nt / n, di = nt % n;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int e = threadIdx.x + k * nt;
@@ -365,6 +370,14 @@ __device__ __forceinline__ void stage_in(T *__restrict__ dst, const T *__restric
             ++ll;
         }
     }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void stage_in(T *__restrict__ dst, const T *__restrict__ src, int cnt,
+                                         int n, int ls) {
+    T v[M];
+    stage_load<T, M>(v, src, cnt);
+    stage_put<T, M>(dst, v, cnt, n, ls);
 }
 
 template <typename T, int M>

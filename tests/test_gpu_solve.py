@@ -220,6 +220,30 @@ def test_s_adjoint_matches_oracle(trid, orc, dt, axis):
     assert err <= TOL[dt] * 10
 
 
+# x lines take the LDS-staged transposed solve: line lengths across the tile
+# sizes and the one-line-per-block limit, line counts with a ragged last block
+S_ADJ_X = [(1, 7), (2, 5), (8, 33), (9, 70), (255, 13), (256, 40), (1000, 3), (2048, 2), (2100, 3)]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("n,lines", S_ADJ_X, ids=[str(g) for g in S_ADJ_X])
+def test_s_adjoint_x_lines(trid, orc, dt, n, lines):
+    rng = np.random.default_rng(n + lines)
+    shape = gen.mesh_shape((n,), lines)
+    s = (0.2 * rng.lognormal(0.0, 0.5, shape)).astype(dt)
+    x = rng.standard_normal(shape).astype(dt)
+    gy = rng.standard_normal(shape).astype(dt)
+    gs0 = rng.standard_normal(shape).astype(dt)
+    a, b, c = orc.implicit_coefs(s)
+    lam, ga, gb, gc = orc.gtsv_adjoint(a, b, c, x, gy, 0)
+    gs_ref = gs0 + (-ga + 2.0 * gb - gc)
+    tg, tgs = _t(gy), _t(gs0)
+    trid.gtsv_s_adjoint(_t(s), _t(x), tg, tgs, 0)
+    assert _line_err(tg.cpu().numpy().astype(np.float64), lam, 0) <= TOL[dt]
+    err = float(np.max(np.abs(tgs.cpu().numpy() - gs_ref)) / max(np.max(np.abs(gs_ref)), 1e-30))
+    assert err <= TOL[dt] * 10
+
+
 # ------------------------------------------------ constant-row fast path ----
 
 CONST_GEOMS = [((64, 96, 32), 2, 0), ((64, 96, 32), 2, 1), ((64, 96, 32), 2, 2),
