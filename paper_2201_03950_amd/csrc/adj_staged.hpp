@@ -73,10 +73,10 @@ __global__ __launch_bounds__(256) void k_staged_adj_s(StagedGeom gm, const T *__
         TileState<T, M> ts;
         tile_eliminate_fn<T, M>(rows, rd, ts);
         T f, lv;
-        reduced_pcr<T, M>(ts, red, L * P, P, p, t, 1, f, lv);
+        reduced_solve<T, M>(ts, red, L * P, P, p, t, 1, f, lv);
         tile_backsub<T, M>(ts, f, lv, lam);
     }
-    // every thread took its rhs before the barriers inside reduced_pcr
+    __syncthreads();  // every thread has taken its rhs
     stage_put<T, M>(sh, vx, cnt, n, ls);
     __syncthreads();
     T gsd[M];

@@ -151,20 +151,6 @@ __device__ __forceinline__ float vget<float>(const float4 &v, int j) {
     return j == 0 ? v.x : (j == 1 ? v.y : (j == 2 ? v.z : v.w));
 }
 
-// DPP lane moves (row shifts within 16-lane rows, wave shifts by one lane);
-// lanes whose source is outside the row / wavefront receive 0.
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
-                                                                 0xF, 0xF, true));
-}
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
-    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
 // Plain right-hand side: copy d's block into LDS with 16-byte loads.
 template <typename T>
 struct CStgCopy {
@@ -335,15 +321,6 @@ struct PcrTab {
 
 template <typename T>
 bool make_pcr_tab(double a, double b, double c, int M, int P, PcrTab<T> *t);
-
-template <int S, typename T>
-__device__ __forceinline__ T row_from_lower(T v) {  // value of tile p - S
-    return dpp_move<0x110 + S>(v);
-}
-template <int S, typename T>
-__device__ __forceinline__ T row_from_upper(T v) {  // value of tile p + S
-    return dpp_move<0x100 + S>(v);
-}
 
 template <typename T, int P, int S>
 struct PcrLevels {

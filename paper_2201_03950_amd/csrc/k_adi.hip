@@ -164,8 +164,8 @@ __global__ __launch_bounds__(256) void k_rhs_x(RhsGeom g, const T *__restrict__ 
     }
     T uu[M];
     tile_solve<T, M>(ra, rb, rc, rd, red, L * P, P, p, t, 1, uu);
-    // each thread overwrites only the positions it took (all passed the
-    // barriers inside tile_solve)
+    // each thread overwrites only the slots it took itself (no other thread
+    // reads them before the barrier below)
 #pragma unroll
     for (int k = 0; k < M; ++k) sh[pos + k] = uu[k];
     __syncthreads();

@@ -80,7 +80,10 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
                              ((regions > 0 && r.out == Out::Store) || (adj_s && M <= 16)) &&
                              P <= kStagedMaxThreads;
     if (want_staged) {
-        int L = r.force_L ? r.force_L : std::max(1, kStagedMaxThreads / (int)P);
+        // about one wavefront per block: the block's barriers then cost little
+        // and many blocks per CU overlap their load, solve and store phases
+        // (measured faster than 256-thread blocks for line lengths 128..256)
+        int L = r.force_L ? r.force_L : std::max(1, 64 / (int)P);
         L = std::max(1, std::min(L, pow2_ceil(r.outer)));
         const int ls = (int)P * (M + 1);
         auto bytes = [&](int LL) {  // one staging region + reduced-solve scratch
@@ -97,8 +100,19 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
             return true;
         }
     }
-    int L = r.force_L ? r.force_L : std::min(64, pow2_floor(maxt / P));
-    if (!r.force_L && r.inner < L) L = std::max(1, pow2_ceil(r.inner));
+    int L = r.force_L;
+    if (!L) {
+        if (r.mode == Mode::Arrays || r.mode == Mode::ArraysT) {
+            L = std::min(64, pow2_floor(maxt / P));  // four input streams: long row segments
+        } else {
+            // 64-byte row segments per tile; twice that when the grid would
+            // otherwise be small (fewer than 4096 blocks)
+            L = 64 / w;
+            if (cdiv(r.inner, L) * r.outer < 4096) L *= 2;
+            L = std::min(L, pow2_floor(maxt / P));
+        }
+        if (r.inner < L) L = std::max(1, pow2_ceil(r.inner));
+    }
     if ((i64)L * P > maxt) {
         *err = "plan exceeds 1024 threads per block";
         return false;

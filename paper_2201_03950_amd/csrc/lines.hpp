@@ -524,8 +524,8 @@ __global__ __launch_bounds__(MAXT) void k_staged(StagedGeom gm, Src src, Out out
     }
     T u[M];
     tile_solve<T, M>(ra, rb, rc, rd, red, S, P, p, t, 1, u);
-    // the staging region is dead once every thread has taken its rows (they all
-    // passed the barriers inside tile_solve): overwrite own positions with results
+    // take() reads only this thread's own slots, so they can hold its results
+    // right away (no other thread reads them before the barrier below)
 #pragma unroll
     for (int k = 0; k < M; ++k) sh[pos + k] = u[k];
     __syncthreads();

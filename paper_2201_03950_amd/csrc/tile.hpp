@@ -58,6 +58,29 @@ __device__ __forceinline__ U load_if(const U *p, I i, bool ok, I safe) {
     return ok ? v : U{};
 }
 
+// DPP lane moves (row shifts within 16-lane rows, wave shifts by one lane);
+// lanes whose source is outside the row / wavefront receive 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <int S, typename T>
+__device__ __forceinline__ T row_from_lower(T v) {  // value of tile p - S
+    return dpp_move<0x110 + S>(v);
+}
+template <int S, typename T>
+__device__ __forceinline__ T row_from_upper(T v) {  // value of tile p + S
+    return dpp_move<0x100 + S>(v);
+}
+
 // Result of the per-tile sweep (eq. (7)).
 //   first row: fa*l_{p-1} + fb*f_p + fc*l_p = fd   (f_p, l_p: tile's first/last unknown)
 //   last row:  la*f_p + l_p + lc*f_{p+1} = ld
@@ -213,6 +236,66 @@ __device__ __forceinline__ void reduced_pcr(const TileState<T, M> &ts, T *__rest
     lv = ts.ld - ts.la * f - ts.lc * fn;
 }
 
+// Reduced solve of one line with its P tiles in P adjacent lanes of one
+// 16-lane DPP row (P a power of two <= 16, lines aligned to P-lane groups):
+// the same elimination and PCR (Alg. 2) as reduced_pcr, with every neighbour
+// value moved by a DPP row shift instead of LDS -- no barrier, no scratch.
+template <typename T, int M, int P, int S>
+struct DppPcr {
+    __device__ __forceinline__ static void run(int p, T &a, T &c, T &d) {
+        if constexpr (S < P) {
+            T am = row_from_lower<S>(a), cm = row_from_lower<S>(c), dm = row_from_lower<S>(d);
+            T an = row_from_upper<S>(a), cn = row_from_upper<S>(c), dn = row_from_upper<S>(d);
+            if (p < S) am = cm = dm = T(0);  // the row also holds other lines
+            if (p + S >= P) an = cn = dn = T(0);
+            const T r = fast_rcp(T(1) - a * cm - c * an);
+            const T na = -r * (a * am);
+            const T nc = -r * (c * cn);
+            d = r * (d - a * dm - c * dn);
+            a = na;
+            c = nc;
+            DppPcr<T, M, P, 2 * S>::run(p, a, c, d);
+        }
+    }
+};
+
+template <typename T, int M, int P>
+__device__ __forceinline__ void reduced_pcr_dpp(const TileState<T, M> &ts, int p, T &f, T &lv) {
+    T pa = row_from_lower<1>(ts.la), pc = row_from_lower<1>(ts.lc), pd = row_from_lower<1>(ts.ld);
+    if (p == 0) pa = pc = pd = T(0);
+    const T gsub = -ts.fa * pa;
+    const T gdia = ts.fb - ts.fa * pc - ts.fc * ts.la;
+    const T gsup = -ts.fc * ts.lc;
+    const T grhs = ts.fd - ts.fa * pd - ts.fc * ts.ld;
+    const T rg = fast_rcp(gdia);
+    T a = gsub * rg, c = gsup * rg, d = grhs * rg;
+    DppPcr<T, M, P, 1>::run(p, a, c, d);
+    f = d;
+    T fn = row_from_upper<1>(f);
+    if (p + 1 >= P) fn = T(0);
+    lv = ts.ld - ts.la * f - ts.lc * fn;
+}
+
+// Reduced solve dispatch: the DPP form when the line's tiles are adjacent
+// lanes (pstride 1, slot = line * P + p) and P is a power of two <= 16 (a
+// uniform choice: P is the same for the whole launch); reduced_pcr otherwise.
+// Callers must not rely on a barrier inside (the DPP form has none).
+template <typename T, int M>
+__device__ __forceinline__ void reduced_solve(const TileState<T, M> &ts, T *__restrict__ sh, int S, int P,
+                                              int p, int slot, int pstride, T &f, T &lv) {
+    if (pstride == 1) {
+        switch (P) {
+            case 1: reduced_pcr_dpp<T, M, 1>(ts, p, f, lv); return;
+            case 2: reduced_pcr_dpp<T, M, 2>(ts, p, f, lv); return;
+            case 4: reduced_pcr_dpp<T, M, 4>(ts, p, f, lv); return;
+            case 8: reduced_pcr_dpp<T, M, 8>(ts, p, f, lv); return;
+            case 16: reduced_pcr_dpp<T, M, 16>(ts, p, f, lv); return;
+            default: break;
+        }
+    }
+    reduced_pcr<T, M>(ts, sh, S, P, p, slot, pstride, f, lv);
+}
+
 // Back substitution (eq. (7)): the tile's M unknowns.
 template <typename T, int M>
 __device__ __forceinline__ void tile_backsub(const TileState<T, M> &ts, T f, T lv, T (&u)[M]) {
@@ -230,7 +313,7 @@ __device__ __forceinline__ void tile_solve(const T (&ra)[M], const T (&rb)[M], c
     TileState<T, M> ts;
     tile_eliminate<T, M>(ra, rb, rc, rd, ts);
     T f, lv;
-    reduced_pcr<T, M>(ts, sh, S, P, p, slot, pstride, f, lv);
+    reduced_solve<T, M>(ts, sh, S, P, p, slot, pstride, f, lv);
     tile_backsub<T, M>(ts, f, lv, u);
 }
 

@@ -220,9 +220,42 @@ def test_s_adjoint_matches_oracle(trid, orc, dt, axis):
     assert err <= TOL[dt] * 10
 
 
+# staged x solves: every reduced-solve form (DPP row shifts for P = 1..16 tiles
+# per line, LDS PCR for 32 and for P not a power of two), both tile sizes
+STAGED_P = [8, 16, 24, 32, 64, 100, 128, 256]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("M", [8, 16])
+@pytest.mark.parametrize("n", STAGED_P)
+def test_staged_x_every_reduced_form(trid, orc, dt, M, n):
+    lines = 37  # ragged last block for every L
+    a, b, c, d = (v.astype(dt) for v in gen.dd_mesh((n,), lines, seed=n + M))
+    ref = orc.gtsv(a, b, c, d, 0)
+    s = (0.2 * np.random.default_rng(n).lognormal(0.0, 0.5, d.shape)).astype(dt)
+    ref_s = orc.gtsv_s(s, d, 0)
+    trid.set_tile(M, 0)
+    try:
+        td = _t(d)
+        trid.gtsv(_t(a), _t(b), _t(c), td, 0)
+        ts = _t(d)
+        trid.gtsv_s(_t(s), ts, 0)
+        u = gen.adi3d_field((n, 6, 5), 2, seed=n).astype(dt)
+        sp = (0.2 * np.random.default_rng(n + 1).lognormal(0.0, 0.5, u.shape)).astype(dt)
+        ref_u = orc.adi_step(u, s=sp, nsteps=2)
+        tu = _t(u)
+        trid.adi_step(tu, s=_t(sp), nsteps=2)
+    finally:
+        trid.set_tile(0, 0)
+    assert _line_err(td.cpu().numpy().astype(np.float64), ref, 0) <= TOL[dt]
+    assert _line_err(ts.cpu().numpy().astype(np.float64), ref_s, 0) <= TOL[dt]
+    assert _field_err(tu.cpu().numpy().astype(np.float64), ref_u) <= TOL[dt] * 10
+
+
 # x lines take the LDS-staged transposed solve: line lengths across the tile
 # sizes and the one-line-per-block limit, line counts with a ragged last block
-S_ADJ_X = [(1, 7), (2, 5), (8, 33), (9, 70), (255, 13), (256, 40), (1000, 3), (2048, 2), (2100, 3)]
+S_ADJ_X = [(1, 7), (2, 5), (8, 33), (9, 70), (33, 9), (64, 21), (100, 10), (128, 19), (255, 13), (256, 40),
+           (1000, 3), (2048, 2), (2100, 3)]
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
