@@ -183,15 +183,20 @@ struct CStgCopy {
 };
 
 // Right-hand side of the ADI step, d = 2 s0 (sum of neighbours - 2 NDIM u),
-// zero outside the mesh, computed while staging.  Thread t owns one 16-byte
-// column c = t % C (C = N / V vectors per line) of M / V consecutive lines, so
+// zero outside the mesh, computed while staging.  Thread t owns VB consecutive
+// x elements (one or two 16-byte vectors: VB is chosen so that a line row
+// spans at most one wavefront, C = N / VB <= 64 lanes) of LG = M / VB
+// consecutive lines, so
 //   - the y neighbours of its lines are its own previous / next line (a
 //     sliding window in registers; only the two halo lines are extra loads),
-//   - the x neighbours across a vector boundary come from the adjacent lanes
-//     (DPP wave shifts; lanes at a wavefront edge load theirs),
-//   - the z neighbours are two coalesced vector loads per vector.
-// The planner guarantees N = P * M, blockDim = 256 = L * P and M / V lines
-// per thread (so 256 / C thread groups cover the block's L lines).
+//   - the x neighbours across its VB elements come from the adjacent lanes
+//     (DPP wave shifts); when a line row fills whole wavefronts, the first
+//     and last lanes of a row are the line ends and no other load is needed,
+//   - the z neighbours are coalesced vector loads.
+// Offsets are 32-bit byte offsets from the array start (the planner keeps the
+// array below 4 GB), so loads use a scalar base and one VGPR offset.  The
+// planner guarantees N = P * M, blockDim = 256 = L * P, and 256 / C thread
+// groups of LG lines cover the block's L lines.
 template <typename T>
 __device__ __forceinline__ T wave_from_lower_lane(T v) {  // lane i <- lane i - 1 (lane 0: 0)
     return dpp_move<0x138>(v);
@@ -200,6 +205,12 @@ template <typename T>
 __device__ __forceinline__ T wave_from_upper_lane(T v) {  // lane i <- lane i + 1 (lane 63: 0)
     return dpp_move<0x130>(v);
 }
+
+template <typename T, int NV>
+struct Cols {  // VB = NV * V consecutive elements of one line row
+    typename Vec<T>::type v[NV];
+    __device__ __forceinline__ T operator[](int e) const { return vget<T>(v[e / Vec<T>::n], e % Vec<T>::n); }
+};
 
 template <typename T, int NDIM>
 struct CStgRhs {
@@ -211,8 +222,12 @@ struct CStgRhs {
                                           int *) const {
         using VT = typename Vec<T>::type;
         constexpr int V = Vec<T>::n;
-        constexpr int C = N / V;   // vectors per line
-        constexpr int LG = M / V;  // lines per thread
+        constexpr int NV = (N / V > 64) ? 2 : 1;  // 16-byte vectors per thread and row
+        constexpr int VB = NV * V;                // elements per thread and row
+        constexpr int C = N / VB;                 // threads per line row
+        constexpr bool kEdges = !(C <= 64 && 64 % C == 0);  // rows straddle wavefronts
+        constexpr int LG = M / VB;                // lines per thread
+        static_assert(M % VB == 0 && N % VB == 0, "a thread's elements stay in one tile");
         const int t = threadIdx.x, c = t % C, grp = t / C;
         const int lane = t & 63;
         const int lfirst = grp * LG;  // first block line of this thread
@@ -224,10 +239,6 @@ struct CStgRhs {
             j -= ny;
             k = (k + 1 == nz) ? 0 : k + 1;
         }
-        const int sz = ny * N;
-        const T *qb = u + o0 * N + c * V;  // this thread's column of the block's first line
-        const T *q0 = qb + lfirst * N;
-        const int last = (nl - 1) * N;     // offset of the block's last line: in bounds for every lane
         const bool live0 = lfirst < nl;
         // neighbour existence of the thread's lines (no loads involved)
         bool jp[LG], jn[LG], kp[LG], kn[LG];
@@ -245,52 +256,75 @@ struct CStgRhs {
                 }
             }
         }
+        // byte offsets: this thread's column in the block's first line, the
+        // block's last line (in bounds for every lane: idle lanes read it)
+        constexpr unsigned W = sizeof(T), RB = N * sizeof(T);
+        const unsigned col0 = (o0u * N + (unsigned)(c * VB)) * W;
+        const unsigned safe = col0 + (unsigned)(nl - 1) * RB;
+        const unsigned zb = (unsigned)ny * RB;
+        const char *ub = reinterpret_cast<const char *>(u);
+        auto rowld = [&](Cols<T, NV> &dst, unsigned off, bool ok) {
+            const unsigned o = ok ? off : safe;
+#pragma unroll
+            for (int q = 0; q < NV; ++q) {
+                const VT v = *reinterpret_cast<const VT *>(ub + (o + q * 16u));
+                dst.v[q] = ok ? v : VT{};
+            }
+        };
+        auto eld = [&](unsigned off, bool ok) -> T {
+            const T v = *reinterpret_cast<const T *>(ub + (ok ? off : safe));
+            return ok ? v : T(0);
+        };
         // sliding window over lines lfirst-1 .. lfirst+LG (y neighbours).  The
-        // rows go in chunks of CH: all loads of a chunk are issued (branch-free:
-        // idle lanes read the block's last line) before any of its arithmetic.
-        const VT *vb = reinterpret_cast<const VT *>(qb);
-        VT cur = load_if(vb, lfirst * N / V, live0, last / V);
-        VT prev = load_if(vb, (lfirst - 1) * N / V, live0 && jp[0], last / V);
-        constexpr int CH = LG < 4 ? LG : 4;
+        // rows go in chunks of CH: all loads of a chunk are issued before any of
+        // its arithmetic.
+        Cols<T, NV> cur, prev;
+        rowld(cur, col0 + (unsigned)lfirst * RB, live0);
+        rowld(prev, col0 + (unsigned)lfirst * RB - RB, live0 && jp[0]);
+        constexpr int CH = (LG * NV <= 4) ? LG : (4 / NV > 0 ? 4 / NV : 1);
 #pragma unroll
         for (int c0 = 0; c0 < LG; c0 += CH) {
-            VT nx[CH], zm[CH], zp[CH];
+            Cols<T, NV> nx[CH], zm[CH], zp[CH];
             T el[CH], er[CH];
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const int ll = lfirst + c0 + i;
                 const bool live = ll < nl;
-                const int qo = (ll * N) / V;  // vector offset of this line from qb
+                const unsigned off = col0 + (unsigned)ll * RB;
                 // the next line (y+1 neighbour, or the next plane's first line)
-                nx[i] = load_if(vb, qo + N / V, live && (ll + 1 < nl || o0 + nl < g.nlines), last / V);
+                rowld(nx[i], off + RB, live && (ll + 1 < nl || o0 + nl < g.nlines));
                 if (NDIM == 3) {
-                    zm[i] = load_if(vb, qo - sz / V, live && kp[c0 + i], last / V);
-                    zp[i] = load_if(vb, qo + sz / V, live && kn[c0 + i], last / V);
+                    rowld(zm[i], off - zb, live && kp[c0 + i]);
+                    rowld(zp[i], off + zb, live && kn[c0 + i]);
                 }
-                el[i] = load_if(qb, ll * N - 1, live && lane == 0 && c > 0, last);
-                er[i] = load_if(qb, ll * N + V, live && lane == 63 && c < C - 1, last);
+                if (kEdges) {
+                    el[i] = eld(off - W, live && lane == 0 && c > 0);
+                    er[i] = eld(off + VB * W, live && lane == 63 && c < C - 1);
+                }
             }
             asm volatile("" ::: "memory");  // the chunk's loads stay above its arithmetic
 #pragma unroll
             for (int i = 0; i < CH; ++i) {
                 const int r = c0 + i, ll = lfirst + r;
-                VT acc = (jn[r] ? nx[i] : VT{}) + (jp[r] ? prev : VT{});
-                if (NDIM == 3) acc += zm[i] + zp[i];
-                // x neighbours of the vector's first and last element
-                T left = wave_from_lower_lane<T>(vget<T>(cur, V - 1));
-                T right = wave_from_upper_lane<T>(vget<T>(cur, 0));
-                if (lane == 0) left = el[i];
-                if (lane == 63) right = er[i];
+                // x neighbours of the thread's first and last element
+                T left = wave_from_lower_lane<T>(cur[VB - 1]);
+                T right = wave_from_upper_lane<T>(cur[0]);
+                if (kEdges) {
+                    if (lane == 0) left = el[i];
+                    if (lane == 63) right = er[i];
+                }
                 if (c == 0) left = T(0);
                 if (c == C - 1) right = T(0);
                 // ll < L always (the thread groups tile the block's L lines): rows
                 // past nl are written but never read, so the store needs no branch
-                T *dst = sh + ll * g.ls + ((c * V) / M) * (M + 1) + ((c * V) % M);
+                T *dst = sh + ll * g.ls + ((c * VB) / M) * (M + 1) + ((c * VB) % M);
 #pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    const T xl = e == 0 ? left : vget<T>(cur, e - 1);
-                    const T xr = e == V - 1 ? right : vget<T>(cur, e + 1);
-                    dst[e] = s2 * (vget<T>(acc, e) + xl + xr - T(2 * NDIM) * vget<T>(cur, e));
+                for (int e = 0; e < VB; ++e) {
+                    T acc = (jn[r] ? nx[i][e] : T(0)) + (jp[r] ? prev[e] : T(0));
+                    if (NDIM == 3) acc += zm[i][e] + zp[i][e];
+                    const T xl = e == 0 ? left : cur[e - 1];
+                    const T xr = e == VB - 1 ? right : cur[e + 1];
+                    dst[e] = s2 * (acc + xl + xr - T(2 * NDIM) * cur[e]);
                 }
                 prev = cur;
                 cur = nx[i];

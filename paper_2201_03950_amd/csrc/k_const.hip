@@ -289,7 +289,8 @@ hipError_t launch_const_lines(const LineReq &r, int M, hipStream_t s) {
 
 int const_rhs_M(const AdiReq &r) {
     if (r.s) return 0;
-    if (r.nx * r.ny * r.nz * r.batch >= ((i64)1 << 31)) return 0;  // 32-bit line indices
+    // 32-bit line indices and 32-bit byte offsets
+    if (r.nx * r.ny * r.nz * r.batch * (r.f64 ? 8 : 4) >= ((i64)1 << 32)) return 0;
     const int M = const_staged_M(r.nx, r.f64 ? 8 : 4, r.force_M);
     if (!M) return 0;
     const int V = r.f64 ? 2 : 4;
