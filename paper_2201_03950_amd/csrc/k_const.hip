@@ -174,13 +174,16 @@ hipError_t go_strided(const LineReq &r, const ConstTab<T> &tb, Epi epi, hipStrea
 }
 
 template <typename T, int M, int P, class Src>
-hipError_t go_dpp(i64 nlines, int n, const PcrTab<T> &tb, Src src, T *out, hipStream_t s) {
+hipError_t go_dpp(i64 nlines, int n, const PcrTab<T> &tb, Src src, T *out, int force_L, hipStream_t s) {
     ConstStagedGeom g;
     g.nlines = nlines;
     g.n = n;
     // 128-thread blocks for FP64 (measured faster than 256 on the 256^3 step),
-    // 256 for FP32; the staging needs threads >= n / vector width
-    const int nt = (sizeof(T) == 8 && n / 2 <= 128) ? 128 : 256;
+    // 256 for FP32.  A forced line count is taken when the block stays a whole
+    // number of wavefronts of at most 256 threads (the staging maps a line row
+    // onto at most one wavefront).
+    int nt = (sizeof(T) == 8 && n / 2 <= 128) ? 128 : 256;
+    if (force_L > 0 && force_L * P <= 256 && (force_L * P) % 64 == 0) nt = force_L * P;
     g.L = nt / P;
     g.ls = P * (M + 1);
     const size_t shm = (size_t)g.L * g.ls * sizeof(T) + (size_t)g.L * sizeof(int);
@@ -190,26 +193,26 @@ hipError_t go_dpp(i64 nlines, int n, const PcrTab<T> &tb, Src src, T *out, hipSt
 }
 
 template <typename T, int M, class Src>
-hipError_t go_dpp_p(i64 nlines, int n, const PcrTab<T> &tb, int P, Src src, T *out, hipStream_t s) {
+hipError_t go_dpp_p(i64 nlines, int n, const PcrTab<T> &tb, int P, Src src, T *out, int fl, hipStream_t s) {
     switch (P) {
-        case 1: return go_dpp<T, M, 1>(nlines, n, tb, src, out, s);
-        case 2: return go_dpp<T, M, 2>(nlines, n, tb, src, out, s);
-        case 4: return go_dpp<T, M, 4>(nlines, n, tb, src, out, s);
-        case 8: return go_dpp<T, M, 8>(nlines, n, tb, src, out, s);
-        case 16: return go_dpp<T, M, 16>(nlines, n, tb, src, out, s);
+        case 1: return go_dpp<T, M, 1>(nlines, n, tb, src, out, fl, s);
+        case 2: return go_dpp<T, M, 2>(nlines, n, tb, src, out, fl, s);
+        case 4: return go_dpp<T, M, 4>(nlines, n, tb, src, out, fl, s);
+        case 8: return go_dpp<T, M, 8>(nlines, n, tb, src, out, fl, s);
+        case 16: return go_dpp<T, M, 16>(nlines, n, tb, src, out, fl, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 // Staged x lines with constant rows: PcrTab + DPP kernel.
 template <typename T, class Src>
-hipError_t staged_dpp(double a, double b, double c, int M, i64 nlines, int n, Src src, T *out,
+hipError_t staged_dpp(double a, double b, double c, int M, i64 nlines, int n, Src src, T *out, int force_L,
                       hipStream_t s) {
     PcrTab<T> tb;
     const int P = n / M;
     if (!make_pcr_tab<T>(a, b, c, M, P, &tb)) return hipErrorInvalidValue;
-    return M == 32 ? go_dpp_p<T, 32>(nlines, n, tb, P, src, out, s)
-                   : go_dpp_p<T, 16>(nlines, n, tb, P, src, out, s);
+    return M == 32 ? go_dpp_p<T, 32>(nlines, n, tb, P, src, out, force_L, s)
+                   : go_dpp_p<T, 16>(nlines, n, tb, P, src, out, force_L, s);
 }
 
 template <typename T>
@@ -244,7 +247,7 @@ template <typename T>
 hipError_t lines_typed(const LineReq &r, int M, hipStream_t s) {
     if (r.inner == 1) {
         CStgCopy<T> src{static_cast<const T *>(r.d)};
-        return staged_dpp<T>(r.ca, r.cb, r.cc, M, r.outer, (int)r.n, src, static_cast<T *>(r.x), s);
+        return staged_dpp<T>(r.ca, r.cb, r.cc, M, r.outer, (int)r.n, src, static_cast<T *>(r.x), r.force_L, s);
     }
     ConstTab<T> tb;
     if (!make_const_tab<T>(r.ca, r.cb, r.cc, M, (int)(r.n / M), &tb)) return hipErrorInvalidValue;
@@ -262,10 +265,10 @@ hipError_t rhs_typed(const AdiReq &r, int M, hipStream_t s) {
     const double a = -r.s0, b = 1.0 + 2.0 * r.s0, c = -r.s0;
     if (r.ndim == 3) {
         CStgRhs<T, 3> src{u, (T)(2.0 * r.s0), (int)r.ny, (int)r.nz};
-        return staged_dpp<T>(a, b, c, M, nlines, (int)r.nx, src, out, s);
+        return staged_dpp<T>(a, b, c, M, nlines, (int)r.nx, src, out, r.force_L, s);
     }
     CStgRhs<T, 2> src{u, (T)(2.0 * r.s0), (int)r.ny, 1};
-    return staged_dpp<T>(a, b, c, M, nlines, (int)r.nx, src, out, s);
+    return staged_dpp<T>(a, b, c, M, nlines, (int)r.nx, src, out, r.force_L, s);
 }
 
 }  // namespace
