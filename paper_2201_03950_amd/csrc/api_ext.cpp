@@ -19,6 +19,15 @@
 
 namespace trid {
 
+LaunchEvents &launch_events() {
+    thread_local LaunchEvents ev;
+    return ev;
+}
+
+}  // namespace trid
+
+namespace trid {
+
 void ExtState::release() {
     timer.release();
     if (ws2) hipFree(ws2);
@@ -362,7 +371,7 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
         if (e != hipSuccess) return trid::handle_hip_fail(h, e, "hipGraphInstantiate");
         git = sc.graphs.emplace(gkey, exec).first;
     }
-    e = xs.timer.time("varlen", st, [&] { return hipGraphLaunch(git->second, st); });
+    e = xs.timer.time_recorded("varlen", st, [&] { return hipGraphLaunch(git->second, st); });
     if (e != hipSuccess) return trid::handle_hip_fail(h, e, "uneven batch: launch");
     return TRID_OK;
 }

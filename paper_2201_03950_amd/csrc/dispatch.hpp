@@ -2,6 +2,7 @@
 // launch entry points implemented by the kernel translation units.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,6 +26,31 @@ enum class Out {
     AdjArrays,  // g = lambda; ga, gb, gc = coefficient gradients
     AdjS        // g = lambda; gs += lambda * second difference of xf
 };
+
+// Kernel launch used by every entry point.  When a per-kernel timer has armed
+// a pair of events for this thread (and the stream is not being captured),
+// the dispatch itself stamps the kernel's start and end into them
+// (hipExtLaunchKernel), so a timed kernel's duration excludes the queue gaps
+// that separately recorded events would include.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+    bool used = false;
+};
+LaunchEvents &launch_events();  // this thread's armed pair (defined with the timer)
+
+template <typename... Args, typename F = void (*)(Args...)>
+inline void launch(F kernel, dim3 grid, dim3 block, size_t shmem, hipStream_t s, Args... args) {
+    LaunchEvents &ev = launch_events();
+    if (ev.start) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            hipExtLaunchKernelGGL(kernel, grid, block, (std::uint32_t)shmem, s, ev.start, ev.stop, 0u, args...);
+            ev.used = true;
+            return;
+        }
+    }
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+}
 
 // Tile plan of a launch: M rows per tile, P tiles per line, L lines per block.
 struct LinePlan {

@@ -18,9 +18,12 @@ namespace trid {
 
 struct VarlenSchedule;  // defined with the uneven-batch solver
 
-// Optional per-kernel timing: when on, every launch made outside graph capture
-// is bracketed by two HIP events recorded on the launch stream; flush()
-// waits for them and accumulates (count, milliseconds) per kernel name.
+// Optional per-kernel timing.  When on, time() arms a pair of events that the
+// next kernel launch on this thread stamps from its own dispatch (start and
+// end of the kernel, see launch()); time_recorded() brackets work that is not
+// a direct kernel launch (a graph launch) with two events recorded on the
+// stream.  flush() waits for them and accumulates (count, milliseconds) per
+// name.  Launches under graph capture are not timed.
 struct KernelTimer {
     bool on = false;
     struct Pending {
@@ -41,9 +44,31 @@ struct KernelTimer {
         if (hipEventCreate(&e) != hipSuccess) return nullptr;
         return e;
     }
-    // Runs f() (which enqueues one kernel on st) between two events.
+    // f() enqueues one kernel through launch() on st.
     template <class F>
     hipError_t time(const char *name, hipStream_t st, F &&f) {
+        (void)st;
+        if (!on) return f();
+        hipEvent_t e0 = take(), e1 = take();
+        if (!e0 || !e1) return f();
+        LaunchEvents &ev = launch_events();
+        ev.start = e0;
+        ev.stop = e1;
+        ev.used = false;
+        hipError_t e = f();
+        const bool used = ev.used;
+        ev = LaunchEvents{};
+        if (used) {
+            pending.push_back({name, e0, e1});
+        } else {
+            pool.push_back(e0);
+            pool.push_back(e1);
+        }
+        return e;
+    }
+    // f() enqueues work on st that is not a direct kernel launch.
+    template <class F>
+    hipError_t time_recorded(const char *name, hipStream_t st, F &&f) {
         if (!on) return f();
         hipEvent_t e0 = take(), e1 = take();
         if (!e0 || !e1) return f();

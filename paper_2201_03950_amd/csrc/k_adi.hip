@@ -215,7 +215,7 @@ hipError_t go(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
             raised = true;
         }
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g,
+    launch(kern, dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g,
                        static_cast<const T *>(r.u), static_cast<const T *>(r.s), (T)r.s0,
                        static_cast<T *>(r.d));
     return hipGetLastError();

@@ -62,7 +62,7 @@ hipError_t go(const StencilAdjReq &r, hipStream_t st) {
     const int cpl = (int)((r.nx + bd - 1) / bd);
     const i64 nb = lines * cpl;
     if (nb >= ((i64)1 << 31)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_stencil_adjoint<T, NDIM>), dim3((unsigned)nb), dim3(bd), 0, st,
+    launch((k_stencil_adjoint<T, NDIM>), dim3((unsigned)nb), dim3(bd), 0, st,
                        static_cast<const T *>(r.u), static_cast<const T *>(r.s), static_cast<const T *>(r.rbar),
                        static_cast<T *>(r.ubar), static_cast<T *>(r.sbar), (int)r.nx, (int)r.ny, (int)r.nz, cpl);
     return hipGetLastError();

@@ -168,7 +168,7 @@ hipError_t go_strided(const LineReq &r, const ConstTab<T> &tb, Epi epi, hipStrea
     g.L = 64;
     g.P = tb.P;
     const i64 nb = g.nib * r.outer;
-    hipLaunchKernelGGL((k_strided_const<T, M, Epi>), dim3((unsigned)nb), dim3(64 * tb.P), 0, s, g, tb,
+    launch((k_strided_const<T, M, Epi>), dim3((unsigned)nb), dim3(64 * tb.P), 0, s, g, tb,
                        static_cast<const T *>(r.d), epi);
     return hipGetLastError();
 }
@@ -187,7 +187,7 @@ hipError_t go_dpp(i64 nlines, int n, const PcrTab<T> &tb, Src src, T *out, int f
     g.L = nt / P;
     g.ls = P * (M + 1);
     const size_t shm = (size_t)g.L * g.ls * sizeof(T) + (size_t)g.L * sizeof(int);
-    hipLaunchKernelGGL((k_staged_dpp<T, M, P, Src>), dim3((unsigned)cdiv(nlines, g.L)), dim3(g.L * P),
+    launch((k_staged_dpp<T, M, P, Src>), dim3((unsigned)cdiv(nlines, g.L)), dim3(g.L * P),
                        shm, s, g, tb, src, out);
     return hipGetLastError();
 }

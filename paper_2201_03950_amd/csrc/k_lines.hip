@@ -140,7 +140,7 @@ hipError_t go_strided(const LineReq &r, const LinePlan &pl, Src src, Epi epi, hi
     g.L = pl.L;
     g.P = pl.P;
     constexpr int MAXT = strided_max_threads(M, (int)sizeof(T), Epi::kWide);
-    hipLaunchKernelGGL((k_strided<T, M, MAXT, Src, Epi>), dim3((unsigned)pl.nblocks),
+    launch((k_strided<T, M, MAXT, Src, Epi>), dim3((unsigned)pl.nblocks),
                        dim3(pl.threads()), pl.shmem, s, g, src, epi);
     return hipGetLastError();
 }
@@ -164,7 +164,7 @@ hipError_t go_staged(const LineReq &r, const LinePlan &pl, Src src, hipStream_t 
     g.P = pl.P;
     g.ls = pl.ls;
     StgOut<T> out{static_cast<T *>(r.x)};
-    hipLaunchKernelGGL((k_staged<T, M, kStagedMaxThreads, Src, StgOut<T>>),
+    launch((k_staged<T, M, kStagedMaxThreads, Src, StgOut<T>>),
                        dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g, src, out);
     return hipGetLastError();
 }
@@ -188,7 +188,7 @@ hipError_t go_staged_adj_s(const LineReq &r, const LinePlan &pl, hipStream_t s) 
     g.P = pl.P;
     g.ls = pl.ls;
     const T *grhs = static_cast<const T *>(r.d ? r.d : r.g);
-    hipLaunchKernelGGL((k_staged_adj_s<T, M>), dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g,
+    launch((k_staged_adj_s<T, M>), dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g,
                        static_cast<const T *>(r.s), grhs, static_cast<const T *>(r.xf), static_cast<T *>(r.g),
                        static_cast<T *>(r.gs));
     return hipGetLastError();

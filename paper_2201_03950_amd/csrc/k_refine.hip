@@ -155,7 +155,7 @@ hipError_t go_strided(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
     g.L = pl.L;
     g.P = pl.P;
     constexpr int MAXT = refine_strided_maxt(M, SM);
-    hipLaunchKernelGGL((k_refine_strided<TD, M, SM, MAXT>), dim3((unsigned)pl.nblocks), dim3(pl.L * pl.P),
+    launch((k_refine_strided<TD, M, SM, MAXT>), dim3((unsigned)pl.nblocks), dim3(pl.L * pl.P),
                        pl.shmem, s, g, r.src, static_cast<const TD *>(r.d), r.x);
     return hipGetLastError();
 }
@@ -168,7 +168,7 @@ hipError_t go_staged(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
     g.L = pl.L;
     g.P = pl.P;
     g.ls = pl.ls;
-    hipLaunchKernelGGL((k_refine_staged<TD, M, SM>), dim3((unsigned)pl.nblocks), dim3(pl.L * pl.P),
+    launch((k_refine_staged<TD, M, SM>), dim3((unsigned)pl.nblocks), dim3(pl.L * pl.P),
                        pl.shmem, s, g, r.src, static_cast<const TD *>(r.d), r.x);
     return hipGetLastError();
 }

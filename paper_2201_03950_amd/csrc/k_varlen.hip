@@ -20,6 +20,7 @@
 #include <numeric>
 #include <vector>
 
+#include "dispatch.hpp"
 #include "refine_tile.hpp"
 #include "varlen.hpp"
 
@@ -284,7 +285,7 @@ int occupancy_blocks(K kernel, int nt, size_t lds) {
 template <typename K>
 hipError_t launch_persistent(K kernel, int nt, size_t lds, const VarlenSchedule &sc, const VarlenArgs &g,
                              hipStream_t s) {
-    hipLaunchKernelGGL(kernel, dim3((unsigned)sc.nblocks), dim3(nt), lds, s, g);
+    launch(kernel, dim3((unsigned)sc.nblocks), dim3(nt), lds, s, g);
     return hipGetLastError();
 }
 
