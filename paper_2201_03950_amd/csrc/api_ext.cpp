@@ -297,13 +297,28 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
         for (const auto &v : trid::varlen_variants(p))
             if (trid::varlen_variant_fits(v, maxlen)) cands.push_back(v);
         if (cands.empty()) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "no tile plan fits the longest system");
+        // split plans: systems longer than a 256-thread block of 8-row tiles
+        // holds run with a big-block variant, the rest with 256-thread blocks
+        // (several per CU)
+        const trid::VarlenVariant small{8, 256};
+        struct Plan {
+            trid::VarlenVariant v;
+            bool split;
+        };
+        std::vector<Plan> plans;
+        for (const auto &v : cands) plans.push_back({v, false});
+        if (maxlen > (int64_t)small.M * small.NT)
+            for (const auto &v : cands)
+                if (v.NT > small.NT) plans.push_back({v, true});
         auto tuned = xs.tuned.find(pkey);
-        const bool tune = autotune_requested() && cands.size() > 1;
+        auto tuned_small = xs.tuned.find(pkey + "/small");
+        const bool tune = autotune_requested() && plans.size() > 1;
         trid::VarlenSchedule *best = nullptr;
         if (tune) {
-            for (const auto &v : cands) {
+            bool best_split = false;
+            for (const auto &pl : plans) {
                 auto *sc = new trid::VarlenSchedule();
-                hipError_t e = trid::varlen_build(off, nsys, p, v, sc);
+                hipError_t e = trid::varlen_build(off, nsys, p, pl.v, sc, pl.split ? &small : nullptr);
                 float us = 0.f;
                 if (e == hipSuccess) e = time_schedule(*sc, a, b, c, d, x, st, &us);
                 if (e != hipSuccess) {
@@ -322,19 +337,26 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
                         delete best;
                     }
                     best = sc;
+                    best_split = pl.split;
                 } else {
                     trid::varlen_free(sc);
                     delete sc;
                 }
             }
             xs.tuned[pkey] = {best->M, best->NT};
+            if (best_split)
+                xs.tuned[pkey + "/small"] = {small.M, small.NT};
+            else
+                xs.tuned.erase(pkey + "/small");
         } else {
             trid::VarlenVariant v = cands.front();
             if (tuned != xs.tuned.end())
                 for (const auto &c2 : cands)
                     if (c2.M == tuned->second.first && c2.NT == tuned->second.second) v = c2;
+            const bool split = tuned_small != xs.tuned.end() && tuned_small->second.first == small.M &&
+                               tuned_small->second.second == small.NT && maxlen > (int64_t)small.M * small.NT;
             best = new trid::VarlenSchedule();
-            hipError_t e = trid::varlen_build(off, nsys, p, v, best);
+            hipError_t e = trid::varlen_build(off, nsys, p, v, best, split ? &small : nullptr);
             if (e != hipSuccess) {
                 trid::varlen_free(best);
                 delete best;

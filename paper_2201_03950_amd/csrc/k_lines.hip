@@ -58,6 +58,9 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
     // whenever a block can hold the line that way
     const bool adj_x = adj_s && r.inner == 1 && !r.force_strided && cdiv(r.n, 8) <= kStagedMaxThreads;
     int M = r.force_M ? r.force_M : ((r.f64 || adj_x) ? 8 : 16);
+    // FP64 coefficient arrays on strided lines: 16-row tiles (fewer reduced-solve
+    // levels for the four input streams; measured 8-12% faster than 8 rows)
+    if (!r.force_M && r.f64 && r.mode == Mode::Arrays && r.inner > 1) M = 16;
     if (M != 8 && M != 16 && M != 32) {
         *err = "tile size must be 8, 16 or 32";
         return false;

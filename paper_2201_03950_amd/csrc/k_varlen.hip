@@ -293,9 +293,9 @@ hipError_t launch_persistent(K kernel, int nt, size_t lds, const VarlenSchedule 
 
 // The (M, NT) variants compiled for each precision.
 const std::vector<VarlenVariant> &varlen_variants(int prec) {
-    static const std::vector<VarlenVariant> f64 = {{8, 1024}, {16, 512}, {32, 256}};
-    static const std::vector<VarlenVariant> f32 = {{8, 1024}, {16, 512}, {32, 256}};
-    static const std::vector<VarlenVariant> ref = {{8, 1024}, {16, 512}, {32, 256}};
+    static const std::vector<VarlenVariant> f64 = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}};
+    static const std::vector<VarlenVariant> f32 = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}};
+    static const std::vector<VarlenVariant> ref = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}};
     return prec == 0 ? f64 : (prec == 1 ? f32 : ref);
 }
 
@@ -309,6 +309,8 @@ auto with_kernel(int prec, int M, int NT, F &&f) -> decltype(f(k_varlen_refine<1
             return f(k_varlen_refine<8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 1024 * (16 + 24)));
         if (M == 16 && NT == 512)
             return f(k_varlen_refine<16, 512>, 512, varlen_lds_bytes<16, 512>(8, 512 * (16 + 24)));
+        if (M == 8 && NT == 256)
+            return f(k_varlen_refine<8, 256>, 256, varlen_lds_bytes<8, 256>(8, 256 * (16 + 24)));
         return f(k_varlen_refine<32, 256>, 256, varlen_lds_bytes<32, 256>(8, 256 * (16 + 24)));
     }
     if (prec == 0) {
@@ -316,12 +318,16 @@ auto with_kernel(int prec, int M, int NT, F &&f) -> decltype(f(k_varlen_refine<1
             return f(k_varlen_plain<double, 16, 512>, 512, varlen_lds_bytes<16, 512>(8, 6 * 512 * 8));
         if (M == 8 && NT == 1024)
             return f(k_varlen_plain<double, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 6 * 1024 * 8));
+        if (M == 8 && NT == 256)
+            return f(k_varlen_plain<double, 8, 256>, 256, varlen_lds_bytes<8, 256>(8, 6 * 256 * 8));
         return f(k_varlen_plain<double, 32, 256>, 256, varlen_lds_bytes<32, 256>(8, 6 * 256 * 8));
     }
     if (M == 16 && NT == 512)
         return f(k_varlen_plain<float, 16, 512>, 512, varlen_lds_bytes<16, 512>(4, 6 * 512 * 4));
     if (M == 8 && NT == 1024)
         return f(k_varlen_plain<float, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(4, 6 * 1024 * 4));
+    if (M == 8 && NT == 256)
+        return f(k_varlen_plain<float, 8, 256>, 256, varlen_lds_bytes<8, 256>(4, 6 * 256 * 4));
     return f(k_varlen_plain<float, 32, 256>, 256, varlen_lds_bytes<32, 256>(4, 6 * 256 * 4));
 }
 
@@ -329,14 +335,18 @@ auto with_kernel(int prec, int M, int NT, F &&f) -> decltype(f(k_varlen_refine<1
 
 bool varlen_variant_fits(const VarlenVariant &v, i64 maxlen) { return (maxlen + v.M - 1) / v.M <= v.NT; }
 
-hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const VarlenVariant &v,
-                        VarlenSchedule *sc) {
+namespace {
+
+// Schedule of the systems `ids` (packed longest first into work items of at
+// most NT tiles) for variant v.
+hipError_t build_ids(const int64_t *offsets_host, std::vector<int> ids, int prec, const VarlenVariant &v,
+                     VarlenSchedule *sc) {
+    const i64 nsys = (i64)ids.size();
     sc->prec = prec;
     sc->M = v.M;
     sc->NT = v.NT;
     sc->nsys = nsys;
-    std::vector<int> order(nsys);
-    std::iota(order.begin(), order.end(), 0);
+    std::vector<int> &order = ids;
     std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
         return offsets_host[i + 1] - offsets_host[i] > offsets_host[j + 1] - offsets_host[j];
     });
@@ -359,7 +369,9 @@ hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const V
     item_pmax.push_back(pmax);
     sc->nitems = (int)item_pmax.size();
     // one device allocation: off | order | tstart | item_begin | item_pmax | counter
-    const size_t b_off = sizeof(i64) * (nsys + 1), b_ord = sizeof(int) * nsys, b_ts = sizeof(int) * nsys;
+    // (off holds every system's offsets; order names the systems of this schedule)
+    const i64 nall = 1 + *std::max_element(order.begin(), order.end());
+    const size_t b_off = sizeof(i64) * (nall + 1), b_ord = sizeof(int) * nsys, b_ts = sizeof(int) * nsys;
     const size_t b_ib = sizeof(int) * item_begin.size(), b_ip = sizeof(int) * item_pmax.size();
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t total = up(b_off) + up(b_ord) + up(b_ts) + up(b_ib) + up(b_ip) + 256;
@@ -391,6 +403,24 @@ hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const V
     return hipSuccess;
 }
 
+}  // namespace
+
+hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const VarlenVariant &v, VarlenSchedule *sc,
+                        const VarlenVariant *small) {
+    std::vector<int> all(nsys);
+    std::iota(all.begin(), all.end(), 0);
+    if (!small) return build_ids(offsets_host, all, prec, v, sc);
+    const i64 cap = (i64)small->M * small->NT;  // longest system the small-block variant holds
+    std::vector<int> lng, shr;
+    for (int k : all) (offsets_host[k + 1] - offsets_host[k] > cap ? lng : shr).push_back(k);
+    if (lng.empty()) return build_ids(offsets_host, shr, prec, *small, sc);
+    if (shr.empty()) return build_ids(offsets_host, lng, prec, v, sc);
+    hipError_t e = build_ids(offsets_host, lng, prec, v, sc);
+    if (e != hipSuccess) return e;
+    sc->next = new VarlenSchedule();
+    return build_ids(offsets_host, shr, prec, *small, sc->next);
+}
+
 hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b, const void *c, const void *d,
                          void *x, hipStream_t s) {
     VarlenArgs g;
@@ -406,15 +436,22 @@ hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b,
     g.item_pmax = sc.item_pmax;
     g.counter = sc.counter;
     g.nitems = sc.nitems;
-    return with_kernel(sc.prec, sc.M, sc.NT,
-                       [&](auto k, int nt, size_t lds) { return launch_persistent(k, nt, lds, sc, g, s); });
+    hipError_t e = with_kernel(sc.prec, sc.M, sc.NT,
+                               [&](auto k, int nt, size_t lds) { return launch_persistent(k, nt, lds, sc, g, s); });
+    if (e != hipSuccess || !sc.next) return e;
+    return varlen_launch(*sc.next, a, b, c, d, x, s);
 }
 
 void varlen_free(VarlenSchedule *sc) {
-    for (auto &kv : sc->graphs) hipGraphExecDestroy(kv.second);
+    for (auto &kv : sc->graphs) (void)hipGraphExecDestroy(kv.second);
     sc->graphs.clear();
-    if (sc->dev) hipFree(sc->dev);
+    if (sc->dev) (void)hipFree(sc->dev);
     sc->dev = nullptr;
+    if (sc->next) {
+        varlen_free(sc->next);
+        delete sc->next;
+        sc->next = nullptr;
+    }
 }
 
 }  // namespace trid

@@ -67,7 +67,10 @@ __device__ __forceinline__ void refine_tile(const RefCoef<M, SM> &cf, const doub
         TileState<float, M> ts;
         tile_eliminate_fn<float, M>(rows, rd, ts);
         float f, lv;
-        reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv, Pu);
+        if (Pu)  // lines of different lengths share the block (uneven batch)
+            reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv, Pu);
+        else
+            reduced_solve<float, M>(ts, red, S, P, p, slot, pstride, f, lv);
         tile_backsub<float, M>(ts, f, lv, x32);
     }
     // neighbours of the tile's first and last rows for the residual
@@ -90,7 +93,10 @@ __device__ __forceinline__ void refine_tile(const RefCoef<M, SM> &cf, const doub
         TileState<float, M> ts;
         tile_eliminate_fn<float, M>(rows, rd, ts);
         float f, lv;
-        reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv, Pu);
+        if (Pu)  // lines of different lengths share the block (uneven batch)
+            reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv, Pu);
+        else
+            reduced_solve<float, M>(ts, red, S, P, p, slot, pstride, f, lv);
         tile_backsub<float, M>(ts, f, lv, dx);
     }
 #pragma unroll

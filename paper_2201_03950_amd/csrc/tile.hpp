@@ -276,10 +276,52 @@ __device__ __forceinline__ void reduced_pcr_dpp(const TileState<T, M> &ts, int p
     lv = ts.ld - ts.la * f - ts.lc * fn;
 }
 
-// Reduced solve dispatch: the DPP form when the line's tiles are adjacent
-// lanes (pstride 1, slot = line * P + p) and P is a power of two <= 16 (a
-// uniform choice: P is the same for the whole launch); reduced_pcr otherwise.
-// Callers must not rely on a barrier inside (the DPP form has none).
+// Same reduced solve for a line of 32 or 64 tiles in adjacent lanes of one
+// wavefront: neighbours at any stride come through the LDS crossbar
+// (ds_bpermute) within the wavefront -- no LDS storage, no barrier.
+template <typename T>
+__device__ __forceinline__ T lane_up(T v, int s) {  // value of lane - s
+    return __shfl_up(v, (unsigned)s, 64);
+}
+template <typename T>
+__device__ __forceinline__ T lane_down(T v, int s) {  // value of lane + s
+    return __shfl_down(v, (unsigned)s, 64);
+}
+
+template <typename T, int M, int P>
+__device__ __forceinline__ void reduced_pcr_wave(const TileState<T, M> &ts, int p, T &f, T &lv) {
+    T pa = lane_up(ts.la, 1), pc = lane_up(ts.lc, 1), pd = lane_up(ts.ld, 1);
+    if (p == 0) pa = pc = pd = T(0);
+    const T gsub = -ts.fa * pa;
+    const T gdia = ts.fb - ts.fa * pc - ts.fc * ts.la;
+    const T gsup = -ts.fc * ts.lc;
+    const T grhs = ts.fd - ts.fa * pd - ts.fc * ts.ld;
+    const T rg = fast_rcp(gdia);
+    T a = gsub * rg, c = gsup * rg, d = grhs * rg;
+#pragma unroll
+    for (int S = 1; S < P; S <<= 1) {
+        T am = lane_up(a, S), cm = lane_up(c, S), dm = lane_up(d, S);
+        T an = lane_down(a, S), cn = lane_down(c, S), dn = lane_down(d, S);
+        if (p < S) am = cm = dm = T(0);
+        if (p + S >= P) an = cn = dn = T(0);
+        const T r = fast_rcp(T(1) - a * cm - c * an);
+        const T na = -r * (a * am);
+        const T nc = -r * (c * cn);
+        d = r * (d - a * dm - c * dn);
+        a = na;
+        c = nc;
+    }
+    f = d;
+    T fn = lane_down(f, 1);
+    if (p + 1 >= P) fn = T(0);
+    lv = ts.ld - ts.la * f - ts.lc * fn;
+}
+
+// Reduced solve dispatch (a uniform choice: P is the same for the whole
+// launch).  With the line's tiles in adjacent lanes (pstride 1, slot = line *
+// P + p): DPP row shifts for P a power of two <= 16, wavefront lane moves for
+// P = 32 or 64 (a line never straddles two wavefronts); reduced_pcr otherwise.
+// Callers must not rely on a barrier inside (the lane forms have none).
 template <typename T, int M>
 __device__ __forceinline__ void reduced_solve(const TileState<T, M> &ts, T *__restrict__ sh, int S, int P,
                                               int p, int slot, int pstride, T &f, T &lv) {
@@ -290,6 +332,8 @@ __device__ __forceinline__ void reduced_solve(const TileState<T, M> &ts, T *__re
             case 4: reduced_pcr_dpp<T, M, 4>(ts, p, f, lv); return;
             case 8: reduced_pcr_dpp<T, M, 8>(ts, p, f, lv); return;
             case 16: reduced_pcr_dpp<T, M, 16>(ts, p, f, lv); return;
+            case 32: reduced_pcr_wave<T, M, 32>(ts, p, f, lv); return;
+            case 64: reduced_pcr_wave<T, M, 64>(ts, p, f, lv); return;
             default: break;
         }
     }

@@ -27,6 +27,9 @@ struct VarlenSchedule {
     int *order = nullptr, *tstart = nullptr, *item_begin = nullptr, *item_pmax = nullptr;
     int *counter = nullptr;
     float tuned_us = 0.f;  // measured time when chosen by the autotuner
+    // split schedule: the systems too long for a small-block variant run in
+    // this launch, the rest in `next` (launched right after, same arrays)
+    VarlenSchedule *next = nullptr;
     // captured launches keyed by (a, b, c, d, x, stream)
     std::map<std::tuple<const void *, const void *, const void *, const void *, void *, hipStream_t>,
              hipGraphExec_t>
@@ -35,7 +38,10 @@ struct VarlenSchedule {
 
 const std::vector<VarlenVariant> &varlen_variants(int prec);
 bool varlen_variant_fits(const VarlenVariant &v, i64 maxlen);
-hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const VarlenVariant &v, VarlenSchedule *sc);
+// Schedule for all systems with variant v; with `small` given, the systems of at
+// most small.M * small.NT rows go to a second launch with that variant.
+hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const VarlenVariant &v, VarlenSchedule *sc,
+                        const VarlenVariant *small = nullptr);
 hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b, const void *c, const void *d,
                          void *x, hipStream_t s);
 void varlen_free(VarlenSchedule *sc);

@@ -104,3 +104,48 @@ def test_varlen_autotune_and_plan_cache(trid, orc, tmp_path, monkeypatch):
     trid.plan_load(str(path))
     with pytest.raises(trid.TridError):
         trid.plan_load(str(tmp_path / "missing.json"))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "refine"])
+def test_varlen_split_plan_matches_oracle(trid, orc, tmp_path, monkeypatch, prec):
+    """A split plan (systems above 2048 rows in 1024-thread blocks, the rest in
+    256-thread blocks, two launches), forced through the plan cache of a fresh handle."""
+    import json
+    import threading
+
+    a32, b32, c32, d64, off = gen.varlen_batch(1500, 32, 8192, seed=41)
+    p = {"f64": trid.PREC_F64, "f32": trid.PREC_F32, "refine": trid.PREC_F32_REFINE64}[prec]
+    d_in = d64.astype(np.float32).astype(np.float64) if prec == "f32" else d64
+    ref = orc.gtsv_varlen(a32, b32, c32, d_in, off)
+    a, b, c, d, x = _run(trid, p, a32, b32, c32, d64)
+    monkeypatch.setenv("TRID_AUTOTUNE", "1")
+    trid.gtsv_varlen(p, a, b, c, d, x, off)  # autotuned on this thread's handle: learn the plan key
+    monkeypatch.delenv("TRID_AUTOTUNE")
+    saved = tmp_path / "tuned.json"
+    trid.plan_save(str(saved))
+    key = next(k for k in json.loads(saved.read_text())["plans"] if k.startswith("varlen/") and "/small" not in k)
+    forced = tmp_path / "split.json"
+    forced.write_text('{\n "plans": {\n  "%s": {"M": 8, "NT": 1024},\n  "%s/small": {"M": 8, "NT": 256}\n }\n}\n'
+                      % (key, key))
+    out = {}
+
+    def worker():  # a new thread gets a new library handle (empty schedule cache)
+        try:
+            trid.plan_load(str(forced))
+            xs = [torch.zeros_like(x) for _ in range(2)]
+            for xi in xs:
+                trid.gtsv_varlen(p, a, b, c, d, xi, off)
+            torch.cuda.synchronize()
+            out["x"] = xs
+        except Exception as e:  # re-raised on the test thread
+            out["err"] = e
+
+    th = threading.Thread(target=worker)
+    th.start()
+    th.join()
+    if "err" in out:
+        raise out["err"]
+    x1, x2 = out["x"]
+    tol = {"f64": 1e-12, "f32": 1e-5, "refine": 1e-9}[prec]
+    assert _sys_err(x1.cpu().numpy().astype(np.float64), ref, off) <= tol
+    assert torch.equal(x1, x2)
