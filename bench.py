@@ -309,10 +309,14 @@ def extra_varlen(trid):
 
 
 def extra_gradient(trid):
-    """Differentiable 3D ADI, 128^3, 20 steps, s = 0.2 kappa: forward vs forward+backward."""
+    """Differentiable 3D ADI, 128^3, 20 steps, s = 0.2 kappa: forward vs forward+backward.
+
+    Two reverse-pass modes: intermediates kept by the forward steps (default),
+    or one checkpoint per step with the step recomputed in the reverse pass."""
     import numpy as np
     import torch
 
+    from paper_2201_03950_amd import _binding as B
     from paper_2201_03950_amd import autograd
     from workloads import gen
 
@@ -320,17 +324,17 @@ def extra_gradient(trid):
     steps, s0 = 20, 0.2
     tk, tu, tks = (torch.from_numpy(v).cuda() for v in (kappa, u0, kstar))
     with torch.no_grad():
-        target = autograd.adi(tu, s0 * tks, steps)
+        target = autograd.adi(tu, s0 * tks, steps, False)
 
     def fwd():
         with torch.no_grad():
-            uT = autograd.adi(tu, s0 * tk, steps)
+            uT = autograd.adi(tu, s0 * tk, steps, False)
             return torch.sum((uT.double() - target.double()) ** 2)
 
-    def fwd_bwd():
+    def fwd_bwd(keep):
         k = tk.clone().requires_grad_(True)
         u = tu.clone().requires_grad_(True)
-        uT = autograd.adi(u, s0 * k, steps)
+        uT = autograd.adi(u, s0 * k, steps, keep)
         loss = torch.sum((uT.double() - target.double()) ** 2)
         loss.backward()
         return k.grad
@@ -340,31 +344,33 @@ def extra_gradient(trid):
     fwd()
     fwd_kernels = {k: round(ms / c * 1e3, 2) for k, (c, ms) in trid.timing_read().items()}  # us per launch
     trid.timing_enable(False)
-    tb = time_calls(fwd_bwd, 3, warm=1)
-    # the reverse pass's kernels, launched from this thread (autograd runs its
+    tb_keep = time_calls(lambda: fwd_bwd(True), 3, warm=1)
+    tb_rec = time_calls(lambda: fwd_bwd(False), 3, warm=1)
+    # the kept-mode kernels, launched from this thread (autograd runs its
     # backward on a worker thread, whose handle is not the one timed here)
-    from paper_2201_03950_amd import _binding as B
-
     s_pp = (s0 * tk).contiguous()
     u = tu.clone()
-    ckpts = []
-    for _ in range(steps):
-        ckpts.append(u.clone())
-        B.adi_step(u, s=s_pp, nsteps=1)
-    ubar, sbar = torch.ones_like(u), torch.zeros_like(s_pp)
+    saved = []
     trid.timing_enable(True)
-    for ck in reversed(ckpts):
-        B.adi_step_adjoint(ck, s_pp, ubar, sbar)
-    bwd_kernels = {k: [c, round(ms / c * 1e3, 2)] for k, (c, ms) in trid.timing_read().items()}
+    for _ in range(steps):
+        ws = [torch.empty_like(u) for _ in range(3)]
+        saved.append((u.clone(), ws))
+        B.adi_step_keep(u, s_pp, *ws)
+    ubar, sbar = torch.ones_like(u), torch.zeros_like(s_pp)
+    for ck, ws in reversed(saved):
+        B.adi_step_adjoint_kept(ck, s_pp, ws[0], ws[1], ws[2], ubar, sbar)
+    kept_kernels = {k: [c, round(ms / c * 1e3, 2)] for k, (c, ms) in trid.timing_read().items()}
     trid.timing_enable(False)
-    del ckpts
+    del saved
     u64 = tu.double()
     k64 = tk.double()
-    tf64 = time_calls(lambda: autograd.adi(u64, s0 * k64, steps), 3, warm=1)
-    return {"diff_adi3d_128_20steps": {"fwd_ms_f32": round(tf * 1e3, 3), "fwd_bwd_ms_f32": round(tb * 1e3, 3),
-                                       "fwd_bwd_over_fwd": round(tb / tf, 3),
+    tf64 = time_calls(lambda: autograd.adi(u64, s0 * k64, steps, False), 3, warm=1)
+    return {"diff_adi3d_128_20steps": {"fwd_ms_f32": round(tf * 1e3, 3), "fwd_bwd_ms_f32": round(tb_keep * 1e3, 3),
+                                       "fwd_bwd_over_fwd": round(tb_keep / tf, 3),
+                                       "fwd_bwd_ms_f32_recompute": round(tb_rec * 1e3, 3),
+                                       "fwd_bwd_over_fwd_recompute": round(tb_rec / tf, 3),
                                        "fwd_ms_f64": round(tf64 * 1e3, 3),
-                                       "fwd_kernel_us": fwd_kernels, "bwd_kernels_count_us": bwd_kernels}}
+                                       "fwd_kernel_us": fwd_kernels, "kept_kernels_count_us": kept_kernels}}
 
 
 def pmc_copy_calibration():

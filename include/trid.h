@@ -212,6 +212,27 @@ int trid_gtsv_batched_s_adjoint(trid_handle_t h, trid_dtype_t dt, const void *s,
 int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s,
                           void *u_bar, void *s_bar, int ndim, const int64_t *dims, int64_t batch);
 
+/* One ADI step with per-point s (as trid_adi_step, one step, no graph) that
+ * KEEPS its intermediates for the reverse pass instead of discarding them:
+ *   w1 = X^{-1} (2 s L u),  w2 = Y^{-1} w1,  (3D) w3 = Z^{-1} w2,
+ * then u += w3 (3D) or u += w2 (2D) (Alg. 3, Douglas delta form).  w1, w2, w3
+ * are caller-owned device arrays of the mesh's size and type, distinct from u
+ * and from each other; w3 is ignored (may be NULL) in 2D.  The kept step costs
+ * one extra mesh-sized write (the last solve also stores its solution) and
+ * lets trid_adi_step_adjoint_kept skip the recomputation.  Errors as
+ * trid_adi_step; aliasing arrays are TRID_ERR_ARG. */
+int trid_adi_step_keep(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, int ndim,
+                       const int64_t *dims, int64_t batch, void *w1, void *w2, void *w3);
+
+/* Reverse of one kept step: as trid_adi_step_adjoint, with the intermediates
+ * w1, w2, (3D) w3 written by trid_adi_step_keep for the step that started from
+ * u_t, so nothing is recomputed.  u_bar is overwritten with dL/du_t; dL/ds is
+ * ACCUMULATED into s_bar.  Workspace (one mesh-sized array) is owned by the
+ * handle. */
+int trid_adi_step_adjoint_kept(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s,
+                               const void *w1, const void *w2, const void *w3, void *u_bar,
+                               void *s_bar, int ndim, const int64_t *dims, int64_t batch);
+
 /* ------------------------------------------------------------ plan cache -- */
 
 /* Load / save the tile-plan cache (JSON text: one entry per tuned key, each

@@ -12,6 +12,8 @@ from ._binding import (  # noqa: F401
     TridError,
     adi_step,
     adi_step_adjoint,
+    adi_step_adjoint_kept,
+    adi_step_keep,
     gtsv,
     gtsv_adjoint,
     gtsv_const,

@@ -49,6 +49,8 @@ SIGNATURES = {
     "trid_gtsv_batched_adjoint": ([_H, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_s_adjoint": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_adi_step_adjoint": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I64], _I),
+    "trid_adi_step_keep": ([_H, _I, _P, _P, _I, _I64P, _I64, _P, _P, _P], _I),
+    "trid_adi_step_adjoint_kept": ([_H, _I, _P, _P, _P, _P, _P, _P, _P, _I, _I64P, _I64], _I),
     "trid_plan_load": ([_H, ctypes.c_char_p], _I),
     "trid_plan_save": ([_H, ctypes.c_char_p], _I),
 }
@@ -290,6 +292,32 @@ def adi_step_adjoint(u_t, s, u_bar, s_bar):
     nd, dims, batch = _mesh(u_t)
     _check(lib.trid_adi_step_adjoint(h, _dtype_code(u_t), u_t.data_ptr(), s.data_ptr(),
                                      u_bar.data_ptr(), s_bar.data_ptr(), nd, dims, batch), h)
+    return u_bar, s_bar
+
+
+def adi_step_keep(u, s, w1, w2, w3=None):
+    """One ADI step in place on u (per-point s) that keeps its intermediates in
+    w1, w2 and (3D) w3 for adi_step_adjoint_kept."""
+    _dev(u, s, w1, w2, w3)
+    _same(u, s, w1, w2, w3)
+    h = handle()
+    lib = _prep(h)
+    nd, dims, batch = _mesh(u)
+    _check(lib.trid_adi_step_keep(h, _dtype_code(u), u.data_ptr(), s.data_ptr(), nd, dims, batch,
+                                  w1.data_ptr(), w2.data_ptr(), w3.data_ptr() if w3 is not None else None), h)
+    return u
+
+
+def adi_step_adjoint_kept(u_t, s, w1, w2, w3, u_bar, s_bar):
+    """Reverse of a kept step: u_bar := dL/du_t, s_bar += dL/ds (no recomputation)."""
+    _dev(u_t, s, w1, w2, w3, u_bar, s_bar)
+    _same(u_t, s, w1, w2, w3, u_bar, s_bar)
+    h = handle()
+    lib = _prep(h)
+    nd, dims, batch = _mesh(u_t)
+    _check(lib.trid_adi_step_adjoint_kept(h, _dtype_code(u_t), u_t.data_ptr(), s.data_ptr(), w1.data_ptr(),
+                                          w2.data_ptr(), w3.data_ptr() if w3 is not None else None,
+                                          u_bar.data_ptr(), s_bar.data_ptr(), nd, dims, batch), h)
     return u_bar, s_bar
 
 

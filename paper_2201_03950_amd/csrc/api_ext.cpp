@@ -398,93 +398,181 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
     return TRID_OK;
 }
 
-int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s, void *u_bar,
-                          void *s_bar, int ndim, const int64_t *dims, int64_t batch) {
-    if (!h) return TRID_ERR_ARG;
-    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
-    if (!u_t || !s || !u_bar || !s_bar) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
-    if (ndim != 2 && ndim != 3) return trid::handle_fail(h, TRID_ERR_ARG, "ADI needs ndim 2 or 3");
+}  // extern "C"
+
+namespace {
+
+struct AdiGeom {
+    bool f64;
+    int ndim;
     trid::i64 inner[3], n[3], outer[3];
+    trid::i64 nx, ny, nz, batch;
+    size_t bytes;  // one mesh-sized array
+};
+
+// Shared argument checks of the per-point-s ADI entry points beyond the plain step.
+int adi_geom(trid_handle_t h, trid_dtype_t dt, int ndim, const int64_t *dims, int64_t batch, AdiGeom *g) {
+    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
+    if (ndim != 2 && ndim != 3) return trid::handle_fail(h, TRID_ERR_ARG, "ADI needs ndim 2 or 3");
     for (int ax = 0; ax < ndim; ++ax) {
-        int rc = trid::handle_check_mesh(h, ndim, dims, ax, batch, &inner[ax], &n[ax], &outer[ax]);
+        int rc = trid::handle_check_mesh(h, ndim, dims, ax, batch, &g->inner[ax], &g->n[ax], &g->outer[ax]);
         if (rc) return rc;
     }
-    const bool f64 = dt == TRID_F64;
-    const trid::i64 nx = dims[0], ny = dims[1], nz = ndim == 3 ? dims[2] : 1;
-    const size_t bytes = (size_t)(nx * ny * nz * batch) * (f64 ? 8 : 4);
-    const size_t slot = (bytes + 255) & ~(size_t)255;
-    void *ws = nullptr;
-    int rc = trid::handle_workspace2(h, 4 * slot, &ws);
-    if (rc) return rc;
-    char *wb = static_cast<char *>(ws);
-    void *W[5] = {nullptr, wb, wb + slot, wb + 2 * slot, wb + 3 * slot};  // W[1..3]: forward outputs, W[4]: lambda
+    g->f64 = dt == TRID_F64;
+    g->ndim = ndim;
+    g->nx = dims[0];
+    g->ny = dims[1];
+    g->nz = ndim == 3 ? dims[2] : 1;
+    g->batch = batch;
+    g->bytes = (size_t)(g->nx * g->ny * g->nz * batch) * (g->f64 ? 8 : 4);
+    return TRID_OK;
+}
+
+// Forward pieces of one step with per-point s: W1 = X^{-1} (2 s L u) and the
+// line solves after it.  keep_u: NULL -> W[k+1] = A_k^{-1} W[k] for every axis
+// (the recompute of the reverse pass); non-NULL -> the last solve also does
+// u += W[ndim] (the step itself, intermediates kept).
+int adi_forward_parts(trid_handle_t h, const AdiGeom &g, const void *u, const void *s, void *const W[4],
+                      void *keep_u, const char *names[3]) {
     trid::ExtState &x = trid::handle_ext(h);
     hipStream_t st = trid::handle_stream(h);
     std::string msg;
-    // recompute the forward step from the checkpoint: W1 = X^-1 (2 s L u_t), W[k+1] = A_k^-1 W[k]
     trid::AdiReq ar;
-    ar.f64 = f64;
-    ar.ndim = ndim;
-    ar.u = u_t;
+    ar.f64 = g.f64;
+    ar.ndim = g.ndim;
+    ar.u = u;
     ar.s = s;
     ar.d = W[1];
-    ar.nx = nx;
-    ar.ny = ny;
-    ar.nz = nz;
-    ar.batch = batch;
+    ar.nx = g.nx;
+    ar.ny = g.ny;
+    ar.nz = g.nz;
+    ar.batch = g.batch;
     trid::LinePlan pl;
     if (!trid::plan_rhs_x(ar, &pl, &msg)) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
-    hipError_t e = x.timer.time("adj_rhs_x", st, [&] { return trid::launch_rhs_x(ar, pl, st); });
-    if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI adjoint: stencil + x launch");
-    for (int k = 1; k < ndim; ++k) {
+    hipError_t e = x.timer.time(names[0], st, [&] { return trid::launch_rhs_x(ar, pl, st); });
+    if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI: stencil + x launch");
+    for (int k = 1; k < g.ndim; ++k) {
         trid::LineReq r;
-        r.f64 = f64;
+        r.f64 = g.f64;
         r.mode = trid::Mode::S;
-        r.out = trid::Out::Store;
         r.s = s;
         r.d = W[k];
-        r.x = W[k + 1];
-        r.inner = inner[k];
-        r.n = n[k];
-        r.outer = outer[k];
+        const bool last = k == g.ndim - 1;
+        if (keep_u && last) {
+            r.out = trid::Out::AddKeep;
+            r.x = keep_u;
+            r.x2 = W[k + 1];
+        } else {
+            r.out = trid::Out::Store;
+            r.x = W[k + 1];
+        }
+        r.inner = g.inner[k];
+        r.n = g.n[k];
+        r.outer = g.outer[k];
         if (!trid::plan_lines(r, &pl, &msg)) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
-        e = x.timer.time("adj_fwd_solve", st, [&] { return trid::launch_lines(r, pl, st); });
-        if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI adjoint: forward solve launch");
+        e = x.timer.time(names[k], st, [&] { return trid::launch_lines(r, pl, st); });
+        if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI: line-solve launch");
     }
-    // reverse sweep: lambda = A_k^-T lambda, sbar += lambda * (second difference of A_k's output)
-    for (int k = ndim - 1; k >= 0; --k) {
+    return TRID_OK;
+}
+
+// Reverse sweep of one step given its intermediates W[1..ndim] and scratch W[4]:
+// lambda = A_k^{-T} lambda (z, y, x), sbar += lambda * second difference of
+// W[k+1], then the stencil adjoint into u_bar and s_bar.
+int adi_reverse(trid_handle_t h, const AdiGeom &g, const void *u_t, const void *s, void *const W[5], void *u_bar,
+                void *s_bar) {
+    trid::ExtState &x = trid::handle_ext(h);
+    hipStream_t st = trid::handle_stream(h);
+    std::string msg;
+    trid::LinePlan pl;
+    hipError_t e;
+    for (int k = g.ndim - 1; k >= 0; --k) {
         trid::LineReq r;
-        r.f64 = f64;
+        r.f64 = g.f64;
         r.mode = trid::Mode::ST;
         r.out = trid::Out::AdjS;
         r.s = s;
         r.xf = W[k + 1];
-        r.d = (k == ndim - 1) ? u_bar : W[4];
+        r.d = (k == g.ndim - 1) ? u_bar : W[4];
         r.g = W[4];
         r.gs = s_bar;
-        r.inner = inner[k];
-        r.n = n[k];
-        r.outer = outer[k];
+        r.inner = g.inner[k];
+        r.n = g.n[k];
+        r.outer = g.outer[k];
         if (!trid::plan_lines(r, &pl, &msg)) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
         e = x.timer.time("adj_solve", st, [&] { return trid::launch_lines(r, pl, st); });
         if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI adjoint: transposed solve launch");
     }
     // lambda is now dLoss/d(rhs): stencil adjoint into u_bar and s_bar
     trid::StencilAdjReq sa;
-    sa.f64 = f64;
-    sa.ndim = ndim;
+    sa.f64 = g.f64;
+    sa.ndim = g.ndim;
     sa.u = u_t;
     sa.s = s;
     sa.rbar = W[4];
     sa.ubar = u_bar;
     sa.sbar = s_bar;
-    sa.nx = nx;
-    sa.ny = ny;
-    sa.nz = nz;
-    sa.batch = batch;
+    sa.nx = g.nx;
+    sa.ny = g.ny;
+    sa.nz = g.nz;
+    sa.batch = g.batch;
     e = x.timer.time("adj_stencil", st, [&] { return trid::launch_stencil_adjoint(sa, st); });
     if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI adjoint: stencil adjoint launch");
     return TRID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s, void *u_bar,
+                          void *s_bar, int ndim, const int64_t *dims, int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (!u_t || !s || !u_bar || !s_bar) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    AdiGeom g;
+    int rc = adi_geom(h, dt, ndim, dims, batch, &g);
+    if (rc) return rc;
+    const size_t slot = (g.bytes + 255) & ~(size_t)255;
+    void *ws = nullptr;
+    rc = trid::handle_workspace2(h, 4 * slot, &ws);
+    if (rc) return rc;
+    char *wb = static_cast<char *>(ws);
+    void *W[5] = {nullptr, wb, wb + slot, wb + 2 * slot, wb + 3 * slot};  // W[1..3]: forward outputs, W[4]: lambda
+    // recompute the forward step from the checkpoint: W1 = X^-1 (2 s L u_t), W[k+1] = A_k^-1 W[k]
+    const char *names[3] = {"adj_rhs_x", "adj_fwd_solve", "adj_fwd_solve"};
+    rc = adi_forward_parts(h, g, u_t, s, W, nullptr, names);
+    if (rc) return rc;
+    return adi_reverse(h, g, u_t, s, W, u_bar, s_bar);
+}
+
+int trid_adi_step_keep(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, int ndim, const int64_t *dims,
+                       int64_t batch, void *w1, void *w2, void *w3) {
+    if (!h) return TRID_ERR_ARG;
+    if (!u || !s || !w1 || !w2 || (ndim == 3 && !w3)) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    AdiGeom g;
+    int rc = adi_geom(h, dt, ndim, dims, batch, &g);
+    if (rc) return rc;
+    if (w1 == u || w2 == u || w1 == w2 || (ndim == 3 && (w3 == u || w3 == w1 || w3 == w2)))
+        return trid::handle_fail(h, TRID_ERR_ARG, "u, w1, w2 and w3 must be distinct arrays");
+    void *W[4] = {nullptr, w1, w2, w3};
+    const char *names[3] = {"keep_rhs_x", "keep_y", "keep_z"};
+    return adi_forward_parts(h, g, u, s, W, u, names);
+}
+
+int trid_adi_step_adjoint_kept(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s, const void *w1,
+                               const void *w2, const void *w3, void *u_bar, void *s_bar, int ndim,
+                               const int64_t *dims, int64_t batch) {
+    if (!h) return TRID_ERR_ARG;
+    if (!u_t || !s || !w1 || !w2 || (ndim == 3 && !w3) || !u_bar || !s_bar)
+        return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    AdiGeom g;
+    int rc = adi_geom(h, dt, ndim, dims, batch, &g);
+    if (rc) return rc;
+    void *ws = nullptr;
+    rc = trid::handle_workspace2(h, g.bytes, &ws);  // lambda only
+    if (rc) return rc;
+    void *W[5] = {nullptr, const_cast<void *>(w1), const_cast<void *>(w2), const_cast<void *>(w3), ws};
+    return adi_reverse(h, g, u_t, s, W, u_bar, s_bar);
 }
 
 static std::string device_arch() {

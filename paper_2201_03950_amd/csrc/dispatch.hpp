@@ -23,6 +23,7 @@ enum class Mode {
 enum class Out {
     Store,      // x = solution
     Add,        // x += solution
+    AddKeep,    // x += solution and x2 = solution (a step that keeps its intermediates)
     AdjArrays,  // g = lambda; ga, gb, gc = coefficient gradients
     AdjS        // g = lambda; gs += lambda * second difference of xf
 };
@@ -72,6 +73,7 @@ struct LineReq {
     const void *a = nullptr, *b = nullptr, *c = nullptr, *s = nullptr, *d = nullptr;
     double ca = 0, cb = 0, cc = 0;
     void *x = nullptr;         // Store / Add target
+    void *x2 = nullptr;        // AddKeep: copy of the solution
     const void *xf = nullptr;  // forward solution (adjoints)
     void *g = nullptr, *ga = nullptr, *gb = nullptr, *gc = nullptr, *gs = nullptr;
     i64 inner = 1, n = 1, outer = 1;  // line stride, length, number of outer indices

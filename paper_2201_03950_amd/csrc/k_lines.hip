@@ -236,6 +236,8 @@ hipError_t launch_typed(const LineReq &r, const LinePlan &pl, hipStream_t s) {
             default: return hipErrorInvalidValue;
         }
     }
+    if (r.out == Out::AddKeep && r.mode == Mode::S)
+        return strided_M<T>(r, pl, SrcS<T>{sp, d}, EpiAddKeep<T>{x, static_cast<T *>(r.x2)}, s);
     const T *xf = static_cast<const T *>(r.xf);
     // adjoint right-hand side: r.d if given (out of place), else g itself
     const T *grhs = r.d ? d : static_cast<const T *>(r.g);

@@ -217,6 +217,41 @@ struct EpiAdd {  // u += solution (the update of Alg. 3, fused into the last sol
     }
 };
 
+// u += solution and w = solution: the update of Alg. 3 for a step whose
+// intermediates are kept for the reverse pass (w is the step's increment).
+template <typename T>
+struct EpiAddKeep {
+    static constexpr bool kWide = true;  // keeps the M prefetched values of u
+    T *u;
+    T *w;
+    template <int M>
+    struct Pre {
+        T v[M];
+    };
+    template <int M>
+    __device__ __forceinline__ void prefetch(Pre<M> &pre, i64 base, i64 st, int g0, int n,
+                                             bool act) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            pre.v[k] = load_if(u, base + (i64)g * st, act && g < n, base);
+        }
+    }
+    template <int M>
+    __device__ __forceinline__ void store(const Pre<M> &pre, i64 base, i64 st, int g0, int n,
+                                          bool act, const T (&x)[M]) const {
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int g = g0 + k;
+            if (act && g < n) {
+                const i64 off = base + (i64)g * st;
+                u[off] = pre.v[k] + x[k];
+                w[off] = x[k];
+            }
+        }
+    }
+};
+
 // Adjoint epilogue, arrays form: lambda -> g; ga = -lambda x_{g-1}, gb = -lambda x_g,
 // gc = -lambda x_{g+1} (0 at the ignored a_0 / c_{N-1}).
 template <typename T>

@@ -135,5 +135,9 @@ def test_refine_and_adjoint_argument_checks(lib, h):
     assert lib.trid_gtsv_batched_s_refine(h, 5, FAKE, FAKE, ctypes.c_void_p(0x2000), 2, d, 0, 1) == 1
     assert lib.trid_adi_step_adjoint(h, 1, FAKE, None, FAKE, FAKE, 3, _dims(8, 8, 8), 1) == 1
     assert lib.trid_adi_step_adjoint(h, 1, FAKE, FAKE, FAKE, FAKE, 1, _dims(8), 1) == 1
+    assert lib.trid_adi_step_keep(h, 1, FAKE, FAKE, 3, _dims(8, 8, 8), 1, FAKE, FAKE, None) == 1  # 3D needs w3
+    assert lib.trid_adi_step_keep(h, 1, FAKE, None, 3, _dims(8, 8, 8), 1, FAKE, FAKE, FAKE) == 1
+    assert lib.trid_adi_step_keep(h, 1, FAKE, FAKE, 1, _dims(8), 1, FAKE, FAKE, None) == 1
+    assert lib.trid_adi_step_adjoint_kept(h, 1, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, 3, _dims(8, 8, 8), 1) == 1
     assert lib.trid_plan_load(h, None) == 1
     assert lib.trid_plan_load(h, b"/nonexistent/plans.json") == 1

@@ -103,3 +103,50 @@ def test_adi_fn_gradcheck_small(trid):
     u = torch.rand(shape, generator=g, dtype=torch.float64).cuda().requires_grad_(True)
     s = (0.2 * torch.rand(shape, generator=g, dtype=torch.float64) + 0.05).cuda().requires_grad_(True)
     assert torch.autograd.gradcheck(lambda uu, ss: autograd.adi(uu, ss, 3), [u, s], eps=1e-6, atol=1e-8)
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("dims,batch", [((20, 17, 13), 2), ((41, 30), 3), ((64, 32, 16), 1)])
+def test_kept_step_matches_plain_step_and_recompute(trid, dt, dims, batch):
+    """A step that keeps its intermediates gives the same field as the plain
+    step, its last intermediate is the increment, and its reverse pass equals
+    the recomputing one (same kernels, same arithmetic: bitwise)."""
+    rng = np.random.default_rng(7 + sum(dims))
+    shape = gen.mesh_shape(dims, batch)
+    u = _t(rng.uniform(0, 1, shape).astype(dt))
+    s = _t((0.2 * rng.lognormal(0.0, 0.5, shape)).astype(dt))
+    u_plain = u.clone()
+    trid.adi_step(u_plain, s=s, nsteps=1)
+    u_keep = u.clone()
+    ws = [torch.empty_like(u) for _ in range(len(dims))]
+    trid.adi_step_keep(u_keep, s, *ws)
+    assert torch.equal(u_keep, u_plain)
+    assert torch.equal(u_keep, u + ws[-1])
+    ubar = _t(rng.standard_normal(shape).astype(dt))
+    sbar = _t(rng.standard_normal(shape).astype(dt))
+    ub1, sb1 = ubar.clone(), sbar.clone()
+    trid.adi_step_adjoint(u, s, ub1, sb1)
+    ub2, sb2 = ubar.clone(), sbar.clone()
+    trid.adi_step_adjoint_kept(u, s, ws[0], ws[1], ws[2] if len(ws) == 3 else None, ub2, sb2)
+    assert torch.equal(ub1, ub2) and torch.equal(sb1, sb2)
+
+
+@pytest.mark.parametrize("keep", [True, False])
+def test_adi_fn_gradcheck_keep_modes(trid, keep):
+    from paper_2201_03950_amd import autograd
+
+    g = torch.Generator().manual_seed(3)
+    shape = (1, 4, 5, 6)
+    u = torch.rand(shape, generator=g, dtype=torch.float64).cuda().requires_grad_(True)
+    s = (0.2 * torch.rand(shape, generator=g, dtype=torch.float64) + 0.05).cuda().requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda uu, ss: autograd.adi(uu, ss, 3, keep), [u, s], eps=1e-6, atol=1e-8)
+
+
+def test_kept_step_argument_checks(trid):
+    u = torch.zeros((1, 4, 5, 6), dtype=torch.float64, device="cuda")
+    s = torch.full_like(u, 0.2)
+    w = torch.empty_like(u)
+    with pytest.raises(trid.TridError):
+        trid.adi_step_keep(u, s, w, w, torch.empty_like(u))  # aliasing intermediates
+    with pytest.raises(trid.TridError):
+        trid.adi_step_keep(u, s, u, torch.empty_like(u), torch.empty_like(u))  # w1 aliases u
