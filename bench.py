@@ -427,17 +427,22 @@ def extra_gradient(trid):
 
 
 def pmc_copy_calibration():
-    """A plain device copy of known size (2 x 134,217,728 bytes moved), for counter scaling."""
+    """A plain device copy of known size (2 x 536,870,912 bytes moved), for counter scaling.
+
+    The source is larger than every cache level (8 x 4 MB L2, 256 MB MALL) and a
+    64 MB write in between evicts the L2s, so the copy's reads all miss."""
     import torch
 
     src = torch.ones(COPY_ELEMS, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
+    evict = torch.zeros(1 << 23, dtype=torch.float64, device="cuda")
+    sync()
     dst.copy_(src)
     sync()
-    del src, dst
+    del src, dst, evict
 
 
-COPY_ELEMS = 1 << 24  # 128 MiB of float64
+COPY_ELEMS = 1 << 26  # 512 MiB of float64
 
 
 def ingest_pmc(fetch_dir, write_dir):
@@ -464,9 +469,9 @@ def ingest_pmc(fetch_dir, write_dir):
     known = COPY_ELEMS * 8.0
 
     def copy_value(per):
-        cands = [v for k, v in per.items() if "trid::" not in k and ("copy" in k.lower() or "elementwise" in k.lower())]
-        vals = [x for v in cands for x in v if x > 0.25 * known]
-        return sum(vals) / len(vals)
+        # the calibration copy: the largest device-to-device copy dispatch of the run
+        vals = [x for k, v in per.items() if "copyBuffer" in k for x in v]
+        return max(vals)
 
     kf, kw = known / copy_value(fetch), known / copy_value(write)
     names = {"StgRhs": "adi_stencil_x", "EpiAdd": "adi_z_update", "EpiStore": "adi_y"}

@@ -115,6 +115,8 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
             L = std::min(L, pow2_floor(maxt / P));
         }
         if (r.inner < L) L = std::max(1, pow2_ceil(r.inner));
+        // small batches are latency-bound: keep at least two blocks per CU
+        while (L > 4 && cdiv(r.inner, L) * r.outer < 512) L /= 2;
     }
     if ((i64)L * P > maxt) {
         *err = "plan exceeds 1024 threads per block";
