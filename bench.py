@@ -219,7 +219,7 @@ def extra_workloads(trid):
         del ta, tb, tc, td
         torch.cuda.empty_cache()
     for name, fn in (("adi2d_64x1024sq_xy", extra_2d), ("varlen_20000", extra_varlen),
-                     ("diff_adi3d_128_20steps", extra_gradient)):
+                     ("diff_adi3d_128_20steps", extra_gradient), ("long_64x1M_f64", extra_long)):
         log("extra: " + name)
         try:
             out.update(fn(trid))
@@ -305,6 +305,50 @@ def extra_2d(trid):
     res["refine_time_vs_f64"] = round(res["f32_refine64"]["ms"] / res["f64"]["ms"], 3)
     out["adi2d_64x1024sq_xy"] = res
     return out
+
+
+def extra_long(trid):
+    """64 contiguous lines of 2^20 rows (FP64): the chunked solve for lines longer
+    than one workgroup holds.  Coefficient arrays and per-point s; the error is
+    the relative residual of the first two lines."""
+    import torch
+
+    from workloads import gen
+
+    nl, n = 64, 1 << 20
+    a, b, c, d = gen.dd_lines(nl, n, seed=21)
+    ta, tb, tc, d0 = (torch.from_numpy(v).cuda() for v in (a, b, c, d))
+    del a, b, c, d
+    td = d0.clone()
+    out = {}
+    for mode in ("arrays", "s"):
+        def call():
+            if mode == "arrays":
+                trid.gtsv(ta, tb, tc, td, 0)
+            else:
+                trid.gtsv_s(tb, td, 0)
+
+        td.copy_(d0)
+        call()
+        x = td[:2].double()
+        if mode == "arrays":
+            ax = tb[:2] * x
+            ax[:, 1:] += ta[:2, 1:] * x[:, :-1]
+            ax[:, :-1] += tc[:2, :-1] * x[:, 1:]
+        else:
+            ax = _apply_rows(tb[:2], x, 0)
+        resid = _err_vs(d0[:2], ax)
+        trid.timing_enable(True)
+        t = time_calls(call, 10)
+        kt = trid.timing_read()
+        trid.timing_enable(False)
+        cnt, ms = kt["gtsv_long"]
+        kern = ms / cnt * 1e-3
+        byts = alg_bytes(mode, 8, nl * n)
+        out[mode] = {"ms_per_call": round(t * 1e3, 4), "ms_events": round(kern * 1e3, 4),
+                     "rows_per_s": round(nl * n / kern, 1), "gbs_alg": round(byts / kern / 1e9, 1),
+                     "frac_alg": round(byts / kern / 1e9 / PEAK_GBS, 4), "rel_residual": resid}
+    return {"long_64x1M_f64": out}
 
 
 def extra_varlen(trid):

@@ -71,6 +71,12 @@ enum {
 /* Longest line a single-workgroup tile plan handles (rows). */
 #define TRID_MAX_LINE 8192
 
+/* Longest contiguous line (axis 0, i.e. the line is the fastest-varying
+ * index) the batched solves accept: longer than TRID_MAX_LINE, such a line is
+ * cut into chunks of 2048 rows, one workgroup each, coupled through a reduced
+ * system of two rows per chunk (the tiling of Section III-B one level up). */
+#define TRID_MAX_LONG_LINE 8388608
+
 /* ---------------------------------------------------------------- handle -- */
 
 /* Create a handle.  Allocates host memory only; device state (workspace,
@@ -116,9 +122,13 @@ int trid_timing_read(trid_handle_t h, char *buf, int64_t len);
  * coefficient arrays a (sub), b (diagonal), c (super) of dtype dt, in the
  * mesh layout (eqs. (1)-(2), Section II-B).  d is IN/OUT: the right-hand side
  * on entry, the solution on return.  a, b, c are read only.
+ * Lines of axis 0 may be up to TRID_MAX_LONG_LINE rows long; those longer
+ * than TRID_MAX_LINE take the chunked solve (three launches, a workspace of
+ * 10 * lines * ceil(n / 2048) values owned by the handle).
  * Errors: TRID_ERR_ARG (null pointer, ndim not in 1..3, axis not in
  * 0..ndim-1, a dim < 1, batch < 1, bad dtype), TRID_ERR_UNSUPPORTED (line
- * length > TRID_MAX_LINE), TRID_ERR_HIP. */
+ * length > TRID_MAX_LINE along axis > 0, or > TRID_MAX_LONG_LINE), TRID_ERR_ALLOC,
+ * TRID_ERR_HIP. */
 int trid_gtsv_batched(trid_handle_t h, trid_dtype_t dt, const void *a, const void *b,
                       const void *c, void *d, int ndim, const int64_t *dims, int axis,
                       int64_t batch);

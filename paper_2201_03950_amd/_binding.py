@@ -71,6 +71,13 @@ def load_library(path=LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise ImportError("libtrid.so not built (run __graft_entry__.build()): %s" % path)
+        # torch ships its own HIP runtime; loaded first, it also serves libtrid's
+        # dependency, so both use one runtime (loading libtrid first would bring
+        # in a second copy that sees no device once torch has initialised its own)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(path)
         for name, (args, res) in SIGNATURES.items():
             fn = getattr(lib, name)

@@ -62,8 +62,10 @@ int hip_fail(trid_handle_t h, hipError_t e, const char *what) {
 bool dtype_ok(int dt) { return dt == TRID_F32 || dt == TRID_F64; }
 
 // Validate mesh arguments; on success fill the line geometry of `axis`.
+// long_ok: contiguous lines up to TRID_MAX_LONG_LINE are accepted (the
+// chunked solve of run_lines).
 int check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, int64_t batch, i64 *inner,
-               i64 *n, i64 *outer) {
+               i64 *n, i64 *outer, bool long_ok = false) {
     if (ndim < 1 || ndim > 3) return fail(h, TRID_ERR_ARG, "ndim must be 1, 2 or 3");
     if (!dims) return fail(h, TRID_ERR_ARG, "dims is NULL");
     if (axis < 0 || axis >= ndim) return fail(h, TRID_ERR_ARG, "axis out of range");
@@ -77,15 +79,24 @@ int check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, int64_t
     i64 in = 1, out = batch;
     for (int k = 0; k < axis; ++k) in *= dims[k];
     for (int k = axis + 1; k < ndim; ++k) out *= dims[k];
-    if (dims[axis] > TRID_MAX_LINE)
-        return fail(h, TRID_ERR_UNSUPPORTED, "line length exceeds TRID_MAX_LINE");
+    if (dims[axis] > TRID_MAX_LINE) {
+        if (!long_ok || in != 1)
+            return fail(h, TRID_ERR_UNSUPPORTED, "line length exceeds TRID_MAX_LINE");
+        if (dims[axis] > TRID_MAX_LONG_LINE)
+            return fail(h, TRID_ERR_UNSUPPORTED, "line length exceeds TRID_MAX_LONG_LINE");
+        if (out * 2 * ((dims[axis] + 2047) / 2048) >= ((i64)1 << 31))
+            return fail(h, TRID_ERR_UNSUPPORTED, "too many long lines in one call");
+    }
     *inner = in;
     *n = dims[axis];
     *outer = out;
     return TRID_OK;
 }
 
+int run_long_lines(trid_handle_t h, const trid::LineReq &r);
+
 int run_lines(trid_handle_t h, const trid::LineReq &r) {
+    if (r.n > TRID_MAX_LINE) return run_long_lines(h, r);
     trid::LinePlan pl;
     std::string msg;
     trid::LineReq rr = r;
@@ -148,6 +159,27 @@ int handle_workspace(trid_handle_t h, size_t bytes, void **ptr) {
 
 }  // namespace trid
 
+namespace {
+
+// Contiguous lines longer than TRID_MAX_LINE: chunk pass, reduced lines, solve
+// pass, with the reduced rows in the handle's workspace.
+int run_long_lines(trid_handle_t h, const trid::LineReq &r) {
+    void *ws = nullptr;
+    int rc = trid::handle_workspace(h, trid::long_lines_workspace(r), &ws);
+    if (rc) return rc;
+    std::string msg;
+    hipError_t e = h->ext.timer.time_recorded("gtsv_long", h->stream,
+                                              [&] { return trid::launch_long_lines(r, ws, h->stream, &msg); });
+    if (e != hipSuccess) {
+        if (!msg.empty()) return fail(h, TRID_ERR_UNSUPPORTED, msg);
+        return hip_fail(h, e, "long line-solve launch");
+    }
+    h->err.clear();
+    return TRID_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int trid_version(void) { return 10000; }
@@ -194,7 +226,7 @@ int trid_gtsv_batched(trid_handle_t h, trid_dtype_t dt, const void *a, const voi
     if (!dtype_ok(dt)) return fail(h, TRID_ERR_ARG, "bad dtype");
     if (!a || !b || !c || !d) return fail(h, TRID_ERR_ARG, "NULL data pointer");
     trid::LineReq r;
-    int rc = check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    int rc = check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer, true);
     if (rc) return rc;
     r.f64 = dt == TRID_F64;
     r.mode = trid::Mode::Arrays;
@@ -213,7 +245,7 @@ int trid_gtsv_batched_const(trid_handle_t h, trid_dtype_t dt, double a, double b
     if (!dtype_ok(dt)) return fail(h, TRID_ERR_ARG, "bad dtype");
     if (!d) return fail(h, TRID_ERR_ARG, "NULL data pointer");
     trid::LineReq r;
-    int rc = check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    int rc = check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer, true);
     if (rc) return rc;
     r.f64 = dt == TRID_F64;
     r.mode = trid::Mode::Const;
@@ -232,7 +264,7 @@ int trid_gtsv_batched_s(trid_handle_t h, trid_dtype_t dt, const void *s, void *d
     if (!dtype_ok(dt)) return fail(h, TRID_ERR_ARG, "bad dtype");
     if (!s || !d) return fail(h, TRID_ERR_ARG, "NULL data pointer");
     trid::LineReq r;
-    int rc = check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    int rc = check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer, true);
     if (rc) return rc;
     r.f64 = dt == TRID_F64;
     r.mode = trid::Mode::S;

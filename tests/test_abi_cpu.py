@@ -89,7 +89,16 @@ def test_null_pointers_rejected(lib, h):
 
 
 def test_line_longer_than_limit_is_unsupported(lib, h):
-    rc = lib.trid_gtsv_batched(h, 1, FAKE, FAKE, FAKE, FAKE, 1, _dims(8193), 0, 1)
+    # strided lines (axis > 0) stay within one workgroup
+    rc = lib.trid_gtsv_batched(h, 1, FAKE, FAKE, FAKE, FAKE, 2, _dims(4, 8193), 1, 1)
+    assert rc == 4
+    assert b"TRID_MAX_LINE" in lib.trid_last_error(h)
+    # contiguous lines take the chunked solve up to TRID_MAX_LONG_LINE
+    rc = lib.trid_gtsv_batched_s(h, 1, FAKE, FAKE, 1, _dims(8388609), 0, 1)
+    assert rc == 4
+    assert b"TRID_MAX_LONG_LINE" in lib.trid_last_error(h)
+    # the refinement and adjoint solves have no chunked form
+    rc = lib.trid_gtsv_batched_refine(h, 1, FAKE, FAKE, FAKE, FAKE, ctypes.c_void_p(0x2000), 1, _dims(8193), 0, 1)
     assert rc == 4
     assert b"TRID_MAX_LINE" in lib.trid_last_error(h)
 
