@@ -117,7 +117,9 @@ template <typename T, int PASS>
 __global__ __launch_bounds__(kP) void k_chunk(ChunkArgs g) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sh = reinterpret_cast<T *>(smem_raw);
-    T *red = sh + g.ls;
+    // the reduced solve's scratch reuses the staging area: the rows are in
+    // registers by then (every put ends with a barrier)
+    T *red = sh;
     const int p = threadIdx.x;
     const i64 id = xcd_block_id();
     const i64 line = id / g.nch;
@@ -127,23 +129,43 @@ __global__ __launch_bounds__(kP) void k_chunk(ChunkArgs g) {
     const int g0 = p * kM;
     const int pos = p * (kM + 1);
     T ra[kM], rb[kM], rc[kM], rd[kM];
-    auto take = [&](const T *src, T(&dst)[kM], T idle) {
-        stage_in<T, kM>(sh, src + base, cnt, kC, g.ls);
+    // every array's loads are issued before the first is staged, so a block
+    // waits for memory once rather than once per array
+    auto put = [&](const T(&v)[kM], T(&dst)[kM], T idle) {
+        stage_put<T, kM>(sh, v, cnt, kC, g.ls);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kM; ++k) {
-            const T v = sh[pos + k];
-            dst[k] = (g0 + k < cnt) ? v : idle;
+            const T x = sh[pos + k];
+            dst[k] = (g0 + k < cnt) ? x : idle;
         }
         __syncthreads();
     };
+    const T *dsrc = static_cast<const T *>(g.d) + base;
+    const int ri = (int)(line * 2 * g.nch) + 2 * ch;  // this chunk's reduced rows
+    T rx0 = T(0), rx1 = T(0);
+    if (PASS == 1) {  // the chunk's end values from the reduced lines (block-uniform)
+        rx0 = static_cast<const T *>(g.rx)[ri];
+        rx1 = static_cast<const T *>(g.rx)[ri + 1];
+    }
     if (g.mode == 0) {
-        take(static_cast<const T *>(g.a), ra, T(0));
-        take(static_cast<const T *>(g.b), rb, T(1));
-        take(static_cast<const T *>(g.c), rc, T(0));
+        T va[kM], vb[kM], vc[kM], vd[kM];
+        stage_load<T, kM>(va, static_cast<const T *>(g.a) + base, cnt);
+        stage_load<T, kM>(vb, static_cast<const T *>(g.b) + base, cnt);
+        stage_load<T, kM>(vc, static_cast<const T *>(g.c) + base, cnt);
+        stage_load<T, kM>(vd, dsrc, cnt);
+        asm volatile("" ::: "memory");  // keep the loads together, ahead of their uses
+        put(va, ra, T(0));
+        put(vb, rb, T(1));
+        put(vc, rc, T(0));
+        put(vd, rd, T(0));
     } else if (g.mode == 1) {
-        T sv[kM];
-        take(static_cast<const T *>(g.s), sv, T(0));
+        T vs[kM], vd[kM], sv[kM];
+        stage_load<T, kM>(vs, static_cast<const T *>(g.s) + base, cnt);
+        stage_load<T, kM>(vd, dsrc, cnt);
+        asm volatile("" ::: "memory");
+        put(vs, sv, T(0));
+        put(vd, rd, T(0));
 #pragma unroll
         for (int k = 0; k < kM; ++k) {
             const bool v = g0 + k < cnt;
@@ -152,6 +174,9 @@ __global__ __launch_bounds__(kP) void k_chunk(ChunkArgs g) {
             rc[k] = v ? -sv[k] : T(0);
         }
     } else {
+        T vd[kM];
+        stage_load<T, kM>(vd, dsrc, cnt);
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < kM; ++k) {
             const bool v = g0 + k < cnt;
@@ -159,8 +184,8 @@ __global__ __launch_bounds__(kP) void k_chunk(ChunkArgs g) {
             rb[k] = v ? (T)g.cb : T(1);
             rc[k] = v ? (T)g.cc : T(0);
         }
+        put(vd, rd, T(0));
     }
-    take(static_cast<const T *>(g.d), rd, T(0));
     // the line's own ends: a at row 0 and c at row n-1 are not part of the system
     const i64 gl0 = (i64)ch * kC + g0;  // line row of this tile's first row
 #pragma unroll
@@ -182,7 +207,6 @@ __global__ __launch_bounds__(kP) void k_chunk(ChunkArgs g) {
         rb[kM - 1] = T(1);
         rc[kM - 1] = T(0);
     }
-    const int ri = (int)(line * 2 * g.nch) + 2 * ch;  // this chunk's reduced rows
     if (PASS == 0) {
         // one elimination, three right-hand sides: (0, d_1..d_{C-2}, 0), e_0 and
         // e_{C-1}.  The unit vectors only touch the chunk's identity end rows, so
@@ -215,12 +239,11 @@ __global__ __launch_bounds__(kP) void k_chunk(ChunkArgs g) {
             RD[ri + 1] = D1 - A1 * s1;
         }
     } else {
-        const T *RX = static_cast<const T *>(g.rx);
-        if (first) rd[0] = RX[ri];
-        if (last) rd[kM - 1] = RX[ri + 1];
+        if (first) rd[0] = rx0;
+        if (last) rd[kM - 1] = rx1;
         T u[kM];
         tile_solve<T, kM>(ra, rb, rc, rd, red, kP, kP, p, p, 1, u);
-        // each thread read only its own slots of the staging region
+        __syncthreads();  // the reduced solve's last reads of the shared area are done
 #pragma unroll
         for (int k = 0; k < kM; ++k) sh[pos + k] = u[k];
         __syncthreads();
@@ -230,7 +253,7 @@ __global__ __launch_bounds__(kP) void k_chunk(ChunkArgs g) {
 
 template <typename T>
 hipError_t go(const ChunkArgs &g, i64 nlines, int pass, hipStream_t s) {
-    const size_t shm = ((size_t)g.ls + 10 * kP) * sizeof(T);
+    const size_t shm = (size_t)std::max(g.ls, (pass == 0 ? 10 : 6) * kP) * sizeof(T);
     const i64 nb = nlines * g.nch;
     if (nb >= ((i64)1 << 31)) return hipErrorInvalidValue;
     if (pass == 0)
