@@ -15,6 +15,7 @@
 #include "../../include/trid.h"
 #include "dispatch.hpp"
 #include "ext.hpp"
+#include "long_lines.hpp"
 
 using trid::i64;
 

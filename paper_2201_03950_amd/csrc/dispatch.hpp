@@ -88,12 +88,6 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err);
 // Enqueue the solve described by r on stream s.
 hipError_t launch_lines(const LineReq &r, const LinePlan &pl, hipStream_t s);
 
-// Contiguous lines (inner == 1) longer than one workgroup holds: chunked
-// solve through a reduced system of two rows per chunk.  ws must hold
-// long_lines_workspace(r) bytes; err receives a message for unsupported shapes.
-size_t long_lines_workspace(const LineReq &r);
-hipError_t launch_long_lines(const LineReq &r, void *ws, hipStream_t s, std::string *err);
-
 // ADI: RHS stencil fused with the x-line solve.  d = X^{-1} (2 s L u) for
 // `batch` meshes of nx*ny*nz points (nz = 1 in 2D), s per point (s != NULL)
 // or the constant s0.

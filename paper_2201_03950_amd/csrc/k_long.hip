@@ -19,8 +19,8 @@
 // pass reads the rows, the solve pass reads them again and writes x.
 #include <algorithm>
 
-#include "dispatch.hpp"
 #include "lines.hpp"
+#include "long_lines.hpp"
 
 namespace trid {
 
