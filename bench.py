@@ -219,7 +219,8 @@ def extra_workloads(trid):
         del ta, tb, tc, td
         torch.cuda.empty_cache()
     for name, fn in (("adi2d_64x1024sq_xy", extra_2d), ("varlen_20000", extra_varlen),
-                     ("diff_adi3d_128_20steps", extra_gradient), ("long_64x1M_f64", extra_long)):
+                     ("diff_adi3d_128_20steps", extra_gradient), ("long_64x1M_f64", extra_long),
+                     ("adi_small_batched", extra_small_batched)):
         log("extra: " + name)
         try:
             out.update(fn(trid))
@@ -349,6 +350,66 @@ def extra_long(trid):
                      "rows_per_s": round(nl * n / kern, 1), "gbs_alg": round(byts / kern / 1e9, 1),
                      "frac_alg": round(byts / kern / 1e9 / PEAK_GBS, 4), "rel_residual": resid}
     return {"long_64x1M_f64": out}
+
+
+# Words per point and time step that the calls of Alg. 3 access (coefficients
+# generated, not stored): the right-hand side reads u and writes d, each line
+# solve reads and writes d, the update reads u and d and writes u.
+ALG3_WORDS = {2: 2 + 2 + 2 + 3, 3: 2 + 2 + 2 + 2 + 3}
+
+
+def extra_small_batched(trid):
+    """Batched small meshes at the 2D and 3D application shapes: 2D meshes of
+    32^2..128^2, 1500 and 3000 meshes, 120 steps; 3D meshes of 32^3..96^3, 24 and
+    72 meshes, 100 steps; s = 0.2.  2D runs the LDS-resident time loop (one
+    launch) and, for comparison, the per-step kernels.  Bandwidths count the mesh
+    words every call of Alg. 3 accesses (the convention of the paper's
+    application tables), so the resident loop's figure exceeds what HBM moves."""
+    import numpy as np
+    import torch
+
+    out = {}
+    rng = np.random.default_rng(33)
+    for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
+        w = 4 if dt == torch.float32 else 8
+        for n in (32, 64, 96, 128):
+            for batch in (1500, 3000):
+                steps = 120
+                u0 = torch.from_numpy(rng.uniform(0.0, 1.0, (batch, n, n))).to(dt).cuda()
+                u = u0.clone()
+                res = {}
+                for mode in ("resident", "streamed"):
+                    stream = mode == "streamed"
+                    trid.timing_enable(True)
+                    t = time_calls(lambda: trid.adi_step(u, s0=0.2, nsteps=steps, stream=stream), 2, warm=1)
+                    kt = trid.timing_read()
+                    trid.timing_enable(False)
+                    if mode == "resident" and "adi2d_resident" not in kt:
+                        continue  # does not fit one workgroup's LDS
+                    pts = batch * n * n * steps
+                    r = {"ms": round(t * 1e3, 3), "mpoint_steps_per_s": round(pts / t / 1e6, 1),
+                         "alg3_gbs": round(ALG3_WORDS[2] * w * pts / t / 1e9, 1)}
+                    if stream:
+                        words = {"adi_stencil_x": 2, "adi_y_update": 3}
+                        r["kernel_gbs"] = {k: round(words[k] * w * batch * n * n / (ms / cnt * 1e-3) / 1e9, 1)
+                                           for k, (cnt, ms) in kt.items() if k in words}
+                    res[mode] = r
+                if "resident" in res:
+                    res["speedup_resident"] = round(res["streamed"]["ms"] / res["resident"]["ms"], 2)
+                out["2d_%s_%d^2_x%d" % (tag, n, batch)] = res
+                del u0, u
+        for n in (32, 48, 64, 80, 96):
+            for batch in (24, 72):
+                steps = 100
+                u = torch.from_numpy(rng.uniform(0.0, 1.0, (batch, n, n, n))).to(dt).cuda()
+                t = time_calls(lambda: trid.adi_step(u, s0=0.2, nsteps=steps, graph=True), 2, warm=1)
+                pts = batch * n ** 3 * steps
+                out["3d_%s_%d^3_x%d" % (tag, n, batch)] = {
+                    "ms": round(t * 1e3, 3), "mpoint_steps_per_s": round(pts / t / 1e6, 1),
+                    "alg3_gbs": round(ALG3_WORDS[3] * w * pts / t / 1e9, 1)}
+                del u
+        log("small batched meshes %s done" % tag)
+    return {"adi_small_batched": out}
 
 
 def extra_varlen(trid):

@@ -67,6 +67,7 @@ enum {
 
 /* flags of trid_adi_step */
 #define TRID_ADI_GRAPH 1u /* capture the nsteps launches in a hipGraph once and replay it */
+#define TRID_ADI_STREAM 2u /* 2D: always run the per-step kernels, never the LDS-resident loop */
 
 /* Longest line a single-workgroup tile plan handles (rows). */
 #define TRID_MAX_LINE 8192
@@ -191,6 +192,11 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t p, const void *a, const void *
  * and two in 2D.  The d workspace (one mesh-sized array) is owned by the
  * handle.  With TRID_ADI_GRAPH the launches of all nsteps are captured once
  * into a hipGraph keyed on (u, s, s0, dims, batch, nsteps, dt) and replayed.
+ * 2D meshes of at most 128 points per line whose u, d (and s) fit one
+ * workgroup's LDS run instead as ONE launch with each mesh resident in LDS
+ * for all nsteps (u read and written once; the on-chip pipeline and unrolled
+ * time loop of the 2D application, Section V); TRID_ADI_STREAM forces the
+ * per-step kernels.  Both compute the same steps up to rounding.
  * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED, TRID_ERR_ALLOC, TRID_ERR_HIP. */
 int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, double s0, int ndim,
                   const int64_t *dims, int64_t batch, int nsteps, unsigned flags);

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_PKG, "libtrid.so")
 TRID_F32, TRID_F64 = 0, 1
 PREC_F64, PREC_F32, PREC_F32_REFINE64 = 0, 1, 2
 TRID_ADI_GRAPH = 1
+TRID_ADI_STREAM = 2
 ERRORS = {1: "TRID_ERR_ARG", 2: "TRID_ERR_ALLOC", 3: "TRID_ERR_HIP", 4: "TRID_ERR_UNSUPPORTED"}
 
 # exported symbol -> (argtypes, restype); mirrors include/trid.h
@@ -251,8 +252,10 @@ def gtsv_varlen(prec, a, b, c, d, x, offsets):
     return x
 
 
-def adi_step(u, s=None, s0=0.0, nsteps=1, graph=False):
-    """``nsteps`` ADI steps (Alg. 3) in place on u; s per point (tensor) or constant s0."""
+def adi_step(u, s=None, s0=0.0, nsteps=1, graph=False, stream=False):
+    """``nsteps`` ADI steps (Alg. 3) in place on u; s per point (tensor) or constant s0.
+
+    Small 2D meshes run all steps in one LDS-resident launch unless ``stream``."""
     _dev(u, s)
     _same(u, s)
     h = handle()
@@ -260,7 +263,7 @@ def adi_step(u, s=None, s0=0.0, nsteps=1, graph=False):
     nd, dims, batch = _mesh(u)
     _check(lib.trid_adi_step(h, _dtype_code(u), u.data_ptr(), s.data_ptr() if s is not None else None,
                              float(s0), nd, dims, batch, int(nsteps),
-                             TRID_ADI_GRAPH if graph else 0), h)
+                             (TRID_ADI_GRAPH if graph else 0) | (TRID_ADI_STREAM if stream else 0)), h)
     return u
 
 

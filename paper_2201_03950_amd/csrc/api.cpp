@@ -16,6 +16,7 @@
 #include "dispatch.hpp"
 #include "ext.hpp"
 #include "long_lines.hpp"
+#include "resident.hpp"
 
 using trid::i64;
 
@@ -354,7 +355,7 @@ int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, doub
     if (!u) return fail(h, TRID_ERR_ARG, "u is NULL");
     if (ndim != 2 && ndim != 3) return fail(h, TRID_ERR_ARG, "ADI needs ndim 2 or 3");
     if (nsteps < 0) return fail(h, TRID_ERR_ARG, "nsteps must be >= 0");
-    if (flags & ~TRID_ADI_GRAPH) return fail(h, TRID_ERR_ARG, "unknown flags");
+    if (flags & ~(TRID_ADI_GRAPH | TRID_ADI_STREAM)) return fail(h, TRID_ERR_ARG, "unknown flags");
     i64 inner, n, outer;
     for (int ax = 0; ax < ndim; ++ax) {
         int rc = check_mesh(h, ndim, dims, ax, batch, &inner, &n, &outer);
@@ -363,6 +364,24 @@ int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, doub
     if (nsteps == 0) return TRID_OK;
     const bool f64 = dt == TRID_F64;
     const i64 nx = dims[0], ny = dims[1], nz = ndim == 3 ? dims[2] : 1;
+    if (ndim == 2 && !(flags & TRID_ADI_STREAM)) {
+        trid::ResidentReq rr;
+        rr.f64 = f64;
+        rr.u = u;
+        rr.s = s;
+        rr.s0 = s0;
+        rr.nx = nx;
+        rr.ny = ny;
+        rr.batch = batch;
+        rr.nsteps = nsteps;
+        if (trid::resident_fits(rr)) {
+            hipError_t e = h->ext.timer.time("adi2d_resident", h->stream,
+                                             [&] { return trid::launch_resident(rr, h->stream); });
+            if (e != hipSuccess) return hip_fail(h, e, "resident ADI launch");
+            h->err.clear();
+            return TRID_OK;
+        }
+    }
     const size_t bytes = (size_t)(nx * ny * nz * batch) * (f64 ? 8 : 4);
     void *dws = nullptr;
     int rc = trid::handle_workspace(h, bytes, &dws);

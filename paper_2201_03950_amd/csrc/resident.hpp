@@ -1,0 +1,25 @@
+// resident.hpp -- host entry of the LDS-resident 2D ADI time loop (k_resident.hip).
+#pragma once
+
+#include "dispatch.hpp"
+
+namespace trid {
+
+// `nsteps` 2D ADI steps of `batch` meshes of nx * ny points, each mesh held in
+// one workgroup's LDS for the whole time loop (u read from HBM once, written
+// once).  s per point (s != NULL) or the constant s0.
+struct ResidentReq {
+    bool f64 = true;
+    void *u = nullptr;
+    const void *s = nullptr;
+    double s0 = 0;
+    i64 nx = 1, ny = 1, batch = 1;
+    int nsteps = 1;
+};
+
+// Whether the request fits the resident kernel (lines of at most 128 points,
+// the mesh's arrays within one workgroup's LDS); no HIP calls.
+bool resident_fits(const ResidentReq &r);
+hipError_t launch_resident(const ResidentReq &r, hipStream_t s);
+
+}  // namespace trid

@@ -145,13 +145,14 @@ def test_adi3d_small_matches_oracle(trid, orc, dt, perpoint, graph):
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("perpoint", [False, True])
-def test_adi2d_small_matches_oracle(trid, orc, dt, perpoint):
+@pytest.mark.parametrize("stream", [False, True], ids=["resident", "streamed"])
+def test_adi2d_small_matches_oracle(trid, orc, dt, perpoint, stream):
     dims, batch, steps = (61, 45), 3, 4
     u = gen.adi3d_field(dims, batch, seed=8).astype(dt)
     s = (0.1 * np.exp(0.5 * np.random.default_rng(9).standard_normal(u.shape))).astype(dt) if perpoint else None
     ref = orc.adi_step(u, s=s, s0=0.3, nsteps=steps)
     tu = _t(u)
-    trid.adi_step(tu, s=_t(s) if s is not None else None, s0=0.3, nsteps=steps)
+    trid.adi_step(tu, s=_t(s) if s is not None else None, s0=0.3, nsteps=steps, stream=stream)
     assert _field_err(tu.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
 
 
@@ -301,5 +302,5 @@ def test_adi_const_fast_path_matches_oracle(trid, orc, dt, dims, batch):
     u = gen.adi3d_field(dims, batch, seed=4).astype(dt)
     ref = orc.adi_step(u, s0=0.2, nsteps=3)
     tu = _t(u)
-    trid.adi_step(tu, s0=0.2, nsteps=3)
+    trid.adi_step(tu, s0=0.2, nsteps=3, stream=True)  # the per-step kernels, also in 2D
     assert _field_err(tu.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
