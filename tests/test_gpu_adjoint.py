@@ -116,7 +116,7 @@ def test_kept_step_matches_plain_step_and_recompute(trid, dt, dims, batch):
     u = _t(rng.uniform(0, 1, shape).astype(dt))
     s = _t((0.2 * rng.lognormal(0.0, 0.5, shape)).astype(dt))
     u_plain = u.clone()
-    trid.adi_step(u_plain, s=s, nsteps=1)
+    trid.adi_step(u_plain, s=s, nsteps=1, stream=True)  # the per-step kernels the kept step uses
     u_keep = u.clone()
     ws = [torch.empty_like(u) for _ in range(len(dims))]
     trid.adi_step_keep(u_keep, s, *ws)
