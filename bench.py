@@ -218,9 +218,7 @@ def extra_workloads(trid):
             "frac": round(byts / kern / 1e9 / PEAK_GBS, 4)}
         del ta, tb, tc, td
         torch.cuda.empty_cache()
-    for name, fn in (("adi2d_64x1024sq_xy", extra_2d), ("varlen_20000", extra_varlen),
-                     ("diff_adi3d_128_20steps", extra_gradient), ("long_64x1M_f64", extra_long),
-                     ("adi_small_batched", extra_small_batched)):
+    for name, fn in EXTRA_LEGS.items():
         log("extra: " + name)
         try:
             out.update(fn(trid))
@@ -619,6 +617,12 @@ def cpu_baseline(budget_s=12.0, max_steps=60):
             "sample": "%d ADI step(s) of the 256^3 FP64 workload (s=0.2), %.1f s wall" % (steps, el)}
 
 
+# The other workloads, each a function of the loaded binding returning {name: result}.
+EXTRA_LEGS = {"adi2d_64x1024sq_xy": extra_2d, "varlen_20000": extra_varlen,
+              "diff_adi3d_128_20steps": extra_gradient, "long_64x1M_f64": extra_long,
+              "adi_small_batched": extra_small_batched}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -630,6 +634,8 @@ def main():
                     help="run a plain copy of known size first (counter calibration)")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the HBM-traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--only", choices=sorted(EXTRA_LEGS),
+                    help="run one of the other workloads alone, print its JSON and exit (for profiling)")
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc)
@@ -644,6 +650,9 @@ def main():
 
     trid.load_library()
     torch.cuda.init()
+    if args.only:
+        print(json.dumps(EXTRA_LEGS[args.only](trid)))
+        return
     if args.pmc_copy:
         pmc_copy_calibration()
     log("main workload: 256^3 FP64 ADI, %d warmup + %d timed steps" % (args.warmup, args.steps))

@@ -131,9 +131,11 @@ __device__ __forceinline__ void varlen_finish(int *counter) {
 }
 
 // Dynamic LDS of the uneven-batch kernels: staging region of NT (M + 1)
-// elements of `Big` bytes, then tile ranges, then the solver scratch.
+// elements of `Big` bytes (which also holds the solver scratch), then tile
+// ranges, then `red_bytes` more.
 template <int M, int NT>
 constexpr size_t varlen_lds_bytes(size_t big, size_t red_bytes) {
+    static_assert(M + 1 >= 6, "the staging region holds the reduced solve's 6 NT elements");
     return ((size_t)NT * (M + 1) * big + 15) / 16 * 16 + (size_t)NT * (8 + 4) + red_bytes;
 }
 
@@ -145,7 +147,10 @@ __global__ __launch_bounds__(NT) void k_varlen_plain(VarlenArgs g) {
     T *reg = reinterpret_cast<T *>(smem_raw);
     i64 *s_base = reinterpret_cast<i64 *>(smem_raw + ((size_t)NT * (M + 1) * sizeof(T) + 15) / 16 * 16);
     int *s_cnt = reinterpret_cast<int *>(s_base + NT);
-    T *red = reinterpret_cast<T *>(s_cnt + NT);
+    // the reduced solve's scratch (6 NT elements) reuses the staging region:
+    // the rows are in registers by then, and the solution goes back only after
+    // a barrier
+    T *red = reg;
     const T *arr[4] = {static_cast<const T *>(g.a), static_cast<const T *>(g.b), static_cast<const T *>(g.c),
                        static_cast<const T *>(g.d)};
     T *x = static_cast<T *>(g.x);
@@ -192,6 +197,7 @@ __global__ __launch_bounds__(NT) void k_varlen_plain(VarlenArgs g) {
         reduced_pcr<T, M>(ts, red, NT, P, p, t, 1, f, lv, g.item_pmax[item]);
         T u[M];
         tile_backsub<T, M>(ts, f, lv, u);
+        __syncthreads();  // the reduced solve's last reads of the shared region are done
 #pragma unroll
         for (int k = 0; k < M; ++k) reg[pos + k] = u[k];
         __syncthreads();
@@ -210,7 +216,9 @@ __global__ __launch_bounds__(NT) void k_varlen_refine(VarlenArgs g) {
     float *regf = reinterpret_cast<float *>(smem_raw);
     i64 *s_base = reinterpret_cast<i64 *>(smem_raw + ((size_t)NT * (M + 1) * 8 + 15) / 16 * 16);
     int *s_cnt = reinterpret_cast<int *>(s_base + NT);
-    double *xb = reinterpret_cast<double *>(s_cnt + NT);
+    // refinement scratch (2 NT doubles + 6 NT floats) inside the staging region,
+    // used only between the barriers around refine_tile
+    double *xb = reg;
     float *red = reinterpret_cast<float *>(xb + 2 * NT);
     const float *arr[3] = {static_cast<const float *>(g.a), static_cast<const float *>(g.b),
                            static_cast<const float *>(g.c)};
@@ -255,8 +263,9 @@ __global__ __launch_bounds__(NT) void k_varlen_refine(VarlenArgs g) {
 #pragma unroll
         for (int k = 0; k < M; ++k) dd[k] = (act && p * M + k < n) ? reg[pos + k] : 0.0;
         double out[M];
+        __syncthreads();  // every thread has read its d: the region becomes scratch
         refine_tile<M, false>(cf, dd, red, xb, NT, P, p, t, 1, out, g.item_pmax[item]);
-        // every thread read its d before refine_tile's first barrier: reuse the region
+        __syncthreads();  // scratch reads done: the region takes the solution
 #pragma unroll
         for (int k = 0; k < M; ++k) reg[pos + k] = out[k];
         __syncthreads();
@@ -306,29 +315,29 @@ template <class F>
 auto with_kernel(int prec, int M, int NT, F &&f) -> decltype(f(k_varlen_refine<16, 512>, 512, size_t(0))) {
     if (prec == 2) {
         if (M == 8 && NT == 1024)
-            return f(k_varlen_refine<8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 1024 * (16 + 24)));
+            return f(k_varlen_refine<8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 0));
         if (M == 16 && NT == 512)
-            return f(k_varlen_refine<16, 512>, 512, varlen_lds_bytes<16, 512>(8, 512 * (16 + 24)));
+            return f(k_varlen_refine<16, 512>, 512, varlen_lds_bytes<16, 512>(8, 0));
         if (M == 8 && NT == 256)
-            return f(k_varlen_refine<8, 256>, 256, varlen_lds_bytes<8, 256>(8, 256 * (16 + 24)));
-        return f(k_varlen_refine<32, 256>, 256, varlen_lds_bytes<32, 256>(8, 256 * (16 + 24)));
+            return f(k_varlen_refine<8, 256>, 256, varlen_lds_bytes<8, 256>(8, 0));
+        return f(k_varlen_refine<32, 256>, 256, varlen_lds_bytes<32, 256>(8, 0));
     }
     if (prec == 0) {
         if (M == 16 && NT == 512)
-            return f(k_varlen_plain<double, 16, 512>, 512, varlen_lds_bytes<16, 512>(8, 6 * 512 * 8));
+            return f(k_varlen_plain<double, 16, 512>, 512, varlen_lds_bytes<16, 512>(8, 0));
         if (M == 8 && NT == 1024)
-            return f(k_varlen_plain<double, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 6 * 1024 * 8));
+            return f(k_varlen_plain<double, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 0));
         if (M == 8 && NT == 256)
-            return f(k_varlen_plain<double, 8, 256>, 256, varlen_lds_bytes<8, 256>(8, 6 * 256 * 8));
-        return f(k_varlen_plain<double, 32, 256>, 256, varlen_lds_bytes<32, 256>(8, 6 * 256 * 8));
+            return f(k_varlen_plain<double, 8, 256>, 256, varlen_lds_bytes<8, 256>(8, 0));
+        return f(k_varlen_plain<double, 32, 256>, 256, varlen_lds_bytes<32, 256>(8, 0));
     }
     if (M == 16 && NT == 512)
-        return f(k_varlen_plain<float, 16, 512>, 512, varlen_lds_bytes<16, 512>(4, 6 * 512 * 4));
+        return f(k_varlen_plain<float, 16, 512>, 512, varlen_lds_bytes<16, 512>(4, 0));
     if (M == 8 && NT == 1024)
-        return f(k_varlen_plain<float, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(4, 6 * 1024 * 4));
+        return f(k_varlen_plain<float, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(4, 0));
     if (M == 8 && NT == 256)
-        return f(k_varlen_plain<float, 8, 256>, 256, varlen_lds_bytes<8, 256>(4, 6 * 256 * 4));
-    return f(k_varlen_plain<float, 32, 256>, 256, varlen_lds_bytes<32, 256>(4, 6 * 256 * 4));
+        return f(k_varlen_plain<float, 8, 256>, 256, varlen_lds_bytes<8, 256>(4, 0));
+    return f(k_varlen_plain<float, 32, 256>, 256, varlen_lds_bytes<32, 256>(4, 0));
 }
 
 }  // namespace
