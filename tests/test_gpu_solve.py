@@ -86,7 +86,7 @@ def test_arrays_any_axis(trid, orc, dt, geom):
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("mode", ["const", "s"])
 @pytest.mark.parametrize("geom", [((33, 41, 10), 2, 0), ((33, 41, 10), 2, 1), ((33, 41, 10), 2, 2),
-                                  ((300, 7), 1, 0), ((7, 300), 1, 1)])
+                                  ((300, 7), 1, 0), ((7, 300), 1, 1), ((9, 1100), 1, 1), ((6, 4, 1500), 1, 2)])
 def test_generated_coefficients(trid, orc, dt, mode, geom):
     dims, batch, axis = geom
     rng = np.random.default_rng(5)
