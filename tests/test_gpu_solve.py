@@ -103,6 +103,23 @@ def test_generated_coefficients(trid, orc, dt, mode, geom):
     assert _line_err(td.cpu().numpy().astype(np.float64), ref, axis) <= TOL[dt]
 
 
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("mode", ["arrays", "s"])
+def test_x_lines_large_grid(trid, orc, dt, mode):
+    """65,536 x lines of 200 rows: a grid of many thousand blocks (arrays loaded
+    one at a time), against the small grids of the other cases (all at once)."""
+    a, b, c, d = (v.astype(dt) for v in gen.dd_lines(65536, 200, seed=12))
+    td = _t(d[None])
+    if mode == "arrays":
+        ref = orc.gtsv(a[None], b[None], c[None], d[None], 0)
+        trid.gtsv(_t(a[None]), _t(b[None]), _t(c[None]), td, 0)
+    else:
+        s = (0.5 * b).astype(dt)
+        ref = orc.gtsv_s(s[None], d[None], 0)
+        trid.gtsv_s(_t(s[None]), td, 0)
+    assert _line_err(td.cpu().numpy().astype(np.float64), ref, 0) <= TOL[dt]
+
+
 PLANS = [(8, 1), (8, 2), (8, 16), (8, 64), (16, 1), (16, 8), (16, 32), (32, 1), (32, 4), (32, 8)]
 
 
