@@ -487,13 +487,13 @@ def extra_gradient(trid):
             uT = autograd.adi(tu, s0 * tk, steps, False)
             return torch.sum((uT.double() - target.double()) ** 2)
 
-    def fwd_bwd(keep):
-        k = tk.clone().requires_grad_(True)
-        u = tu.clone().requires_grad_(True)
+    def fwd_bwd(keep, dt=torch.float32):
+        k = tk.detach().to(dt).clone().requires_grad_(True)  # fresh leaves every call
+        u = tu.detach().to(dt).clone().requires_grad_(True)
         uT = autograd.adi(u, s0 * k, steps, keep)
         loss = torch.sum((uT.double() - target.double()) ** 2)
         loss.backward()
-        return k.grad
+        return k.grad, u.grad
 
     tf = time_calls(fwd, 3, warm=1)
     trid.timing_enable(True)
@@ -521,11 +521,22 @@ def extra_gradient(trid):
     u64 = tu.double()
     k64 = tk.double()
     tf64 = time_calls(lambda: autograd.adi(u64, s0 * k64, steps, False), 3, warm=1)
+    # gradient error of the FP32 run: normwise against the FP64 GPU gradient of
+    # the same loss (the FP64 path is itself checked against the oracle's
+    # adjoint and finite differences in the tests)
+    gk32, gu32 = fwd_bwd(True)
+    gk64, gu64 = fwd_bwd(True, torch.float64)
+
+    def nrel(a, b):
+        return float((a.double() - b).norm() / b.norm())
+
+    grad_err = {"dL_dkappa": nrel(gk32, gk64), "dL_du0": nrel(gu32, gu64)}
     return {"diff_adi3d_128_20steps": {"fwd_ms_f32": round(tf * 1e3, 3), "fwd_bwd_ms_f32": round(tb_keep * 1e3, 3),
                                        "fwd_bwd_over_fwd": round(tb_keep / tf, 3),
                                        "fwd_bwd_ms_f32_recompute": round(tb_rec * 1e3, 3),
                                        "fwd_bwd_over_fwd_recompute": round(tb_rec / tf, 3),
                                        "fwd_ms_f64": round(tf64 * 1e3, 3),
+                                       "grad_err_f32_vs_f64": grad_err,
                                        "fwd_kernel_us": fwd_kernels, "kept_kernels_count_us": kept_kernels}}
 
 
@@ -612,9 +623,17 @@ def cpu_baseline(budget_s=12.0, max_steps=60):
         u = oracle.adi_step(u, s0=0.2, nsteps=1)
         steps += 1
     el = time.perf_counter() - t0
+    cores = oracle.num_threads()
+    # the same oracle on one host thread, one step
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    oracle.adi_step(u, s0=0.2, nsteps=1)
+    el1 = time.perf_counter() - t1
+    oracle.set_num_threads(cores)
     return {"value": round(3 * 65536 * steps / el, 1), "unit": "solves/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "%d ADI step(s) of the 256^3 FP64 workload (s=0.2), %.1f s wall" % (steps, el)}
+            "cores": cores, "kind": "oracle",
+            "sample": "%d ADI step(s) of the 256^3 FP64 workload (s=0.2), %.1f s wall" % (steps, el),
+            "value_1_thread": round(3 * 65536 / el1, 1)}
 
 
 # The other workloads, each a function of the loaded binding returning {name: result}.
