@@ -343,18 +343,19 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
                     delete sc;
                 }
             }
-            xs.tuned[pkey] = {best->M, best->NT};
+            xs.tuned[pkey] = {best->M, best->NT, best->thomas};
             if (best_split)
-                xs.tuned[pkey + "/small"] = {small.M, small.NT};
+                xs.tuned[pkey + "/small"] = {small.M, small.NT, small.thomas};
             else
                 xs.tuned.erase(pkey + "/small");
         } else {
             trid::VarlenVariant v = cands.front();
             if (tuned != xs.tuned.end())
                 for (const auto &c2 : cands)
-                    if (c2.M == tuned->second.first && c2.NT == tuned->second.second) v = c2;
-            const bool split = tuned_small != xs.tuned.end() && tuned_small->second.first == small.M &&
-                               tuned_small->second.second == small.NT && maxlen > (int64_t)small.M * small.NT;
+                    if (c2.M == tuned->second.M && c2.NT == tuned->second.NT && c2.thomas == tuned->second.thomas)
+                        v = c2;
+            const bool split = tuned_small != xs.tuned.end() && tuned_small->second.M == small.M &&
+                               tuned_small->second.NT == small.NT && maxlen > (int64_t)small.M * small.NT;
             best = new trid::VarlenSchedule();
             hipError_t e = trid::varlen_build(off, nsys, p, v, best, split ? &small : nullptr);
             if (e != hipSuccess) {
@@ -592,7 +593,8 @@ int trid_plan_save(trid_handle_t h, const char *path) {
     f << "{\n \"arch\": \"" << device_arch() << "\",\n \"plans\": {\n";
     size_t i = 0;
     for (auto &kv : x.tuned) {
-        f << "  \"" << kv.first << "\": {\"M\": " << kv.second.first << ", \"NT\": " << kv.second.second << "}"
+        f << "  \"" << kv.first << "\": {\"M\": " << kv.second.M << ", \"NT\": " << kv.second.NT
+          << ", \"reduced\": \"" << (kv.second.thomas ? "thomas" : "pcr") << "\"}"
           << (++i < x.tuned.size() ? "," : "") << "\n";
     }
     f << " }\n}\n";
@@ -612,8 +614,10 @@ int trid_plan_load(trid_handle_t h, const char *path) {
         if (mpos == std::string::npos || npos == std::string::npos || q1 == std::string::npos) continue;
         const std::string key = line.substr(q0 + 1, q1 - q0 - 1);
         const int M = std::atoi(line.c_str() + mpos + 4), NT = std::atoi(line.c_str() + npos + 5);
+        // "reduced": "thomas" selects the Thomas reduced solve (absent: PCR)
+        const int thomas = line.find("\"thomas\"") != std::string::npos ? 1 : 0;
         if (key.rfind("varlen/", 0) != 0 || M <= 0 || NT <= 0) continue;  // unknown keys are ignored
-        x.tuned[key] = {M, NT};
+        x.tuned[key] = {M, NT, thomas};
     }
     return TRID_OK;
 }

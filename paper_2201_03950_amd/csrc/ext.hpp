@@ -101,11 +101,16 @@ struct KernelTimer {
     }
 };
 
+// A tuned uneven-batch plan: tile rows, threads per work item, reduced solve.
+struct TunedPlan {
+    int M = 0, NT = 0, thomas = 0;
+};
+
 struct ExtState {
     int force_M = 0;  // forced tile rows (0: automatic)
     int force_L = 0;  // forced lines per block (0: automatic)
-    // tuned plans: key -> (M, L)
-    std::map<std::string, std::pair<int, int>> tuned;
+    // tuned plans: key -> plan
+    std::map<std::string, TunedPlan> tuned;
     // uneven-batch schedules keyed by a hash of the offsets
     std::map<std::string, VarlenSchedule *> varlen;
     // scratch for adjoint / refinement entry points

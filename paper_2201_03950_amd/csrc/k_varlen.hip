@@ -139,7 +139,56 @@ constexpr size_t varlen_lds_bytes(size_t big, size_t red_bytes) {
     return ((size_t)NT * (M + 1) * big + 15) / 16 * 16 + (size_t)NT * (8 + 4) + red_bytes;
 }
 
-template <typename T, int M, int NT>
+// Reduced solve by Thomas (Alg. 1): the Thomas-Thomas hybrid of Section III-B.
+// Each tile forms its row of the reduced system over the tiles' first unknowns
+// (the same local elimination as the PCR form), then the first thread of each
+// system runs Thomas over the system's P rows in LDS.  sh: 4 S elements; every
+// thread of the block calls it (three barriers).
+template <typename T, int M>
+__device__ __forceinline__ void reduced_thomas(const TileState<T, M> &ts, T *__restrict__ sh, int S, int P, int p,
+                                               int slot, T &f, T &lv) {
+    T *ga = sh, *gb = sh + S, *gc = sh + 2 * S, *gd = sh + 3 * S;
+    ga[slot] = ts.la;  // the tiles' last rows first
+    gb[slot] = ts.lc;
+    gc[slot] = ts.ld;
+    __syncthreads();
+    T pa = T(0), pc = T(0), pd = T(0);
+    if (p > 0) {
+        pa = ga[slot - 1];
+        pc = gb[slot - 1];
+        pd = gc[slot - 1];
+    }
+    __syncthreads();
+    ga[slot] = -ts.fa * pa;
+    gb[slot] = ts.fb - ts.fa * pc - ts.fc * ts.la;
+    gc[slot] = -ts.fc * ts.lc;
+    gd[slot] = ts.fd - ts.fa * pd - ts.fc * ts.ld;
+    __syncthreads();
+    if (p == 0) {  // Alg. 1 over rows slot .. slot + P - 1; c* kept in gc, x written to gd
+        T cp = gc[slot] / gb[slot], dp = gd[slot] / gb[slot];
+        gc[slot] = cp;
+        gd[slot] = dp;
+        for (int i = 1; i < P; ++i) {
+            const T a = ga[slot + i];
+            const T r = T(1) / (gb[slot + i] - a * cp);
+            cp = r * gc[slot + i];
+            dp = r * (gd[slot + i] - a * dp);
+            gc[slot + i] = cp;
+            gd[slot + i] = dp;
+        }
+        T x = dp;
+        for (int i = P - 2; i >= 0; --i) {
+            x = gd[slot + i] - gc[slot + i] * x;
+            gd[slot + i] = x;
+        }
+    }
+    __syncthreads();
+    f = gd[slot];
+    const T fn = (p + 1 < P) ? gd[slot + 1] : T(0);
+    lv = ts.ld - ts.la * f - ts.lc * fn;
+}
+
+template <typename T, int M, int NT, bool THOMAS>
 __global__ __launch_bounds__(NT) void k_varlen_plain(VarlenArgs g) {
     __shared__ int s_item;
     __shared__ short s_sys[NT], s_p[NT];
@@ -194,7 +243,10 @@ __global__ __launch_bounds__(NT) void k_varlen_plain(VarlenArgs g) {
         TileState<T, M> ts;
         tile_eliminate<T, M>(ra, rb, rc, rd, ts);
         T f, lv;
-        reduced_pcr<T, M>(ts, red, NT, P, p, t, 1, f, lv, g.item_pmax[item]);
+        if constexpr (THOMAS)
+            reduced_thomas<T, M>(ts, red, NT, P, p, t, f, lv);
+        else
+            reduced_pcr<T, M>(ts, red, NT, P, p, t, 1, f, lv, g.item_pmax[item]);
         T u[M];
         tile_backsub<T, M>(ts, f, lv, u);
         __syncthreads();  // the reduced solve's last reads of the shared region are done
@@ -302,8 +354,8 @@ hipError_t launch_persistent(K kernel, int nt, size_t lds, const VarlenSchedule 
 
 // The (M, NT) variants compiled for each precision.
 const std::vector<VarlenVariant> &varlen_variants(int prec) {
-    static const std::vector<VarlenVariant> f64 = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}};
-    static const std::vector<VarlenVariant> f32 = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}};
+    static const std::vector<VarlenVariant> f64 = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}, {16, 512, 1}, {32, 256, 1}};
+    static const std::vector<VarlenVariant> f32 = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}, {16, 512, 1}, {32, 256, 1}};
     static const std::vector<VarlenVariant> ref = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}};
     return prec == 0 ? f64 : (prec == 1 ? f32 : ref);
 }
@@ -312,7 +364,15 @@ namespace {
 
 // Calls f(kernel, threads, dynamic LDS bytes) for the compiled variant (prec, M, NT).
 template <class F>
-auto with_kernel(int prec, int M, int NT, F &&f) -> decltype(f(k_varlen_refine<16, 512>, 512, size_t(0))) {
+auto with_kernel(int prec, int M, int NT, int thomas, F &&f) -> decltype(f(k_varlen_refine<16, 512>, 512, size_t(0))) {
+    if (thomas && prec == 0) {
+        if (M == 16) return f(k_varlen_plain<double, 16, 512, true>, 512, varlen_lds_bytes<16, 512>(8, 0));
+        return f(k_varlen_plain<double, 32, 256, true>, 256, varlen_lds_bytes<32, 256>(8, 0));
+    }
+    if (thomas && prec == 1) {
+        if (M == 16) return f(k_varlen_plain<float, 16, 512, true>, 512, varlen_lds_bytes<16, 512>(4, 0));
+        return f(k_varlen_plain<float, 32, 256, true>, 256, varlen_lds_bytes<32, 256>(4, 0));
+    }
     if (prec == 2) {
         if (M == 8 && NT == 1024)
             return f(k_varlen_refine<8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 0));
@@ -324,20 +384,20 @@ auto with_kernel(int prec, int M, int NT, F &&f) -> decltype(f(k_varlen_refine<1
     }
     if (prec == 0) {
         if (M == 16 && NT == 512)
-            return f(k_varlen_plain<double, 16, 512>, 512, varlen_lds_bytes<16, 512>(8, 0));
+            return f(k_varlen_plain<double, 16, 512, false>, 512, varlen_lds_bytes<16, 512>(8, 0));
         if (M == 8 && NT == 1024)
-            return f(k_varlen_plain<double, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(8, 0));
+            return f(k_varlen_plain<double, 8, 1024, false>, 1024, varlen_lds_bytes<8, 1024>(8, 0));
         if (M == 8 && NT == 256)
-            return f(k_varlen_plain<double, 8, 256>, 256, varlen_lds_bytes<8, 256>(8, 0));
-        return f(k_varlen_plain<double, 32, 256>, 256, varlen_lds_bytes<32, 256>(8, 0));
+            return f(k_varlen_plain<double, 8, 256, false>, 256, varlen_lds_bytes<8, 256>(8, 0));
+        return f(k_varlen_plain<double, 32, 256, false>, 256, varlen_lds_bytes<32, 256>(8, 0));
     }
     if (M == 16 && NT == 512)
-        return f(k_varlen_plain<float, 16, 512>, 512, varlen_lds_bytes<16, 512>(4, 0));
+        return f(k_varlen_plain<float, 16, 512, false>, 512, varlen_lds_bytes<16, 512>(4, 0));
     if (M == 8 && NT == 1024)
-        return f(k_varlen_plain<float, 8, 1024>, 1024, varlen_lds_bytes<8, 1024>(4, 0));
+        return f(k_varlen_plain<float, 8, 1024, false>, 1024, varlen_lds_bytes<8, 1024>(4, 0));
     if (M == 8 && NT == 256)
-        return f(k_varlen_plain<float, 8, 256>, 256, varlen_lds_bytes<8, 256>(4, 0));
-    return f(k_varlen_plain<float, 32, 256>, 256, varlen_lds_bytes<32, 256>(4, 0));
+        return f(k_varlen_plain<float, 8, 256, false>, 256, varlen_lds_bytes<8, 256>(4, 0));
+    return f(k_varlen_plain<float, 32, 256, false>, 256, varlen_lds_bytes<32, 256>(4, 0));
 }
 
 }  // namespace
@@ -407,7 +467,9 @@ hipError_t build_ids(const int64_t *offsets_host, std::vector<int> ids, int prec
     if ((e = hipMemcpy(sc->item_begin, item_begin.data(), b_ib, hipMemcpyHostToDevice)) != hipSuccess) return e;
     if ((e = hipMemcpy(sc->item_pmax, item_pmax.data(), b_ip, hipMemcpyHostToDevice)) != hipSuccess) return e;
     if ((e = hipMemset(sc->counter, 0, 2 * sizeof(int))) != hipSuccess) return e;
-    sc->nblocks = with_kernel(prec, v.M, v.NT, [&](auto k, int nt, size_t lds) { return occupancy_blocks(k, nt, lds); });
+    sc->thomas = v.thomas;
+    sc->nblocks =
+        with_kernel(prec, v.M, v.NT, v.thomas, [&](auto k, int nt, size_t lds) { return occupancy_blocks(k, nt, lds); });
     sc->nblocks = std::max(1, std::min(sc->nblocks, sc->nitems));
     return hipSuccess;
 }
@@ -445,7 +507,7 @@ hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b,
     g.item_pmax = sc.item_pmax;
     g.counter = sc.counter;
     g.nitems = sc.nitems;
-    hipError_t e = with_kernel(sc.prec, sc.M, sc.NT,
+    hipError_t e = with_kernel(sc.prec, sc.M, sc.NT, sc.thomas,
                                [&](auto k, int nt, size_t lds) { return launch_persistent(k, nt, lds, sc, g, s); });
     if (e != hipSuccess || !sc.next) return e;
     return varlen_launch(*sc.next, a, b, c, d, x, s);

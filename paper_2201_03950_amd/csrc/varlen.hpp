@@ -12,14 +12,17 @@ namespace trid {
 
 using i64 = int64_t;
 
-// A compiled tile plan: M rows per tile, NT threads (tiles) per work item.
+// A compiled tile plan: M rows per tile, NT threads (tiles) per work item;
+// thomas = 1: reduced systems solved by Thomas on one thread per system
+// (the Thomas-Thomas hybrid), else by PCR across the system's tiles.
 struct VarlenVariant {
     int M, NT;
+    int thomas = 0;
 };
 
 struct VarlenSchedule {
     int prec = 0;  // 0: FP64, 1: FP32, 2: FP32 + FP64 refinement
-    int M = 16, NT = 512;
+    int M = 16, NT = 512, thomas = 0;
     i64 nsys = 0;
     int nitems = 0, nblocks = 0;
     void *dev = nullptr;  // single device allocation holding the arrays below

@@ -106,10 +106,20 @@ def test_varlen_autotune_and_plan_cache(trid, orc, tmp_path, monkeypatch):
         trid.plan_load(str(tmp_path / "missing.json"))
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "refine"])
-def test_varlen_split_plan_matches_oracle(trid, orc, tmp_path, monkeypatch, prec):
-    """A split plan (systems above 2048 rows in 1024-thread blocks, the rest in
-    256-thread blocks, two launches), forced through the plan cache of a fresh handle."""
+FORCED = {
+    # systems above 2048 rows in 1024-thread blocks, the rest in 256-thread blocks (two launches)
+    "split": '"%s": {"M": 8, "NT": 1024},\n  "%s/small": {"M": 8, "NT": 256}',
+    # reduced systems solved by Thomas on one thread per system (Thomas-Thomas)
+    "thomas16": '"%s": {"M": 16, "NT": 512, "reduced": "thomas"}',
+    "thomas32": '"%s": {"M": 32, "NT": 256, "reduced": "thomas"}',
+}
+
+
+@pytest.mark.parametrize("prec,plan", [("f64", "split"), ("f32", "split"), ("refine", "split"),
+                                       ("f64", "thomas16"), ("f64", "thomas32"), ("f32", "thomas16"),
+                                       ("f32", "thomas32")])
+def test_varlen_forced_plan_matches_oracle(trid, orc, tmp_path, monkeypatch, prec, plan):
+    """A plan forced through the plan cache of a fresh handle."""
     import json
     import threading
 
@@ -124,9 +134,9 @@ def test_varlen_split_plan_matches_oracle(trid, orc, tmp_path, monkeypatch, prec
     saved = tmp_path / "tuned.json"
     trid.plan_save(str(saved))
     key = next(k for k in json.loads(saved.read_text())["plans"] if k.startswith("varlen/") and "/small" not in k)
-    forced = tmp_path / "split.json"
-    forced.write_text('{\n "plans": {\n  "%s": {"M": 8, "NT": 1024},\n  "%s/small": {"M": 8, "NT": 256}\n }\n}\n'
-                      % (key, key))
+    forced = tmp_path / "forced.json"
+    entry = FORCED[plan] % ((key, key) if plan == "split" else key)
+    forced.write_text('{\n "plans": {\n  %s\n }\n}\n' % entry)
     out = {}
 
     def worker():  # a new thread gets a new library handle (empty schedule cache)
