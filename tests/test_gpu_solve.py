@@ -120,6 +120,31 @@ def test_x_lines_large_grid(trid, orc, dt, mode):
     assert _line_err(td.cpu().numpy().astype(np.float64), ref, 0) <= TOL[dt]
 
 
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("mode", ["arrays", "s", "const"])
+@pytest.mark.parametrize("axis", [0, 1])
+def test_lines_of_maximum_length(trid, orc, dt, mode, axis):
+    """Lines of TRID_MAX_LINE = 8192 rows, the longest one workgroup holds,
+    along x (staged) and y (strided, 3 lines)."""
+    n, m = 8192, 3
+    a, b, c, d = (v.astype(dt) for v in gen.dd_lines(m, n, seed=81))
+    if axis == 1:  # dims [3, 8192]: the 3 lines interleaved
+        a, b, c, d = (np.ascontiguousarray(v.T) for v in (a, b, c, d))
+    a, b, c, d = (v[None] for v in (a, b, c, d))
+    td = _t(d)
+    if mode == "arrays":
+        ref = orc.gtsv(a, b, c, d, axis)
+        trid.gtsv(_t(a), _t(b), _t(c), td, axis)
+    elif mode == "s":
+        s = (0.5 * b).astype(dt)
+        ref = orc.gtsv_s(s, d, axis)
+        trid.gtsv_s(_t(s), td, axis)
+    else:
+        ref = orc.gtsv_const(-0.3, 1.7, -0.4, d, axis)
+        trid.gtsv_const(-0.3, 1.7, -0.4, td, axis)
+    assert _line_err(td.cpu().numpy().astype(np.float64), ref, axis) <= TOL[dt]
+
+
 PLANS = [(8, 1), (8, 2), (8, 16), (8, 64), (16, 1), (16, 8), (16, 32), (32, 1), (32, 4), (32, 8)]
 
 
