@@ -190,7 +190,21 @@ def extra_workloads(trid):
         (cnt, ms), = trid.timing_read().values()
         trid.timing_enable(False)
         kus = ms / cnt * 1e3
+        # the same call captured 100 times in one graph (torch's capture of the
+        # library's launches on the current stream), replayed: no launch overhead
+        gph = torch.cuda.CUDAGraph()
+        cap = torch.cuda.Stream()
+        cap.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cap):
+            trid.gtsv(ta, tb, tc, td, axis)  # workspace and plans exist before capture
+            with torch.cuda.graph(gph, stream=cap):
+                for _ in range(100):
+                    trid.gtsv(ta, tb, tc, td, axis)
+        torch.cuda.current_stream().wait_stream(cap)
+        tg = time_calls(gph.replay, 20, warm=2) / 100
         out["sys1024x256_f64_%s" % lay] = {"us_per_call": round(t * 1e6, 2),
+                                          "us_per_call_graph": round(tg * 1e6, 2),
+                                          "solves_per_s_graph": round(1024 / tg, 1),
                                           "solves_per_s": round(1024 / t, 1),
                                           "kernel_us": round(kus, 2),
                                           "solves_per_s_kernel": round(1024 / (kus * 1e-6), 1),

@@ -61,6 +61,38 @@ def test_config0_1024_systems_n256_fp64(trid, orc, layout):
     assert _line_err(td.cpu().numpy(), ref, axis) <= 1e-12
 
 
+@pytest.mark.parametrize("layout", ["x", "y"])
+def test_config0_graph_replays_match_eager(trid, orc, layout):
+    """The batched solve captured in a torch CUDA graph (the library launches on
+    the capturing stream) and replayed three times, with eager work between the
+    replays: every replay equals the eager call bitwise and the oracle to 1e-12."""
+    a, b, c, d = gen.dd_lines(1024, 256, seed=0)
+    arrs = [v[None] if layout == "x" else np.ascontiguousarray(v.T)[None] for v in (a, b, c, d)]
+    axis = 0 if layout == "x" else 1
+    ref = orc.gtsv(*arrs, axis)
+    ta, tb, tc, td0 = (_t(v) for v in arrs)
+    eager = td0.clone()
+    trid.gtsv(ta, tb, tc, eager, axis)
+    td = td0.clone()
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        warm = td0.clone()
+        trid.gtsv(ta, tb, tc, warm, axis)
+        with torch.cuda.graph(g, stream=cap):
+            trid.gtsv(ta, tb, tc, td, axis)
+    torch.cuda.current_stream().wait_stream(cap)
+    for _ in range(3):
+        td.copy_(td0)
+        g.replay()
+        other = td0.clone()
+        trid.gtsv(ta, tb, tc, other, axis)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(td, eager)
+        assert _line_err(td.cpu().numpy(), ref, axis) <= 1e-12
+
+
 # ------------------------------------------------------ geometry / plan sweep --
 
 GEOMS = [
