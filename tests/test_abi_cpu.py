@@ -108,6 +108,8 @@ def test_adi_argument_checks(lib, h):
     assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, -1, 0) == 1
     assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, 1, 8) == 1  # unknown flag
     assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, 0, 0) == 0  # no steps: no-op
+    assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 2, _dims(8, 8), 1, 0, 3) == 0  # graph | stream: valid flags
+    assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 2, _dims(8, 8), 1, 0, 4) == 1  # unknown flag
 
 
 def test_set_tile_validation(lib, h):
