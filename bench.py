@@ -384,7 +384,7 @@ def extra_small_batched(trid):
     rng = np.random.default_rng(33)
     for dt, tag in ((torch.float32, "f32"), (torch.float64, "f64")):
         w = 4 if dt == torch.float32 else 8
-        for n in (32, 64, 96, 128):
+        for n in (32, 48, 64, 80, 96, 112, 128):
             for batch in (1500, 3000):
                 steps = 120
                 u0 = torch.from_numpy(rng.uniform(0.0, 1.0, (batch, n, n))).to(dt).cuda()

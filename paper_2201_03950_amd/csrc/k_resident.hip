@@ -12,8 +12,10 @@
 //     reduced solve by PCR over DPP row shifts, Alg. 2) and stores d;
 //   phase B (y lines): thread (x, q) owns tile q of column x, solves d along y
 //     and adds the result to u.
-// Lines are cut into P tiles of M = 8 rows with P a power of two <= 16 (rows
-// beyond the mesh are identity rows), so a line's tiles are P adjacent lanes.
+// Lines are cut into P tiles of M rows (M = 8, 10, 12 or 14, chosen so that the
+// tiles cover the line with the least padding) with P a power of two <= 16
+// (rows beyond the mesh are identity rows), so a line's tiles are P adjacent
+// lanes.
 // LDS holds u, d (and s when it varies per point) with a host-chosen row pitch
 // and per-tile skews that spread both phases' accesses over the banks.
 #include <algorithm>
@@ -28,22 +30,31 @@ namespace trid {
 
 namespace {
 
-constexpr int kRM = 8;           // rows per tile
-constexpr int kMaxLine = 128;    // 16 tiles
-constexpr int kMaxThreads = 1024;
+constexpr int kTileRows[4] = {8, 10, 12, 14};
+constexpr int kMaxLine = 128;    // 16 tiles of 8 rows
 constexpr size_t kLdsBytes = 160 * 1024;
+
+// Threads per workgroup at most: 1024 for 8-row tiles, 512 for longer tiles
+// (their registers).
+constexpr int max_threads(int M) { return M <= 8 ? 1024 : 512; }
 
 struct ResGeom {
     int nx, ny;
+    int m;          // rows per tile
     int px, py;     // tiles per x line and per y line (powers of two)
-    int ldx, skw;   // row pitch, extra offset per block of 8 rows (elements)
-    int tp;         // 1: one pad element after every 8 points of a row
+    int ldx, skw;   // row pitch, extra offset per block of m rows (elements)
+    int tp;         // 1: one pad element after every m points of a row
     int region;     // elements per array (multiple of 4)
     int nsteps;
 };
 
+// LDS position of point (y, x); M is the tile size (g.m), a constant in kernels.
+template <int M>
 __host__ __device__ __forceinline__ int res_at(const ResGeom &g, int y, int x) {
-    return y * g.ldx + (y >> 3) * g.skw + x + (g.tp ? (x >> 3) : 0);
+    return y * g.ldx + (y / M) * g.skw + x + (g.tp ? (x / M) : 0);
+}
+__host__ __forceinline__ int res_at_h(const ResGeom &g, int y, int x) {
+    return y * g.ldx + (y / g.m) * g.skw + x + (g.tp ? (x / g.m) : 0);
 }
 
 // Rows (-s, 1 + 2 s, -s) of one tile along a line of n points starting at
@@ -249,9 +260,9 @@ __device__ __forceinline__ void cf_solve_p(const T *tab, int P, int p, const T (
     }
 }
 
-template <typename T, bool PS>
-__global__ __launch_bounds__(kMaxThreads) void k_adi2d_resident(ResGeom g, T *__restrict__ u_all,
-                                                               const T *__restrict__ s_all, T s0) {
+template <typename T, bool PS, int kRM>
+__global__ __launch_bounds__(max_threads(kRM)) void k_adi2d_resident(ResGeom g, T *__restrict__ u_all,
+                                                                    const T *__restrict__ s_all, T s0) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *U = reinterpret_cast<T *>(smem_raw);
     T *D = U + g.region;
@@ -263,8 +274,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_adi2d_resident(ResGeom g, T *__
     const T *sm = PS ? s_all + (i64)blockIdx.x * npts : nullptr;
     for (int e = t; e < npts; e += nt) {
         const int y = e / nx, x = e - y * nx;
-        U[res_at(g, y, x)] = um[e];
-        if (PS) S[res_at(g, y, x)] = sm[e];
+        U[res_at<kRM>(g, y, x)] = um[e];
+        if (PS) S[res_at<kRM>(g, y, x)] = sm[e];
     }
     if (!PS && t < 64) {  // one wavefront tabulates both line directions
         cf_setup_p<T, kRM>(s0, nx, g.px, t, tabA);
@@ -278,8 +289,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_adi2d_resident(ResGeom g, T *__
             const int y = yb + t / g.px, p = t % g.px, x0 = p * kRM;
             const bool live = y < ny;
             const int ya = live ? y : 0;  // dead lanes address row 0
-            const int base = res_at(g, ya, x0);
-            const int dn = res_at(g, ya + 1, x0) - base, ds = base - res_at(g, ya > 0 ? ya - 1 : 0, x0);
+            const int base = res_at<kRM>(g, ya, x0);
+            const int dn = res_at<kRM>(g, ya + 1, x0) - base, ds = base - res_at<kRM>(g, ya > 0 ? ya - 1 : 0, x0);
             const bool hn = live && y + 1 < ny, hs = live && y > 0;
             // guarded LDS reads fall back to the tile's own first point (always
             // inside the array), so no lane addresses past it
@@ -324,7 +335,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_adi2d_resident(ResGeom g, T *__
             for (int k = 0; k < kRM; ++k) {
                 const int y = y0 + k;
                 const bool v = live && y < ny;
-                off[k] = res_at(g, v ? y : 0, xa);
+                off[k] = res_at<kRM>(g, v ? y : 0, xa);
                 rd[k] = load_if(D, off[k], v, off[k]);
                 sv[k] = PS ? load_if(S, off[k], v, off[k]) : s0;
             }
@@ -346,7 +357,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_adi2d_resident(ResGeom g, T *__
     }
     for (int e = t; e < npts; e += nt) {
         const int y = e / nx, x = e - y * nx;
-        um[e] = U[res_at(g, y, x)];
+        um[e] = U[res_at<kRM>(g, y, x)];
     }
 }
 
@@ -356,14 +367,14 @@ int pow2_ceil(int v) {
     return p;
 }
 
-int tiles_of(i64 n) { return pow2_ceil((int)((n + kRM - 1) / kRM)); }
+int tiles_of(i64 n, int M) { return pow2_ceil((int)((n + M - 1) / M)); }
 
-// Threads per workgroup: one per tile of a pass over the lines; 1024 only
-// when a direction has at least 2048 tiles (measured: 128^2 gains, 96^2 and
-// 64^2 do not).
+// Threads per workgroup: one per tile of a pass over the lines; 1024 (8-row
+// tiles only) when a direction has at least 2048 tiles (measured: 128^2 gains,
+// 96^2 and 64^2 do not).
 int threads_of(const ResGeom &g) {
     const int need = std::max(g.ny * g.px, g.nx * g.py);
-    const int cap = need >= 2048 ? kMaxThreads : kMaxThreads / 2;
+    const int cap = need >= 2048 ? max_threads(g.m) : 512;
     return std::max(64, std::min(cap, pow2_ceil(need)));
 }
 
@@ -375,14 +386,14 @@ int bank_conflicts(const ResGeom &g, int w) {
     int worst = 0;
     for (int phase = 0; phase < 2; ++phase) {
         const int P = phase == 0 ? g.px : g.py;
-        for (int k = 0; k < kRM; ++k) {
+        for (int k = 0; k < g.m; ++k) {
             int cnt[32] = {0};
             for (int l = 0; l < lanes; ++l) {
                 const int line = l / P, tile = l % P;
-                const int y = phase == 0 ? line : tile * kRM + k;
-                const int x = phase == 0 ? tile * kRM + k : line;
+                const int y = phase == 0 ? line : tile * g.m + k;
+                const int x = phase == 0 ? tile * g.m + k : line;
                 if (y >= g.ny || x >= g.nx) continue;
-                const int a = res_at(g, y, x) * w / 4;
+                const int a = res_at_h(g, y, x) * w / 4;
                 for (int dw = 0; dw < w / 4; ++dw) worst = std::max(worst, ++cnt[(a + dw) % 32]);
             }
         }
@@ -390,12 +401,23 @@ int bank_conflicts(const ResGeom &g, int w) {
     return worst;
 }
 
-bool search_layout(const ResidentReq &r, ResGeom *out, size_t *bytes) {
+int cf_fields(int M, int P) {
+    switch (M) {
+        case 8: return CF<8>::fields(P);
+        case 10: return CF<10>::fields(P);
+        case 12: return CF<12>::fields(P);
+        default: return CF<14>::fields(P);
+    }
+}
+
+// Layout search for tile size M.
+bool search_layout_m(const ResidentReq &r, int M, ResGeom *out, size_t *bytes) {
     const int w = r.f64 ? 8 : 4;
     const int narr = r.s ? 3 : 2;
-    const int px = tiles_of(r.nx), py = tiles_of(r.ny);
+    const int px = tiles_of(r.nx, M), py = tiles_of(r.ny, M);
+    if (px > 16 || py > 16) return false;
     const size_t tabs =  // constant s: the factor tables
-        r.s ? 0 : (size_t)(CF<kRM>::fields(px) * px + CF<kRM>::fields(py) * py) * w;
+        r.s ? 0 : (size_t)(cf_fields(M, px) * px + cf_fields(M, py) * py) * w;
     // preference: two workgroups per CU where LDS allows it, then the fewest
     // bank conflicts, then the least LDS
     ResGeom best{};
@@ -405,16 +427,17 @@ bool search_layout(const ResidentReq &r, ResGeom *out, size_t *bytes) {
         ResGeom g{};
         g.nx = (int)r.nx;
         g.ny = (int)r.ny;
+        g.m = M;
         g.px = px;
         g.py = py;
         g.tp = tp;
         g.nsteps = r.nsteps;
-        const int rowlen = g.nx + (tp ? (g.nx - 1) / kRM + 1 : 0);
+        const int rowlen = g.nx + (tp ? (g.nx - 1) / M + 1 : 0);
         for (int ldx = rowlen; ldx < rowlen + 32; ++ldx) {
             for (int skw = 0; skw < 32; ++skw) {
                 g.ldx = ldx;
                 g.skw = skw;
-                g.region = (res_at(g, g.ny - 1, g.nx - 1) + 1 + 3) & ~3;
+                g.region = (res_at_h(g, g.ny - 1, g.nx - 1) + 1 + 3) & ~3;
                 const size_t b = (size_t)narr * g.region * w + tabs;
                 if (b > kLdsBytes) continue;
                 const int occ = (int)std::min<size_t>(2, kLdsBytes / b);
@@ -433,6 +456,19 @@ bool search_layout(const ResidentReq &r, ResGeom *out, size_t *bytes) {
     *out = best;
     *bytes = best_bytes;
     return true;
+}
+
+// Tile size: the least padded tile rows over both directions (ties: the
+// smaller tile), among those whose layout fits.
+bool search_layout(const ResidentReq &r, ResGeom *out, size_t *bytes) {
+    int order[4] = {0, 1, 2, 3};
+    auto padded = [&](int M) {
+        return (i64)tiles_of(r.nx, M) * M * r.ny + (i64)tiles_of(r.ny, M) * M * r.nx;
+    };
+    std::stable_sort(order, order + 4, [&](int a, int b) { return padded(kTileRows[a]) < padded(kTileRows[b]); });
+    for (int i : order)
+        if (search_layout_m(r, kTileRows[i], out, bytes)) return true;
+    return false;
 }
 
 // Layouts are searched once per (nx, ny, precision, s form) and kept.
@@ -456,9 +492,9 @@ bool plan_resident(const ResidentReq &r, ResGeom *out, size_t *bytes) {
     return true;
 }
 
-template <typename T, bool PS>
+template <typename T, bool PS, int M>
 hipError_t go(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_t s) {
-    auto kern = k_adi2d_resident<T, PS>;
+    auto kern = k_adi2d_resident<T, PS, M>;
     if (bytes > 64 * 1024) {
         static bool raised = false;  // one attribute call per instantiation
         if (!raised) {
@@ -473,6 +509,12 @@ hipError_t go(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_t 
     return hipGetLastError();
 }
 
+template <int M>
+hipError_t go_t(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_t s) {
+    if (r.f64) return r.s ? go<double, true, M>(r, g, bytes, s) : go<double, false, M>(r, g, bytes, s);
+    return r.s ? go<float, true, M>(r, g, bytes, s) : go<float, false, M>(r, g, bytes, s);
+}
+
 }  // namespace
 
 bool resident_fits(const ResidentReq &r) {
@@ -485,8 +527,12 @@ hipError_t launch_resident(const ResidentReq &r, hipStream_t s) {
     ResGeom g;
     size_t bytes;
     if (r.batch < 1 || r.batch >= ((i64)1 << 31) || !plan_resident(r, &g, &bytes)) return hipErrorInvalidValue;
-    if (r.f64) return r.s ? go<double, true>(r, g, bytes, s) : go<double, false>(r, g, bytes, s);
-    return r.s ? go<float, true>(r, g, bytes, s) : go<float, false>(r, g, bytes, s);
+    switch (g.m) {
+        case 8: return go_t<8>(r, g, bytes, s);
+        case 10: return go_t<10>(r, g, bytes, s);
+        case 12: return go_t<12>(r, g, bytes, s);
+        default: return go_t<14>(r, g, bytes, s);
+    }
 }
 
 }  // namespace trid

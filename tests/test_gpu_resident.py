@@ -44,9 +44,11 @@ def _run(trid, tu, s, s0, steps, stream=False):
     return names
 
 
-# (nx, ny): 1 to 16 tiles per line, padding tiles (48 -> 8 tiles, 80 -> 16),
-# ragged tails, a single point per line, non-square meshes
-SHAPES = [(32, 32), (64, 64), (48, 48), (80, 80), (128, 128), (100, 37), (13, 90), (5, 3), (1, 7), (128, 1)]
+# (nx, ny): 1 to 16 tiles per line; tiles of 8 (32, 64, 128), 10 (80), 12 (48,
+# 96) and 14 rows (112, and 100 x 37 with padding); ragged tails, a single
+# point per line, non-square meshes
+SHAPES = [(32, 32), (64, 64), (48, 48), (80, 80), (96, 96), (112, 112), (128, 128), (100, 37), (13, 90),
+          (60, 44), (5, 3), (1, 7), (128, 1)]
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
