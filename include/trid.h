@@ -253,7 +253,12 @@ int trid_adi_step_adjoint_kept(trid_handle_t h, trid_dtype_t dt, const void *u_t
 
 /* Load / save the tile-plan cache (JSON text: one entry per tuned key, each
  * with the gfx architecture it was tuned on).  Unknown keys are ignored on
- * load; a missing file on load is TRID_ERR_ARG. */
+ * load; a missing file on load is TRID_ERR_ARG.  With the environment variable
+ * TRID_PLAN_CACHE set to a path, trid_create loads that file when it exists and
+ * trid_destroy writes the handle's plans back to it.
+ *
+ * Testing aid: with TRID_FAIL_ALLOC set, every workspace allocation of the
+ * library fails with TRID_ERR_ALLOC before any HIP call. */
 int trid_plan_load(trid_handle_t h, const char *path);
 int trid_plan_save(trid_handle_t h, const char *path);
 

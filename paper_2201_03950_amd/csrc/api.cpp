@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -136,8 +137,14 @@ int handle_check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, 
 }
 int handle_run_lines(trid_handle_t h, const LineReq &r) { return run_lines(h, r); }
 
+// With TRID_FAIL_ALLOC set (to anything), every workspace allocation fails
+// with TRID_ERR_ALLOC before any HIP call: a host-forced failure for testing
+// the error path.
+bool alloc_failure_forced() { return getenv("TRID_FAIL_ALLOC") != nullptr; }
+
 // Grow the handle's workspace to at least `bytes` (invalidates captured graphs).
 int handle_workspace(trid_handle_t h, size_t bytes, void **ptr) {
+    if (alloc_failure_forced()) return fail(h, TRID_ERR_ALLOC, "workspace allocation failed (TRID_FAIL_ALLOC)");
     if (h->ws_bytes < bytes) {
         if (h->ws) {
             hipError_t e = hipStreamSynchronize(h->stream);
@@ -198,11 +205,21 @@ int trid_create(trid_handle_t *h) {
         return TRID_ERR_ALLOC;
     }
     *h = p;
+    // TRID_PLAN_CACHE names a plan file: loaded here when it exists, written
+    // back when the handle is destroyed
+    if (const char *path = getenv("TRID_PLAN_CACHE")) {
+        if (FILE *f = fopen(path, "r")) {
+            fclose(f);
+            trid_plan_load(p, path);
+        }
+    }
     return TRID_OK;
 }
 
 int trid_destroy(trid_handle_t h) {
     if (!h) return TRID_OK;
+    if (const char *path = getenv("TRID_PLAN_CACHE"))
+        if (!h->ext.tuned.empty()) trid_plan_save(h, path);
     if (h->ws || !h->graphs.empty() || h->capture_stream || h->ext.has_device_state()) {
         hipStreamSynchronize(h->stream);
         for (auto &kv : h->graphs) hipGraphExecDestroy(kv.second);

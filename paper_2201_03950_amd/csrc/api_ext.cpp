@@ -43,6 +43,8 @@ void ExtState::release() {
 }
 
 int handle_workspace2(trid_handle_t h, size_t bytes, void **ptr) {
+    if (alloc_failure_forced())
+        return handle_fail(h, TRID_ERR_ALLOC, "workspace allocation failed (TRID_FAIL_ALLOC)");
     ExtState &x = handle_ext(h);
     if (x.ws2_bytes < bytes) {
         if (x.ws2) {

@@ -142,6 +142,7 @@ int handle_check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, 
                       i64 *inner, i64 *n, i64 *outer);
 int handle_run_lines(trid_handle_t h, const LineReq &r);
 int handle_workspace(trid_handle_t h, size_t bytes, void **ptr);
+bool alloc_failure_forced();  // TRID_FAIL_ALLOC is set: workspace allocations fail
 int handle_workspace2(trid_handle_t h, size_t bytes, void **ptr);
 
 }  // namespace trid

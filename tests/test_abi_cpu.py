@@ -152,3 +152,27 @@ def test_refine_and_adjoint_argument_checks(lib, h):
     assert lib.trid_adi_step_adjoint_kept(h, 1, FAKE, FAKE, FAKE, FAKE, None, FAKE, FAKE, 3, _dims(8, 8, 8), 1) == 1
     assert lib.trid_plan_load(h, None) == 1
     assert lib.trid_plan_load(h, b"/nonexistent/plans.json") == 1
+
+
+def test_forced_allocation_failure(lib, h, monkeypatch):
+    """TRID_FAIL_ALLOC makes every workspace allocation fail before any HIP call."""
+    monkeypatch.setenv("TRID_FAIL_ALLOC", "1")
+    assert lib.trid_adi_step(h, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, 1, 0) == 2
+    assert b"TRID_FAIL_ALLOC" in lib.trid_last_error(h)
+    # contiguous lines beyond TRID_MAX_LINE need the chunked solve's workspace
+    assert lib.trid_gtsv_batched_s(h, 1, FAKE, FAKE, 1, _dims(9000), 0, 1) == 2
+
+
+def test_plan_cache_environment(lib, tmp_path, monkeypatch):
+    """TRID_PLAN_CACHE: a new handle loads the file; a handle with plans writes it back."""
+    cache = tmp_path / "plans.json"
+    cache.write_text('{\n "plans": {\n  "varlen/abc/0": {"M": 16, "NT": 512}\n }\n}\n')
+    monkeypatch.setenv("TRID_PLAN_CACHE", str(cache))
+    hp = ctypes.c_void_p()
+    assert lib.trid_create(ctypes.byref(hp)) == 0
+    out = tmp_path / "saved.json"
+    assert lib.trid_plan_save(hp, str(out).encode()) == 0
+    assert '"varlen/abc/0": {"M": 16, "NT": 512' in out.read_text()
+    cache.unlink()
+    assert lib.trid_destroy(hp) == 0
+    assert '"varlen/abc/0"' in cache.read_text()  # written back on destroy
