@@ -33,7 +33,8 @@ _lib = None
 
 def build(force=False):
     """Compile the oracle library with gcc (plain -O2, IEEE arithmetic, OpenMP over lines)."""
-    if force or not os.path.exists(_LIB):
+    stale = os.path.exists(_LIB) and os.path.getmtime(_LIB) < os.path.getmtime(_SRC)
+    if force or stale or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
         subprocess.check_call(cmd)
@@ -64,6 +65,7 @@ def _load():
             "orc_adi_step": ([P, P, D, I, LP, L, I], I),
             "orc_gtsv_adjoint": ([P, P, P, P, P, P, P, P, I, LP, I, L], I),
             "orc_adi_step_adjoint": ([P, P, P, P, I, LP, L], I),
+            "orc_hv_step": ([P, P, P, P, D, D, LP, L, I], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -203,6 +205,21 @@ def adi_step(u, s=None, s0=0.0, nsteps=1):
     ndim, dims, batch = _geom(x)
     _check(lib.orc_adi_step(_ptr(x), _ptr(sp) if sp is not None else None, float(s0), ndim, dims,
                             batch, int(nsteps)), "adi_step")
+    return x
+
+
+def hv_step(u, a, b, c, dt, theta, nsteps=1):
+    """``nsteps`` Hundsdorfer-Verwer steps of u_t = a u_xx + b u_yy + c u_xy on 2D
+    meshes (batch, ny, nx), zero ghosts: the synthetic stand-in for the call
+    structure of Alg. 4 (predictor stencils alternating with x and y solves)."""
+    lib = _load()
+    x = _f64(u).copy()
+    a, b, c = (_f64(np.broadcast_to(v, x.shape)) for v in (a, b, c))
+    ndim, dims, batch = _geom(x)
+    if ndim != 2:
+        raise ValueError("hv_step takes 2D meshes")
+    _check(lib.orc_hv_step(_ptr(x), _ptr(a), _ptr(b), _ptr(c), float(dt), float(theta), dims, batch,
+                           int(nsteps)), "hv_step")
     return x
 
 

@@ -327,3 +327,113 @@ def test_symmetric_constant_transposed_solve_equals_forward(orc):
     x = orc.gtsv(a, b, c, d, 1)
     lam, _, _, _ = orc.gtsv_adjoint(a, b, c, np.zeros_like(d), d, 1)
     assert np.max(np.abs(lam - x)) <= 1e-15
+
+
+# ------------------------------------------- Hundsdorfer-Verwer (SLV stand-in) --
+
+HV_THETA = 0.5 + math.sqrt(3.0) / 6.0
+
+
+def _hv_amplification(z1, z2, theta):
+    """One HV step on an eigenvector of both one-dimensional operators (z_k = dt lambda_k):
+    the scheme's stages applied to scalars."""
+    y0 = 1.0 + z1 + z2
+    y1 = (y0 - theta * z1) / (1.0 - theta * z1)
+    y2 = (y1 - theta * z2) / (1.0 - theta * z2)
+    w0 = y0 + 0.5 * (z1 + z2) * (y2 - 1.0)
+    w1 = (w0 - theta * z1 * y2) / (1.0 - theta * z1)
+    return (w1 - theta * z2 * y2) / (1.0 - theta * z2)
+
+
+@pytest.mark.parametrize("theta", [HV_THETA, 1.0])
+def test_hv_fourier_mode_amplification(orc, theta):
+    """c = 0, constant a, b: a product of sine modes is an eigenvector of a D_xx
+    (eigenvalue -a mu_p) and b D_yy, so n steps multiply it by R(z1, z2)^n."""
+    nx, ny, p, q, a, b, dt, steps = 23, 17, 3, 2, 0.7, 1.3, 0.4, 6
+    x = np.arange(1, nx + 1)
+    y = np.arange(1, ny + 1)
+    u0 = np.sin(np.pi * q * y / (ny + 1))[:, None] * np.sin(np.pi * p * x / (nx + 1))[None, :]
+    mu = lambda k, n: 4.0 * math.sin(math.pi * k / (2.0 * (n + 1))) ** 2
+    R = _hv_amplification(-dt * a * mu(p, nx), -dt * b * mu(q, ny), theta)
+    out = orc.hv_step(u0[None], a, b, 0.0, dt, theta, steps)
+    assert np.max(np.abs(out[0] - R ** steps * u0)) <= 1e-13
+
+
+def test_hv_matches_dense_operators(orc):
+    """Per-point a, b, c on tiny meshes: the scheme written with dense matrices
+    (the three difference operators assembled entry by entry) and dense solves."""
+    nx, ny, batch, dt, theta = 5, 4, 2, 0.3, HV_THETA
+    rng = np.random.default_rng(17)
+    u = rng.standard_normal((batch, ny, nx))
+    a = rng.uniform(0.2, 1.0, (batch, ny, nx))
+    b = rng.uniform(0.2, 1.0, (batch, ny, nx))
+    c = rng.uniform(-0.3, 0.3, (batch, ny, nx))
+    N = nx * ny
+    Dxx, Dyy, Dxy = np.zeros((N, N)), np.zeros((N, N)), np.zeros((N, N))
+    idx = lambda i, j: j * nx + i
+    for j in range(ny):
+        for i in range(nx):
+            r = idx(i, j)
+            Dxx[r, r] = Dyy[r, r] = -2.0
+            for di in (-1, 1):
+                if 0 <= i + di < nx:
+                    Dxx[r, idx(i + di, j)] = 1.0
+            for dj in (-1, 1):
+                if 0 <= j + dj < ny:
+                    Dyy[r, idx(i, j + dj)] = 1.0
+            for di in (-1, 1):
+                for dj in (-1, 1):
+                    if 0 <= i + di < nx and 0 <= j + dj < ny:
+                        Dxy[r, idx(i + di, j + dj)] = di * dj / 4.0
+    out = orc.hv_step(u, a, b, c, dt, theta, 2)
+    I = np.eye(N)
+    for m in range(batch):
+        A0, A1, A2 = (np.diag(v[m].ravel()) @ D for v, D in ((c, Dxy), (a, Dxx), (b, Dyy)))
+        F = A0 + A1 + A2
+        U = u[m].ravel()
+        for _ in range(2):
+            Y0 = U + dt * F @ U
+            Y1 = np.linalg.solve(I - theta * dt * A1, Y0 - theta * dt * A1 @ U)
+            Y2 = np.linalg.solve(I - theta * dt * A2, Y1 - theta * dt * A2 @ U)
+            W0 = Y0 + 0.5 * dt * (F @ Y2 - F @ U)
+            W1 = np.linalg.solve(I - theta * dt * A1, W0 - theta * dt * A1 @ Y2)
+            U = np.linalg.solve(I - theta * dt * A2, W1 - theta * dt * A2 @ Y2)
+        assert np.max(np.abs(out[m].ravel() - U)) <= 1e-13 * max(1.0, np.max(np.abs(U)))
+
+
+def test_hv_is_second_order_against_the_exact_flow(orc):
+    """Independent of the scheme's formulas: the semi-discrete system u' = F u
+    (F assembled densely, mixed term included) has the exact solution
+    expm(T F) u0; the HV scheme is second order in time, so halving dt divides
+    the error at T by about 4."""
+    nx, ny, T = 6, 5, 0.8
+    rng = np.random.default_rng(23)
+    u = rng.standard_normal((1, ny, nx))
+    a = rng.uniform(0.2, 0.6, (1, ny, nx))
+    b = rng.uniform(0.2, 0.6, (1, ny, nx))
+    c = rng.uniform(-0.2, 0.2, (1, ny, nx))
+    N = nx * ny
+    F = np.zeros((N, N))
+    for j in range(ny):
+        for i in range(nx):
+            r = j * nx + i
+            F[r, r] = -2.0 * (a[0, j, i] + b[0, j, i])
+            for di, dj, w in ((-1, 0, a), (1, 0, a), (0, -1, b), (0, 1, b)):
+                if 0 <= i + di < nx and 0 <= j + dj < ny:
+                    F[r, (j + dj) * nx + i + di] += w[0, j, i]
+            for di in (-1, 1):
+                for dj in (-1, 1):
+                    if 0 <= i + di < nx and 0 <= j + dj < ny:
+                        F[r, (j + dj) * nx + i + di] += c[0, j, i] * di * dj / 4.0
+    exact = scipy.linalg.expm(T * F) @ u.ravel()
+    errs = []
+    for steps in (8, 16, 32):
+        out = orc.hv_step(u, a, b, c, T / steps, HV_THETA, steps)
+        errs.append(np.max(np.abs(out.ravel() - exact)))
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 3.3 <= e1 / e2 <= 4.7, errs
+
+
+def test_hv_zero_step_is_identity(orc):
+    u = np.random.default_rng(3).standard_normal((2, 6, 7))
+    assert np.array_equal(orc.hv_step(u, 0.5, 0.5, 0.1, 0.0, HV_THETA, 3), u)
