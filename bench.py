@@ -424,6 +424,48 @@ def extra_small_batched(trid):
     return {"adi_small_batched": out}
 
 
+# Mesh words per point and HV step that the stand-in's kernels must move: the
+# four predictors read u, r, z and the coefficients they use and write r, z or
+# u (6 + 4 + 6 + 4 words); the four s-form solves read d and s and write x
+# (3 words each).
+HV_WORDS = {"hv_pred": 20, "solves": 12}
+
+
+def extra_hv(trid):
+    """The SLV-like Hundsdorfer-Verwer stand-in (Alg. 4's call structure) at the
+    SLV mesh sizes 40 x 20 and 100 x 50 with 30, 300 and 3000 meshes, 50 steps
+    per call, FP64 and FP32.  Bandwidth counts HV_WORDS per point and step."""
+    import math
+
+    import torch
+
+    from workloads import gen
+
+    theta = 0.5 + math.sqrt(3.0) / 6.0
+    out = {}
+    for dt, tag in ((torch.float64, "f64"), (torch.float32, "f32")):
+        w = 8 if dt == torch.float64 else 4
+        for nx, ny in ((40, 20), (100, 50)):
+            for batch in (30, 300, 3000):
+                steps = 50
+                u, a, b, c = (torch.from_numpy(v).to(dt).cuda() for v in gen.hv_slv((nx, ny), batch))
+                t = time_calls(lambda: trid.hv_step(u, a, b, c, 0.25, theta, steps), 2, warm=1)
+                trid.timing_enable(True)  # kernel times from a call of its own (events cost launch time)
+                trid.hv_step(u, a, b, c, 0.25, theta, steps)
+                kt = trid.timing_read()
+                trid.timing_enable(False)
+                pts = batch * nx * ny
+                words = HV_WORDS["hv_pred"] + HV_WORDS["solves"]
+                r = {"ms_per_step": round(t / steps * 1e3, 4),
+                     "mpoint_steps_per_s": round(pts * steps / t / 1e6, 1),
+                     "gbs": round(words * w * pts * steps / t / 1e9, 1),
+                     "kernel_ms_per_step": {k: round(ms / steps, 4) for k, (cnt, ms) in kt.items()}}
+                out["%s_%dx%d_x%d" % (tag, nx, ny, batch)] = r
+                del u, a, b, c
+        log("hv stand-in %s done" % tag)
+    return {"hv_slv": out}
+
+
 def extra_varlen(trid):
     """20,000 systems with lengths log-uniform in [32, 8192] in one persistent launch.
 
@@ -653,7 +695,7 @@ def cpu_baseline(budget_s=12.0, max_steps=60):
 # The other workloads, each a function of the loaded binding returning {name: result}.
 EXTRA_LEGS = {"adi2d_64x1024sq_xy": extra_2d, "varlen_20000": extra_varlen,
               "diff_adi3d_128_20steps": extra_gradient, "long_64x1M_f64": extra_long,
-              "adi_small_batched": extra_small_batched}
+              "adi_small_batched": extra_small_batched, "hv_slv": extra_hv}
 
 
 def main():

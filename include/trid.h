@@ -201,6 +201,31 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t p, const void *a, const void *
 int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, double s0, int ndim,
                   const int64_t *dims, int64_t batch, int nsteps, unsigned flags);
 
+/* `nsteps` Hundsdorfer-Verwer ADI steps of u_t = a u_xx + b u_yy + c u_xy in
+ * place on u: the synthetic stand-in for the call structure of the SLV
+ * application (Alg. 4, Section V): explicit predictor stencils alternating
+ * with line solves along x and y.  u, a, b, c are device arrays of dtype dt
+ * and shape (batch, ny, nx), x contiguous (dims = {nx, ny}); a, b, c are the
+ * per-point coefficients, with unit spacing and zero values outside the mesh.
+ * With F1 = a D_xx, F2 = b D_yy, F0 = c D_xy (D_xy the 4-point cross stencil
+ * over 4) and F = F0 + F1 + F2, one step of size tau is
+ *   Y0 = U + tau F(U)
+ *   (I - theta tau A1) Y1 = Y0 - theta tau F1(U)
+ *   (I - theta tau A2) Y2 = Y1 - theta tau F2(U)
+ *   W0 = Y0 + tau/2 (F(Y2) - F(U))
+ *   (I - theta tau A1) W1 = W0 - theta tau F1(Y2)
+ *   (I - theta tau A2) U  = W1 - theta tau F2(Y2)
+ * with A1 = a D_xx and A2 = b D_yy, so the implicit systems are the s form
+ * (-s, 1 + 2 s, -s) with s = theta tau a (x lines) or theta tau b (y lines).
+ * Each step is four predictor launches and four batched line solves; the
+ * four mesh-sized work arrays are owned by the handle.  tau >= 0 and
+ * theta > 0, both finite; nsteps >= 0 (0 is a no-op); lines up to
+ * TRID_MAX_LINE rows along each axis.
+ * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED, TRID_ERR_ALLOC, TRID_ERR_HIP. */
+int trid_hv_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *a, const void *b,
+                 const void *c, double tau, double theta, const int64_t *dims, int64_t batch,
+                 int nsteps);
+
 /* ------------------------------------------------------------- adjoints -- */
 
 /* Reverse mode of x = A^{-1} d along `axis` (arrays form).  x is the forward

@@ -22,6 +22,7 @@ from ._binding import (  # noqa: F401
     gtsv_s_adjoint,
     gtsv_s_refine,
     gtsv_varlen,
+    hv_step,
     load_library,
     plan_load,
     plan_save,

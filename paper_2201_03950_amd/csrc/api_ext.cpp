@@ -14,6 +14,7 @@
 #include "../../include/trid.h"
 #include "dispatch.hpp"
 #include "ext.hpp"
+#include "hv.hpp"
 #include "refine.hpp"
 #include "varlen.hpp"
 
@@ -527,6 +528,71 @@ int adi_reverse(trid_handle_t h, const AdiGeom &g, const void *u_t, const void *
 }  // namespace
 
 extern "C" {
+
+int trid_hv_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *a, const void *b, const void *c,
+                 double tau, double theta, const int64_t *dims, int64_t batch, int nsteps) {
+    if (!h) return TRID_ERR_ARG;
+    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!u || !a || !b || !c) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    if (nsteps < 0) return trid::handle_fail(h, TRID_ERR_ARG, "nsteps must be >= 0");
+    if (!(tau >= 0.0) || !(theta > 0.0) || tau > 1e300 || theta > 1e300)
+        return trid::handle_fail(h, TRID_ERR_ARG, "dt must be >= 0 and theta > 0, both finite");
+    int64_t inner, n, outer;
+    for (int ax = 0; ax < 2; ++ax) {
+        int rc = trid::handle_check_mesh(h, 2, dims, ax, batch, &inner, &n, &outer);
+        if (rc) return rc;
+    }
+    if (nsteps == 0) return TRID_OK;
+    const bool f64 = dt == TRID_F64;
+    const int64_t nx = dims[0], ny = dims[1], pts = nx * ny * batch;
+    const size_t slot = ((size_t)pts * (f64 ? 8 : 4) + 255) & ~(size_t)255;
+    void *ws = nullptr;
+    int rc = trid::handle_workspace2(h, 4 * slot, &ws);
+    if (rc) return rc;
+    char *wb = static_cast<char *>(ws);
+    trid::HvReq q;
+    q.f64 = f64;
+    q.u = u;
+    q.r = wb;
+    q.z = wb + slot;
+    q.sa = wb + 2 * slot;
+    q.sb = wb + 3 * slot;
+    q.a = a;
+    q.b = b;
+    q.c = c;
+    q.nx = nx;
+    q.ny = ny;
+    q.batch = batch;
+    q.dt = tau;
+    q.theta = theta;
+    trid::ExtState &xs = trid::handle_ext(h);
+    hipStream_t st = trid::handle_stream(h);
+    auto pred = [&](int which) {
+        hipError_t e = xs.timer.time("hv_pred", st, [&] { return trid::launch_hv_pred(q, which, st); });
+        return e == hipSuccess ? TRID_OK : trid::handle_hip_fail(h, e, "predictor launch");
+    };
+    // the implicit rows (-s, 1 + 2 s, -s): s = theta dt a along x, theta dt b along y
+    auto solve = [&](void *d, int axis) {
+        trid::LineReq r;
+        r.f64 = f64;
+        r.mode = trid::Mode::S;
+        r.out = trid::Out::Store;
+        r.s = axis == 0 ? q.sa : q.sb;
+        r.d = d;
+        r.x = d;
+        r.inner = axis == 0 ? 1 : nx;
+        r.n = axis == 0 ? nx : ny;
+        r.outer = axis == 0 ? ny * batch : batch;
+        return trid::handle_run_lines(h, r);
+    };
+    if ((rc = pred(4))) return rc;
+    for (int it = 0; it < nsteps; ++it) {
+        if ((rc = pred(0)) || (rc = solve(q.r, 0)) || (rc = pred(1)) || (rc = solve(q.r, 1)) ||
+            (rc = pred(2)) || (rc = solve(q.z, 0)) || (rc = pred(3)) || (rc = solve(u, 1)))
+            return rc;
+    }
+    return TRID_OK;
+}
 
 int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s, void *u_bar,
                           void *s_bar, int ndim, const int64_t *dims, int64_t batch) {

@@ -1,4 +1,4 @@
-"""Seeded input generators for the five synthetic workloads.
+"""Seeded input generators for the synthetic workloads.
 
 Layout convention for every mesh array: numpy C order with shape
 ``(batch, nz, ny, nx)`` in 3D, ``(batch, ny, nx)`` in 2D and ``(batch, nx)``
@@ -21,6 +21,10 @@ Workloads (sizes are parameters so the tests can run the same recipe small):
                        rounded to float32; right-hand side kept in float64.
 * ``diffusion3d``   -- kappa ~ lognormal(0, 0.5) per cell, u0 ~ U(0, 1), and a
                        second kappa* from its own seed for the target field.
+* ``hv_slv``        -- batched 2D meshes for the SLV-like mixed-derivative
+                       model: u0 ~ U(0, 1); a, b ~ U(0.1, 1); c = 2 rho sqrt(a b)
+                       with rho ~ U(-0.9, 0.9), so c^2 < 4ab at every point
+                       (the operator stays elliptic).
 
 No function here performs any step of the solver; draws happen in a fixed order
 so that a given seed always yields the same arrays.
@@ -42,11 +46,12 @@ __all__ = [
     "varlen_batch",
     "diffusion3d",
     "fourier_mode_3d",
+    "hv_slv",
     "SEEDS",
 ]
 
 # Seed of each named workload; the target field of the differentiable run has its own.
-SEEDS = {"lines": 0, "adi3d": 1, "adi2d": 2, "varlen": 3, "diffusion3d": 4, "diffusion3d_target": 104}
+SEEDS = {"lines": 0, "adi3d": 1, "adi2d": 2, "varlen": 3, "diffusion3d": 4, "diffusion3d_target": 104, "hv": 5}
 
 
 def mesh_shape(dims, batch):
@@ -139,6 +144,18 @@ def diffusion3d(dims=(128, 128, 128), batch=1, seed=SEEDS["diffusion3d"],
     u0 = rng.uniform(0.0, 1.0, shape)
     kstar = np.random.default_rng(target_seed).lognormal(0.0, 0.5, shape)
     return tuple(np.ascontiguousarray(v, dtype=dtype) for v in (kappa, u0, kstar))
+
+
+def hv_slv(dims=(100, 50), batch=300, seed=SEEDS["hv"], dtype=np.float64):
+    """(u0, a, b, c) for the SLV-like model; drawn u0, a, b, rho in that order."""
+    shape = mesh_shape(dims, batch)
+    rng = np.random.default_rng(seed)
+    u0 = rng.uniform(0.0, 1.0, shape)
+    a = rng.uniform(0.1, 1.0, shape)
+    b = rng.uniform(0.1, 1.0, shape)
+    rho = rng.uniform(-0.9, 0.9, shape)
+    c = 2.0 * rho * np.sqrt(a * b)
+    return tuple(np.ascontiguousarray(v, dtype=dtype) for v in (u0, a, b, c))
 
 
 def fourier_mode_3d(dims, modes):
