@@ -217,14 +217,20 @@ int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, doub
  *   (I - theta tau A2) U  = W1 - theta tau F2(Y2)
  * with A1 = a D_xx and A2 = b D_yy, so the implicit systems are the s form
  * (-s, 1 + 2 s, -s) with s = theta tau a (x lines) or theta tau b (y lines).
- * Each step is four predictor launches and four batched line solves; the
- * four mesh-sized work arrays are owned by the handle.  tau >= 0 and
+ * Meshes of at most 128 points per line whose three work arrays (u and two
+ * stage arrays) fit one workgroup's LDS run all nsteps as ONE launch, each
+ * mesh resident in LDS and every predictor fused into the line solve after
+ * it (the fused on-chip modules of the SLV design, Section V); a, b, c are
+ * read from memory as the phases need them.  Other meshes, or flags =
+ * TRID_ADI_STREAM, take per-step kernels: four predictor launches and four
+ * batched line solves per step, with four mesh-sized work arrays owned by
+ * the handle.  Both compute the same steps up to rounding.  tau >= 0 and
  * theta > 0, both finite; nsteps >= 0 (0 is a no-op); lines up to
- * TRID_MAX_LINE rows along each axis.
+ * TRID_MAX_LINE rows along each axis; flags is 0 or TRID_ADI_STREAM.
  * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED, TRID_ERR_ALLOC, TRID_ERR_HIP. */
 int trid_hv_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *a, const void *b,
                  const void *c, double tau, double theta, const int64_t *dims, int64_t batch,
-                 int nsteps);
+                 int nsteps, unsigned flags);
 
 /* ------------------------------------------------------------- adjoints -- */
 

@@ -49,7 +49,7 @@ SIGNATURES = {
     "trid_adi_step": ([_H, _I, _P, _P, _D, _I, _I64P, _I64, _I, ctypes.c_uint], _I),
     "trid_gtsv_batched_adjoint": ([_H, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_s_adjoint": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
-    "trid_hv_step": ([_H, _I, _P, _P, _P, _P, _D, _D, _I64P, _I64, _I], _I),
+    "trid_hv_step": ([_H, _I, _P, _P, _P, _P, _D, _D, _I64P, _I64, _I, ctypes.c_uint], _I),
     "trid_adi_step_adjoint": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I64], _I),
     "trid_adi_step_keep": ([_H, _I, _P, _P, _I, _I64P, _I64, _P, _P, _P], _I),
     "trid_adi_step_adjoint_kept": ([_H, _I, _P, _P, _P, _P, _P, _P, _P, _I, _I64P, _I64], _I),
@@ -268,9 +268,11 @@ def adi_step(u, s=None, s0=0.0, nsteps=1, graph=False, stream=False):
     return u
 
 
-def hv_step(u, a, b, c, dt, theta, nsteps=1):
+def hv_step(u, a, b, c, dt, theta, nsteps=1, stream=False):
     """``nsteps`` Hundsdorfer-Verwer ADI steps of u_t = a u_xx + b u_yy + c u_xy in place
-    on the 2D meshes u (batch, ny, nx); a, b, c per point, same shape and dtype."""
+    on the 2D meshes u (batch, ny, nx); a, b, c per point, same shape and dtype.
+
+    Small meshes run all steps in one LDS-resident launch unless ``stream``."""
     _dev(u, a, b, c)
     _same(u, a, b, c)
     h = handle()
@@ -279,7 +281,8 @@ def hv_step(u, a, b, c, dt, theta, nsteps=1):
     if nd != 2:
         raise ValueError("hv_step takes 2D meshes (batch, ny, nx)")
     _check(lib.trid_hv_step(h, _dtype_code(u), u.data_ptr(), a.data_ptr(), b.data_ptr(), c.data_ptr(),
-                            float(dt), float(theta), dims, batch, int(nsteps)), h)
+                            float(dt), float(theta), dims, batch, int(nsteps),
+                            TRID_ADI_STREAM if stream else 0), h)
     return u
 
 

@@ -16,6 +16,7 @@
 #include "ext.hpp"
 #include "hv.hpp"
 #include "refine.hpp"
+#include "resident.hpp"
 #include "varlen.hpp"
 
 namespace trid {
@@ -530,8 +531,9 @@ int adi_reverse(trid_handle_t h, const AdiGeom &g, const void *u_t, const void *
 extern "C" {
 
 int trid_hv_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *a, const void *b, const void *c,
-                 double tau, double theta, const int64_t *dims, int64_t batch, int nsteps) {
+                 double tau, double theta, const int64_t *dims, int64_t batch, int nsteps, unsigned flags) {
     if (!h) return TRID_ERR_ARG;
+    if (flags & ~(unsigned)TRID_ADI_STREAM) return trid::handle_fail(h, TRID_ERR_ARG, "unknown flag");
     if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
     if (!u || !a || !b || !c) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
     if (nsteps < 0) return trid::handle_fail(h, TRID_ERR_ARG, "nsteps must be >= 0");
@@ -545,6 +547,27 @@ int trid_hv_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *a, const
     if (nsteps == 0) return TRID_OK;
     const bool f64 = dt == TRID_F64;
     const int64_t nx = dims[0], ny = dims[1], pts = nx * ny * batch;
+    trid::ExtState &xs = trid::handle_ext(h);
+    hipStream_t st = trid::handle_stream(h);
+    if (!(flags & TRID_ADI_STREAM)) {  // all steps in one launch, each mesh resident in LDS
+        trid::ResidentReq rq;
+        rq.f64 = f64;
+        rq.u = u;
+        rq.nx = nx;
+        rq.ny = ny;
+        rq.batch = batch;
+        rq.nsteps = nsteps;
+        rq.hv = true;
+        rq.a = a;
+        rq.b = b;
+        rq.c = c;
+        rq.dt = tau;
+        rq.theta = theta;
+        if (trid::resident_fits(rq)) {
+            hipError_t e = xs.timer.time("hv_resident", st, [&] { return trid::launch_resident(rq, st); });
+            return e == hipSuccess ? TRID_OK : trid::handle_hip_fail(h, e, "resident HV launch");
+        }
+    }
     const size_t slot = ((size_t)pts * (f64 ? 8 : 4) + 255) & ~(size_t)255;
     void *ws = nullptr;
     int rc = trid::handle_workspace2(h, 4 * slot, &ws);
@@ -565,8 +588,6 @@ int trid_hv_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *a, const
     q.batch = batch;
     q.dt = tau;
     q.theta = theta;
-    trid::ExtState &xs = trid::handle_ext(h);
-    hipStream_t st = trid::handle_stream(h);
     auto pred = [&](int which) {
         hipError_t e = xs.timer.time("hv_pred", st, [&] { return trid::launch_hv_pred(q, which, st); });
         return e == hipSuccess ? TRID_OK : trid::handle_hip_fail(h, e, "predictor launch");

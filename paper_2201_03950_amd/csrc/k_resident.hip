@@ -18,6 +18,8 @@
 // lanes.
 // LDS holds u, d (and s when it varies per point) with a host-chosen row pitch
 // and per-tile skews that spread both phases' accesses over the banks.
+// The same layout, tiles and reduced solves serve k_hv_resident, the
+// Hundsdorfer-Verwer steps of the SLV stand-in (Alg. 4's call structure).
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -361,6 +363,168 @@ __global__ __launch_bounds__(max_threads(kRM)) void k_adi2d_resident(ResGeom g, 
     }
 }
 
+// The Hundsdorfer-Verwer steps of the SLV stand-in (u_t = a u_xx + b u_yy +
+// c u_xy, Alg. 4's call structure) with the mesh resident in LDS: U, R, Z
+// (three arrays, same layout as above); a, b, c are read from memory where a
+// phase needs them (read-only; they stay in the caches between steps).  Each
+// predictor is fused into the line solve that follows it:
+//   A (x lines): from U: Z = U + dt/2 F(U), R = X^-1 (U + dt F(U) - th dt F1(U))
+//   B (y lines): R = Y^-1 (R - th dt F2(U))                       (R = Y2)
+//   C (x lines): from R: Z = X^-1 (Z + dt/2 F(Y2) - th dt F1(Y2))  (Z = W1)
+//   D (y lines): U = Y^-1 (Z - th dt F2(Y2))
+// with X, Y the rows (-th dt a, 1 + 2 th dt a, -th dt a) and the same with b.
+// A thread reads the stencil neighbourhood of its tile and writes only its
+// own tile's points, so one barrier after each phase orders the phases.
+template <typename T>
+struct HvCoef {
+    const T *a, *b, *c;
+    T dt, theta;
+};
+
+template <typename T, int kRM, int STAGE>
+__device__ __forceinline__ void hv_x_phase(const ResGeom &g, const HvCoef<T> &cf, i64 mb, const T *src, T *R,
+                                           T *Z) {
+    const int nt = blockDim.x, t = threadIdx.x;
+    const int nx = g.nx, ny = g.ny, la = nt / g.px;
+    const T dt = cf.dt, tdt = cf.theta * cf.dt, hdt = T(0.5) * cf.dt;
+    for (int yb = 0; yb < ny; yb += la) {
+        const int y = yb + t / g.px, p = t % g.px, x0 = p * kRM;
+        const bool live = y < ny;
+        const int ya = live ? y : 0;
+        const int base = res_at<kRM>(g, ya, x0);
+        const int dn = res_at<kRM>(g, ya + 1, x0) - base, ds = base - res_at<kRM>(g, ya > 0 ? ya - 1 : 0, x0);
+        const bool hn = live && y + 1 < ny, hs = live && y > 0;
+        const bool hw = live && x0 > 0, he = live && x0 + kRM < nx;
+        // rows y-1, y, y+1 over x0-1 .. x0+M (zero outside the mesh); guarded
+        // reads fall back to the tile's own first point
+        T vs[kRM + 2], vc[kRM + 2], vn[kRM + 2];
+        vs[0] = load_if(src, base - ds - 1 - g.tp, hs && hw, base);
+        vc[0] = load_if(src, base - 1 - g.tp, hw, base);
+        vn[0] = load_if(src, base + dn - 1 - g.tp, hn && hw, base);
+#pragma unroll
+        for (int k = 0; k < kRM; ++k) {
+            const bool v = live && x0 + k < nx;
+            vs[k + 1] = load_if(src, base - ds + k, v && hs, base);
+            vc[k + 1] = load_if(src, base + k, v, base);
+            vn[k + 1] = load_if(src, base + dn + k, v && hn, base);
+        }
+        vs[kRM + 1] = load_if(src, base - ds + kRM + g.tp, hs && he, base);
+        vc[kRM + 1] = load_if(src, base + kRM + g.tp, he, base);
+        vn[kRM + 1] = load_if(src, base + dn + kRM + g.tp, hn && he, base);
+        const i64 e0 = mb + (i64)ya * nx + x0;
+        T rd[kRM], sv[kRM];
+#pragma unroll
+        for (int k = 0; k < kRM; ++k) {
+            const bool v = live && x0 + k < nx;
+            const T ak = load_if(cf.a, e0 + k, v, mb), bk = load_if(cf.b, e0 + k, v, mb);
+            const T ck = load_if(cf.c, e0 + k, v, mb);
+            const T f1 = ak * (vc[k] - T(2) * vc[k + 1] + vc[k + 2]);
+            const T f = ck * ((vn[k + 2] - vs[k + 2] - vn[k] + vs[k]) * T(0.25)) + f1 +
+                        bk * (vs[k + 1] - T(2) * vc[k + 1] + vn[k + 1]);
+            sv[k] = tdt * ak;
+            if constexpr (STAGE == 0) {
+                if (v) Z[base + k] = vc[k + 1] + hdt * f;
+                rd[k] = v ? vc[k + 1] + dt * f - tdt * f1 : T(0);
+            } else {
+                rd[k] = v ? Z[base + k] + hdt * f - tdt * f1 : T(0);
+            }
+        }
+        TileState<T, kRM> ts;
+        tile_eliminate_fn<T, kRM>(SRows<T>{sv, x0, live ? nx : 0}, rd, ts);
+        T f, lv, xs[kRM];
+        dpp_reduced<T, kRM>(ts, g.px, p, f, lv);
+        tile_backsub<T, kRM>(ts, f, lv, xs);
+        T *dst = STAGE == 0 ? R : Z;
+#pragma unroll
+        for (int k = 0; k < kRM; ++k)
+            if (live && x0 + k < nx) dst[base + k] = xs[k];
+    }
+}
+
+template <typename T, int kRM, int STAGE>
+__device__ __forceinline__ void hv_y_phase(const ResGeom &g, const HvCoef<T> &cf, i64 mb, const T *src,
+                                           const T *own, T *dst) {
+    const int nt = blockDim.x, t = threadIdx.x;
+    const int nx = g.nx, ny = g.ny, lb = nt / g.py;
+    const T tdt = cf.theta * cf.dt;
+    for (int xb = 0; xb < nx; xb += lb) {
+        const int x = xb + t / g.py, q = t % g.py, y0 = q * kRM;
+        const bool live = x < nx;
+        const int xa = live ? x : 0;
+        T col[kRM + 2], rd[kRM], sv[kRM];
+        int off[kRM];
+        {
+            const bool v = live && y0 > 0;
+            const int o = res_at<kRM>(g, v ? y0 - 1 : 0, xa);
+            col[0] = load_if(src, o, v, o);
+        }
+#pragma unroll
+        for (int k = 0; k < kRM; ++k) {
+            const int y = y0 + k;
+            const bool v = live && y < ny;
+            off[k] = res_at<kRM>(g, v ? y : 0, xa);
+            col[k + 1] = load_if(src, off[k], v, off[k]);
+        }
+        {
+            const bool v = live && y0 + kRM < ny;
+            const int o = res_at<kRM>(g, v ? y0 + kRM : 0, xa);
+            col[kRM + 1] = load_if(src, o, v, o);
+        }
+#pragma unroll
+        for (int k = 0; k < kRM; ++k) {
+            const int y = y0 + k;
+            const bool v = live && y < ny;
+            const T bk = load_if(cf.b, mb + (i64)y * nx + xa, v, mb);
+            const T ok = load_if(own, off[k], v, off[k]);
+            sv[k] = tdt * bk;
+            rd[k] = v ? ok - tdt * bk * (col[k] - T(2) * col[k + 1] + col[k + 2]) : T(0);
+        }
+        TileState<T, kRM> ts;
+        tile_eliminate_fn<T, kRM>(SRows<T>{sv, y0, live ? ny : 0}, rd, ts);
+        T f, lv, xs[kRM];
+        dpp_reduced<T, kRM>(ts, g.py, q, f, lv);
+        tile_backsub<T, kRM>(ts, f, lv, xs);
+#pragma unroll
+        for (int k = 0; k < kRM; ++k)
+            if (live && y0 + k < ny) dst[off[k]] = xs[k];
+    }
+}
+
+// 512 threads at most for every tile size: a tile's three stencil rows and
+// coefficients need up to 256 VGPRs (FP64, 14-row tiles).
+constexpr int kHvMaxThreads = 512;
+
+template <typename T, int kRM>
+__global__ __launch_bounds__(kHvMaxThreads) void k_hv_resident(ResGeom g, HvCoef<T> cf, T *__restrict__ u_all) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *U = reinterpret_cast<T *>(smem_raw);
+    T *R = U + g.region;
+    T *Z = R + g.region;
+    const int nt = blockDim.x, t = threadIdx.x;
+    const int nx = g.nx, npts = nx * g.ny;
+    const i64 mb = (i64)blockIdx.x * npts;
+    T *um = u_all + mb;
+    for (int e = t; e < npts; e += nt) {
+        const int y = e / nx, x = e - y * nx;
+        U[res_at<kRM>(g, y, x)] = um[e];
+    }
+    __syncthreads();
+    for (int it = 0; it < g.nsteps; ++it) {
+        hv_x_phase<T, kRM, 0>(g, cf, mb, U, R, Z);
+        __syncthreads();
+        hv_y_phase<T, kRM, 0>(g, cf, mb, U, R, R);
+        __syncthreads();
+        hv_x_phase<T, kRM, 1>(g, cf, mb, R, R, Z);
+        __syncthreads();
+        hv_y_phase<T, kRM, 1>(g, cf, mb, R, Z, U);
+        __syncthreads();
+    }
+    for (int e = t; e < npts; e += nt) {
+        const int y = e / nx, x = e - y * nx;
+        um[e] = U[res_at<kRM>(g, y, x)];
+    }
+}
+
 int pow2_ceil(int v) {
     int p = 1;
     while (p < v) p *= 2;
@@ -372,9 +536,9 @@ int tiles_of(i64 n, int M) { return pow2_ceil((int)((n + M - 1) / M)); }
 // Threads per workgroup: one per tile of a pass over the lines; 1024 (8-row
 // tiles only) when a direction has at least 2048 tiles (measured: 128^2 gains,
 // 96^2 and 64^2 do not).
-int threads_of(const ResGeom &g) {
+int threads_of(const ResGeom &g, bool hv = false) {
     const int need = std::max(g.ny * g.px, g.nx * g.py);
-    const int cap = need >= 2048 ? max_threads(g.m) : 512;
+    const int cap = (need >= 2048 && !hv) ? max_threads(g.m) : 512;
     return std::max(64, std::min(cap, pow2_ceil(need)));
 }
 
@@ -413,11 +577,11 @@ int cf_fields(int M, int P) {
 // Layout search for tile size M.
 bool search_layout_m(const ResidentReq &r, int M, ResGeom *out, size_t *bytes) {
     const int w = r.f64 ? 8 : 4;
-    const int narr = r.s ? 3 : 2;
+    const int narr = (r.s || r.hv) ? 3 : 2;  // u, d (, s); HV: u, r, z
     const int px = tiles_of(r.nx, M), py = tiles_of(r.ny, M);
     if (px > 16 || py > 16) return false;
     const size_t tabs =  // constant s: the factor tables
-        r.s ? 0 : (size_t)(cf_fields(M, px) * px + cf_fields(M, py) * py) * w;
+        (r.s || r.hv) ? 0 : (size_t)(cf_fields(M, px) * px + cf_fields(M, py) * py) * w;
     // preference: two workgroups per CU where LDS allows it, then the fewest
     // bank conflicts, then the least LDS
     ResGeom best{};
@@ -474,12 +638,12 @@ bool search_layout(const ResidentReq &r, ResGeom *out, size_t *bytes) {
     return false;
 }
 
-// Layouts are searched once per (nx, ny, precision, s form) and kept.
+// Layouts are searched once per (nx, ny, precision, s form, HV or ADI) and kept.
 bool plan_resident(const ResidentReq &r, ResGeom *out, size_t *bytes) {
     if (r.nx < 1 || r.ny < 1 || r.nx > kMaxLine || r.ny > kMaxLine) return false;
     static std::mutex mu;
-    static std::map<std::tuple<int, int, bool, bool>, std::pair<ResGeom, size_t>> cache;
-    const auto key = std::make_tuple((int)r.nx, (int)r.ny, r.f64, r.s != nullptr);
+    static std::map<std::tuple<int, int, bool, bool, bool>, std::pair<ResGeom, size_t>> cache;
+    const auto key = std::make_tuple((int)r.nx, (int)r.ny, r.f64, r.s != nullptr, r.hv);
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(key);
     if (it == cache.end()) {
@@ -512,8 +676,27 @@ hipError_t go(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_t 
     return hipGetLastError();
 }
 
+template <typename T, int M>
+hipError_t go_hv(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_t s) {
+    auto kern = k_hv_resident<T, M>;
+    if (bytes > 64 * 1024) {
+        static bool raised = false;
+        if (!raised) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)kLdsBytes);
+            if (e != hipSuccess) return e;
+            raised = true;
+        }
+    }
+    HvCoef<T> cf{static_cast<const T *>(r.a), static_cast<const T *>(r.b), static_cast<const T *>(r.c), (T)r.dt,
+                 (T)r.theta};
+    launch(kern, dim3((unsigned)r.batch), dim3(threads_of(g, true)), bytes, s, g, cf, static_cast<T *>(r.u));
+    return hipGetLastError();
+}
+
 template <int M>
 hipError_t go_t(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_t s) {
+    if (r.hv) return r.f64 ? go_hv<double, M>(r, g, bytes, s) : go_hv<float, M>(r, g, bytes, s);
     if (r.f64) return r.s ? go<double, true, M>(r, g, bytes, s) : go<double, false, M>(r, g, bytes, s);
     return r.s ? go<float, true, M>(r, g, bytes, s) : go<float, false, M>(r, g, bytes, s);
 }

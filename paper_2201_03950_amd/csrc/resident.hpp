@@ -7,7 +7,9 @@ namespace trid {
 
 // `nsteps` 2D ADI steps of `batch` meshes of nx * ny points, each mesh held in
 // one workgroup's LDS for the whole time loop (u read from HBM once, written
-// once).  s per point (s != NULL) or the constant s0.
+// once).  s per point (s != NULL) or the constant s0.  With hv set, the steps
+// are instead Hundsdorfer-Verwer steps of u_t = a u_xx + b u_yy + c u_xy
+// (per-point a, b, c, step dt, parameter theta); s and s0 are then unused.
 struct ResidentReq {
     bool f64 = true;
     void *u = nullptr;
@@ -15,6 +17,9 @@ struct ResidentReq {
     double s0 = 0;
     i64 nx = 1, ny = 1, batch = 1;
     int nsteps = 1;
+    bool hv = false;
+    const void *a = nullptr, *b = nullptr, *c = nullptr;
+    double dt = 0, theta = 0;
 };
 
 // Whether the request fits the resident kernel (lines of at most 128 points,
