@@ -475,6 +475,110 @@ def extra_hv(trid):
     return {"hv_slv": out}
 
 
+def extra_perf_model(trid):
+    """Validation of the performance model on configurations outside its
+    calibration sweep: line lengths that are not powers of two (96 .. 3072),
+    both forms, x/y/z lines, FP64 and FP32, 2^20 and 2^23 rows per call, the
+    library's own tile plans; and three uneven-batch length mixes that were not
+    fitted, every plan timed.  Accuracy = 1 - |predicted - measured| / measured
+    (the paper's measure for its model), and for the autotuner the measured time
+    of the best of the model's top 3 plans over the best plan's."""
+    import numpy as np
+    import torch
+
+    from workloads import gen
+
+    errs, worst = [], []
+    for dt in (torch.float64, torch.float32):
+        for form in (trid.TRID_FORM_S, trid.TRID_FORM_ARRAYS):
+            for axis in (0, 1, 2):
+                for n in (96, 192, 384, 768, 1536, 3072):
+                    for size in (1 << 20, 1 << 23):
+                        if axis == 0:
+                            dims = [n]
+                        elif axis == 1:
+                            dims = [256, n]
+                        else:
+                            dims = [64, 64, n]
+                        batch = size // int(np.prod(dims))
+                        if batch < 1:
+                            continue
+                        shape = [batch] + list(reversed(dims))
+                        d = torch.randn(shape, dtype=dt, device="cuda")
+                        if form == trid.TRID_FORM_S:
+                            s = 0.1 + 0.2 * torch.rand(shape, dtype=dt, device="cuda")
+                            call = lambda: trid.gtsv_s(s, d, axis)  # noqa: E731
+                        else:
+                            a = torch.rand(shape, dtype=dt, device="cuda") - 0.5
+                            c = torch.rand(shape, dtype=dt, device="cuda") - 0.5
+                            b = a.abs() + c.abs() + 1.0
+                            call = lambda: trid.gtsv(a, b, c, d, axis)  # noqa: E731
+                        pred, _ = trid.model_gtsv(dt, form, dims, axis, batch)
+                        call()
+                        sync()
+                        trid.timing_enable(True)
+                        for _ in range(5):
+                            call()
+                        (k, ms), = trid.timing_read().values()
+                        trid.timing_enable(False)
+                        meas = ms / k * 1e3
+                        e = abs(pred - meas) / meas
+                        errs.append(e)
+                        worst.append((e, "%s form%d axis%d n%d rows%d pred %.1f meas %.1f" % (
+                            str(dt)[6:], form, axis, n, size, pred, meas)))
+                        del d
+        torch.cuda.empty_cache()
+    errs = np.array(errs)
+    worst.sort(reverse=True)
+    res = {"lines": {"configs": int(len(errs)), "mean_accuracy": round(1 - float(errs.mean()), 3),
+                     "median_accuracy": round(1 - float(np.median(errs)), 3),
+                     "within_15pct": round(float((errs <= 0.15).mean()), 3),
+                     "within_25pct": round(float((errs <= 0.25).mean()), 3),
+                     "worst": [w for _, w in worst[:5]]}}
+    log("model validation: line solves done")
+    # uneven batches outside the fit: every plan timed (TRID_AUTOTUNE_TOP=0)
+    os.environ["TRID_AUTOTUNE"] = "1"
+    os.environ["TRID_AUTOTUNE_TOP"] = "0"
+    rng = np.random.default_rng(77)
+    rng.integers(32, 513, 100000)  # the calibration mixes' draws come first in this stream
+    mixes = {"uni_2048_8192_x2000": rng.integers(2048, 8193, 2000),
+             "loguni_32_8192_x500": gen.varlen_lengths(500, 32, 8192, seed=9)[0],
+             "loguni_16_2048_x50000": None}
+    rng.random(20000)
+    mixes["loguni_16_2048_x50000"] = np.clip(np.rint(np.exp(rng.uniform(np.log(16), np.log(2048), 50000))), 16,
+                                             2048)
+    verrs, prune = [], {}
+    for name, lens in mixes.items():
+        lens = np.asarray(lens, dtype=np.int64)
+        off = np.zeros(len(lens) + 1, dtype=np.int64)
+        np.cumsum(lens, out=off[1:])
+        rows = int(off[-1])
+        for prec in (0, 1, 2):
+            cd = torch.float64 if prec == 0 else torch.float32
+            a = torch.rand(rows, dtype=cd, device="cuda") - 0.5
+            c = torch.rand(rows, dtype=cd, device="cuda") - 0.5
+            b = a.abs() + c.abs() + 1.0
+            d = torch.randn(rows, dtype=torch.float32 if prec == 1 else torch.float64, device="cuda")
+            x = torch.empty_like(d)
+            trid.gtsv_varlen(prec, a, b, c, d, x, off)
+            sync()
+            rep = trid.autotune_report()
+            for q in rep:
+                verrs.append(abs(q["pred_us"] - q["meas_us"]) / q["meas_us"])
+            best = min(q["meas_us"] for q in rep)
+            prune["%s_prec%d" % (name, prec)] = round(min(q["meas_us"] for q in rep[:3]) / best, 3)
+            del a, b, c, d, x
+            torch.cuda.empty_cache()
+    os.environ.pop("TRID_AUTOTUNE_TOP")
+    os.environ.pop("TRID_AUTOTUNE")
+    verrs = np.array(verrs)
+    res["varlen"] = {"plans": int(len(verrs)), "mean_accuracy": round(1 - float(verrs.mean()), 3),
+                     "within_25pct": round(float((verrs <= 0.25).mean()), 3),
+                     "top3_best_over_best": prune}
+    log("model validation: uneven batches done")
+    return {"perf_model": res}
+
+
 def extra_varlen(trid):
     """20,000 systems with lengths log-uniform in [32, 8192] in one persistent launch.
 
@@ -704,7 +808,7 @@ def cpu_baseline(budget_s=12.0, max_steps=60):
 # The other workloads, each a function of the loaded binding returning {name: result}.
 EXTRA_LEGS = {"adi2d_64x1024sq_xy": extra_2d, "varlen_20000": extra_varlen,
               "diff_adi3d_128_20steps": extra_gradient, "long_64x1M_f64": extra_long,
-              "adi_small_batched": extra_small_batched, "hv_slv": extra_hv}
+              "adi_small_batched": extra_small_batched, "hv_slv": extra_hv, "perf_model": extra_perf_model}
 
 
 def main():

@@ -280,6 +280,38 @@ int trid_adi_step_adjoint_kept(trid_handle_t h, trid_dtype_t dt, const void *u_t
                                const void *w1, const void *w2, const void *w3, void *u_bar,
                                void *s_bar, int ndim, const int64_t *dims, int64_t batch);
 
+/* ----------------------------------------------------- performance model -- */
+
+#define TRID_FORM_ARRAYS 0 /* rows from per-point a, b, c (trid_gtsv_batched) */
+#define TRID_FORM_S 1      /* rows (-s, 1 + 2 s, -s) (trid_gtsv_batched_s) */
+
+/* Predicted kernel duration, in microseconds, of the batched solve that
+ * trid_gtsv_batched (form TRID_FORM_ARRAYS) or trid_gtsv_batched_s
+ * (TRID_FORM_S) would launch for this geometry, with the tile plan it would
+ * choose (honouring trid_set_tile).  The model is the GPU counterpart of the
+ * paper's analytic latency model (Section III's per-call clock-cycle counts,
+ * applied to the applications in Section IV, which reports its predictions
+ * within 15% of measured runtimes): a fixed
+ * launch cost plus the larger of (bytes moved / streaming bandwidth of the
+ * access pattern) and (workgroup rounds x one workgroup's memory round trips,
+ * tile sweep and reduced-solve levels).  If json is not NULL, up to len bytes
+ * of a JSON object describing the plan and the model's terms are written.
+ * Host computation only (no HIP call, no GPU needed).  Lines longer than
+ * TRID_MAX_LINE are TRID_ERR_UNSUPPORTED.
+ * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED. */
+int trid_model_gtsv(trid_handle_t h, trid_dtype_t dt, int form, int ndim, const int64_t *dims,
+                    int axis, int64_t batch, double *us, char *json, size_t len);
+
+/* The most recent autotuning run of trid_gtsv_varlen (TRID_AUTOTUNE=1) as a
+ * JSON array, best predicted first: per plan its tile rows M, tiles per work
+ * item NT, reduced solve ("pcr" / "thomas"), split flag, the persistent
+ * workgroups of its launch (blocks; blocks_small for the short systems of a
+ * split plan), the model's predicted time pred_us and the measured time
+ * meas_us (-1 for plans the tuner did not time).  With TRID_AUTOTUNE_TOP=k (default 3) the tuner times only the k
+ * plans the model ranks best; k = 0 times every plan.  An empty array if no
+ * tuning has run.  Errors: TRID_ERR_ARG (NULL buffer or too small). */
+int trid_autotune_report(trid_handle_t h, char *buf, size_t len);
+
 /* ------------------------------------------------------------ plan cache -- */
 
 /* Load / save the tile-plan cache (JSON text: one entry per tuned key, each

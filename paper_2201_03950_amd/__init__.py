@@ -22,6 +22,10 @@ from ._binding import (  # noqa: F401
     gtsv_s_adjoint,
     gtsv_s_refine,
     gtsv_varlen,
+    model_gtsv,
+    autotune_report,
+    TRID_FORM_ARRAYS,
+    TRID_FORM_S,
     hv_step,
     load_library,
     plan_load,

@@ -49,6 +49,9 @@ SIGNATURES = {
     "trid_adi_step": ([_H, _I, _P, _P, _D, _I, _I64P, _I64, _I, ctypes.c_uint], _I),
     "trid_gtsv_batched_adjoint": ([_H, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_s_adjoint": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
+    "trid_model_gtsv": ([_H, _I, _I, _I, _I64P, _I, _I64, ctypes.POINTER(ctypes.c_double), ctypes.c_char_p,
+                         ctypes.c_size_t], _I),
+    "trid_autotune_report": ([_H, ctypes.c_char_p, ctypes.c_size_t], _I),
     "trid_hv_step": ([_H, _I, _P, _P, _P, _P, _D, _D, _I64P, _I64, _I, ctypes.c_uint], _I),
     "trid_adi_step_adjoint": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I64], _I),
     "trid_adi_step_keep": ([_H, _I, _P, _P, _I, _I64P, _I64, _P, _P, _P], _I),
@@ -169,6 +172,40 @@ def timing_read():
     buf = ctypes.create_string_buffer(1 << 16)
     _check(load_library().trid_timing_read(h, buf, len(buf)), h)
     return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
+
+
+TRID_FORM_ARRAYS = 0
+TRID_FORM_S = 1
+
+
+def model_gtsv(dtype, form, dims, axis, batch=1):
+    """Predicted kernel microseconds and plan of the batched solve ``gtsv`` (form
+    TRID_FORM_ARRAYS) or ``gtsv_s`` (TRID_FORM_S) would launch on meshes of
+    ``dims`` = [nx, (ny, (nz))]; host computation only."""
+    import json
+
+    import torch
+
+    h = handle()
+    lib = load_library()
+    code = {torch.float64: TRID_F64, torch.float32: TRID_F32}[dtype]
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    us = ctypes.c_double()
+    buf = ctypes.create_string_buffer(1024)
+    _check(lib.trid_model_gtsv(h, code, int(form), len(dims), d, int(axis), int(batch), ctypes.byref(us), buf,
+                               len(buf)), h)
+    return us.value, json.loads(buf.value.decode())
+
+
+def autotune_report():
+    """The most recent uneven-batch autotuning run: per plan the model's
+    prediction and the measured time (-1 where the plan was not timed)."""
+    import json
+
+    h = handle()
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load_library().trid_autotune_report(h, buf, len(buf)), h)
+    return json.loads(buf.value.decode())
 
 
 def gtsv(a, b, c, d, axis):

@@ -15,6 +15,7 @@
 #include "dispatch.hpp"
 #include "ext.hpp"
 #include "hv.hpp"
+#include "perf_model.hpp"
 #include "refine.hpp"
 #include "resident.hpp"
 #include "varlen.hpp"
@@ -249,6 +250,31 @@ bool autotune_requested() {
     return v && v[0] == '1';
 }
 
+// Plans the autotuner times: the best TRID_AUTOTUNE_TOP by the model (default
+// 3; 0 times every plan).
+size_t autotune_top() {
+    const char *v = std::getenv("TRID_AUTOTUNE_TOP");
+    if (!v || !*v) return 3;
+    const long n = std::strtol(v, nullptr, 10);
+    return n <= 0 ? (size_t)-1 : (size_t)n;
+}
+
+// Predicted time of an uneven-batch plan: one launch, or for a split plan the
+// launch of the long systems with v followed by the short ones with `small`
+// (the partition of varlen_build).
+double predict_varlen_plan(const int64_t *off, int64_t nsys, int prec, const trid::VarlenVariant &v, bool split,
+                           const trid::VarlenVariant &small) {
+    std::vector<int> all(nsys), lng, shr;
+    for (int64_t k = 0; k < nsys; ++k) all[k] = (int)k;
+    if (!split) return trid::model_varlen(off, all, prec, v, trid::varlen_blocks(prec, v)).us;
+    const int64_t cap = (int64_t)small.M * small.NT;
+    for (int k : all) (off[k + 1] - off[k] > cap ? lng : shr).push_back(k);
+    double us = 0;
+    if (!lng.empty()) us += trid::model_varlen(off, lng, prec, v, trid::varlen_blocks(prec, v)).us;
+    if (!shr.empty()) us += trid::model_varlen(off, shr, prec, small, trid::varlen_blocks(prec, small)).us;
+    return us;
+}
+
 // Time one schedule: one warm-up and three timed launches on stream st.
 hipError_t time_schedule(const trid::VarlenSchedule &sc, const void *a, const void *b, const void *c,
                          const void *d, void *x, hipStream_t st, float *us) {
@@ -320,7 +346,29 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
         trid::VarlenSchedule *best = nullptr;
         if (tune) {
             bool best_split = false;
-            for (const auto &pl : plans) {
+            // rank the plans by the model, time the best few
+            std::vector<double> pred(plans.size());
+            std::vector<size_t> rank(plans.size());
+            for (size_t i = 0; i < plans.size(); ++i) {
+                pred[i] = predict_varlen_plan(off, nsys, p, plans[i].v, plans[i].split, small);
+                rank[i] = i;
+            }
+            std::stable_sort(rank.begin(), rank.end(), [&](size_t x, size_t y) { return pred[x] < pred[y]; });
+            const size_t ntime = std::min(plans.size(), autotune_top());
+            xs.last_tune.clear();
+            for (size_t i : rank) {
+                trid::TuneRecord tr;
+                tr.M = plans[i].v.M;
+                tr.NT = plans[i].v.NT;
+                tr.thomas = plans[i].v.thomas;
+                tr.split = plans[i].split ? 1 : 0;
+                tr.blocks = trid::varlen_blocks(p, plans[i].v);
+                tr.blocks_small = plans[i].split ? trid::varlen_blocks(p, small) : 0;
+                tr.pred_us = pred[i];
+                xs.last_tune.push_back(tr);
+            }
+            for (size_t ri = 0; ri < ntime; ++ri) {
+                const auto &pl = plans[rank[ri]];
                 auto *sc = new trid::VarlenSchedule();
                 hipError_t e = trid::varlen_build(off, nsys, p, pl.v, sc, pl.split ? &small : nullptr);
                 float us = 0.f;
@@ -335,6 +383,7 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
                     return trid::handle_hip_fail(h, e, "uneven batch: autotune");
                 }
                 sc->tuned_us = us;
+                xs.last_tune[ri].meas_us = us;
                 if (!best || us < best->tuned_us) {
                     if (best) {
                         trid::varlen_free(best);
@@ -663,6 +712,57 @@ int trid_adi_step_adjoint_kept(trid_handle_t h, trid_dtype_t dt, const void *u_t
     if (rc) return rc;
     void *W[5] = {nullptr, const_cast<void *>(w1), const_cast<void *>(w2), const_cast<void *>(w3), ws};
     return adi_reverse(h, g, u_t, s, W, u_bar, s_bar);
+}
+
+int trid_model_gtsv(trid_handle_t h, trid_dtype_t dt, int form, int ndim, const int64_t *dims, int axis,
+                    int64_t batch, double *us, char *json, size_t len) {
+    if (!h) return TRID_ERR_ARG;
+    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
+    if (form != TRID_FORM_ARRAYS && form != TRID_FORM_S) return trid::handle_fail(h, TRID_ERR_ARG, "bad form");
+    if (!us) return trid::handle_fail(h, TRID_ERR_ARG, "us is NULL");
+    trid::LineReq r;
+    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    if (rc) return rc;
+    r.f64 = dt == TRID_F64;
+    r.mode = form == TRID_FORM_S ? trid::Mode::S : trid::Mode::Arrays;
+    r.out = trid::Out::Store;
+    trid::handle_ext(h).apply_overrides(&r);
+    trid::LinePlan pl;
+    std::string msg;
+    if (!trid::plan_lines(r, &pl, &msg)) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
+    const trid::ModelTerms t = trid::model_lines(r, pl);
+    *us = t.us;
+    if (json && len) {
+        snprintf(json, len,
+                 "{\"kernel\": \"%s\", \"M\": %d, \"L\": %d, \"P\": %d, \"threads\": %d, \"nblocks\": %lld, "
+                 "\"shmem\": %zu, \"bytes\": %.0f, \"t_bytes_us\": %.3f, \"t_lat_us\": %.3f, \"rounds\": %.0f, "
+                 "\"per_cu\": %d, \"us\": %.3f}",
+                 pl.staged ? "staged" : "strided", pl.M, pl.L, pl.P, pl.threads(), (long long)pl.nblocks, pl.shmem,
+                 t.bytes, t.t_bytes, t.t_lat, t.rounds, t.per_cu, t.us);
+    }
+    return TRID_OK;
+}
+
+int trid_autotune_report(trid_handle_t h, char *buf, size_t len) {
+    if (!h) return TRID_ERR_ARG;
+    if (!buf || len < 3) return trid::handle_fail(h, TRID_ERR_ARG, "buffer too small");
+    const auto &rec = trid::handle_ext(h).last_tune;
+    std::ostringstream o;
+    o << "[";
+    char item[256];
+    for (size_t i = 0; i < rec.size(); ++i) {
+        snprintf(item, sizeof item,
+                 "%s{\"M\": %d, \"NT\": %d, \"reduced\": \"%s\", \"split\": %d, \"blocks\": %d, "
+                 "\"blocks_small\": %d, \"pred_us\": %.3f, \"meas_us\": %.3f}",
+                 i ? ", " : "", rec[i].M, rec[i].NT, rec[i].thomas ? "thomas" : "pcr", rec[i].split, rec[i].blocks,
+                 rec[i].blocks_small, rec[i].pred_us, rec[i].meas_us);
+        o << item;
+    }
+    o << "]";
+    const std::string out = o.str();
+    if (out.size() + 1 > len) return trid::handle_fail(h, TRID_ERR_ARG, "buffer too small");
+    std::memcpy(buf, out.c_str(), out.size() + 1);
+    return TRID_OK;
 }
 
 static std::string device_arch() {

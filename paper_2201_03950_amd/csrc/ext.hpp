@@ -106,6 +106,14 @@ struct TunedPlan {
     int M = 0, NT = 0, thomas = 0;
 };
 
+// One plan the uneven-batch autotuner considered: the model's prediction and,
+// when it was among those timed, the measured time (else < 0).
+struct TuneRecord {
+    int M = 0, NT = 0, thomas = 0, split = 0;
+    int blocks = 0, blocks_small = 0;  // persistent workgroups of the launch(es)
+    double pred_us = 0, meas_us = -1;
+};
+
 struct ExtState {
     int force_M = 0;  // forced tile rows (0: automatic)
     int force_L = 0;  // forced lines per block (0: automatic)
@@ -113,6 +121,7 @@ struct ExtState {
     std::map<std::string, TunedPlan> tuned;
     // uneven-batch schedules keyed by a hash of the offsets
     std::map<std::string, VarlenSchedule *> varlen;
+    std::vector<TuneRecord> last_tune;  // the most recent autotuning run
     // scratch for adjoint / refinement entry points
     void *ws2 = nullptr;
     size_t ws2_bytes = 0;

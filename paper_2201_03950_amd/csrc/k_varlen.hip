@@ -402,7 +402,39 @@ auto with_kernel(int prec, int M, int NT, int thomas, F &&f) -> decltype(f(k_var
 
 }  // namespace
 
+int varlen_blocks(int prec, const VarlenVariant &v) {
+    return with_kernel(prec, v.M, v.NT, v.thomas, [&](auto k, int nt, size_t lds) { return occupancy_blocks(k, nt, lds); });
+}
+
 bool varlen_variant_fits(const VarlenVariant &v, i64 maxlen) { return (maxlen + v.M - 1) / v.M <= v.NT; }
+
+void varlen_pack(const int64_t *offsets_host, std::vector<int> *ids, const VarlenVariant &v, std::vector<int> *tstart,
+                 std::vector<int> *item_begin, std::vector<int> *item_pmax) {
+    std::vector<int> &order = *ids;
+    const i64 nsys = (i64)order.size();
+    std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
+        return offsets_host[i + 1] - offsets_host[i] > offsets_host[j + 1] - offsets_host[j];
+    });
+    tstart->assign(nsys, 0);
+    item_begin->assign(1, 0);
+    item_pmax->clear();
+    int used = 0, pmax = 0;
+    for (i64 k = 0; k < nsys; ++k) {
+        const i64 len = offsets_host[order[k] + 1] - offsets_host[order[k]];
+        const int P = (int)((len + v.M - 1) / v.M);
+        if (used + P > v.NT) {  // close the current item (next fit, longest first)
+            item_begin->push_back((int)k);
+            item_pmax->push_back(pmax);
+            used = 0;
+            pmax = 0;
+        }
+        (*tstart)[k] = used;
+        used += P;
+        pmax = std::max(pmax, P);
+    }
+    item_begin->push_back((int)nsys);
+    item_pmax->push_back(pmax);
+}
 
 namespace {
 
@@ -416,26 +448,8 @@ hipError_t build_ids(const int64_t *offsets_host, std::vector<int> ids, int prec
     sc->NT = v.NT;
     sc->nsys = nsys;
     std::vector<int> &order = ids;
-    std::stable_sort(order.begin(), order.end(), [&](int i, int j) {
-        return offsets_host[i + 1] - offsets_host[i] > offsets_host[j + 1] - offsets_host[j];
-    });
-    std::vector<int> tstart(nsys), item_begin(1, 0), item_pmax;
-    int used = 0, pmax = 0;
-    for (i64 k = 0; k < nsys; ++k) {
-        const i64 len = offsets_host[order[k] + 1] - offsets_host[order[k]];
-        const int P = (int)((len + v.M - 1) / v.M);
-        if (used + P > v.NT) {  // close the current item (next fit, longest first)
-            item_begin.push_back((int)k);
-            item_pmax.push_back(pmax);
-            used = 0;
-            pmax = 0;
-        }
-        tstart[k] = used;
-        used += P;
-        pmax = std::max(pmax, P);
-    }
-    item_begin.push_back((int)nsys);
-    item_pmax.push_back(pmax);
+    std::vector<int> tstart, item_begin, item_pmax;
+    varlen_pack(offsets_host, &order, v, &tstart, &item_begin, &item_pmax);
     sc->nitems = (int)item_pmax.size();
     // one device allocation: off | order | tstart | item_begin | item_pmax | counter
     // (off holds every system's offsets; order names the systems of this schedule)

@@ -41,6 +41,14 @@ struct VarlenSchedule {
 
 const std::vector<VarlenVariant> &varlen_variants(int prec);
 bool varlen_variant_fits(const VarlenVariant &v, i64 maxlen);
+// Work items of a schedule: sorts *ids longest first and packs the systems (next
+// fit) into items of at most v.NT tiles; tstart[k] is the first tile of the
+// k-th system in its item, item_begin the first system of each item (plus the
+// end), item_pmax each item's most tiles of one system.  Host only.
+void varlen_pack(const int64_t *offsets_host, std::vector<int> *ids, const VarlenVariant &v, std::vector<int> *tstart,
+                 std::vector<int> *item_begin, std::vector<int> *item_pmax);
+// Persistent blocks a launch of variant v runs with (occupancy x CUs; HIP query).
+int varlen_blocks(int prec, const VarlenVariant &v);
 // Schedule for all systems with variant v; with `small` given, the systems of at
 // most small.M * small.NT rows go to a second launch with that variant.
 hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const VarlenVariant &v, VarlenSchedule *sc,

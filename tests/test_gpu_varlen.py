@@ -159,3 +159,22 @@ def test_varlen_forced_plan_matches_oracle(trid, orc, tmp_path, monkeypatch, pre
     tol = {"f64": 1e-12, "f32": 1e-5, "refine": 1e-9}[prec]
     assert _sys_err(x1.cpu().numpy().astype(np.float64), ref, off) <= tol
     assert torch.equal(x1, x2)
+
+
+@pytest.mark.parametrize("top", [0, 2])
+def test_varlen_autotune_pruned_by_the_model(trid, orc, monkeypatch, top):
+    """TRID_AUTOTUNE_TOP=k times only the model's best k plans (0: all); the
+    report lists every plan best-predicted first, and the chosen plan solves."""
+    a32, b32, c32, d64, off = gen.varlen_batch(2500 + top, 32, 4096, seed=90 + top)  # a fresh schedule key
+    ref = orc.gtsv_varlen(a32, b32, c32, d64.astype(np.float64), off)
+    monkeypatch.setenv("TRID_AUTOTUNE", "1")
+    monkeypatch.setenv("TRID_AUTOTUNE_TOP", str(top))
+    a, b, c, d, x = _run(trid, trid.PREC_F64, a32, b32, c32, d64)
+    trid.gtsv_varlen(trid.PREC_F64, a, b, c, d, x, off)
+    rep = trid.autotune_report()
+    preds = [q["pred_us"] for q in rep]
+    assert len(rep) >= 2 and preds == sorted(preds) and all(p > 0 for p in preds)
+    timed = [q for q in rep if q["meas_us"] >= 0]
+    assert len(timed) == (len(rep) if top == 0 else min(top, len(rep)))
+    assert timed == rep[:len(timed)]
+    assert _sys_err(x.cpu().numpy(), ref, off) <= 1e-12

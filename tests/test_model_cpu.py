@@ -1,0 +1,60 @@
+"""The performance model's host entry (no GPU): predictions for the batched
+line solves follow the plan the library would launch and respond to the
+quantities the model is built from (bytes, tile plan, precision)."""
+
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2201_03950_amd as trid  # noqa: E402
+
+
+@pytest.fixture(autouse=True)
+def _auto_plan():
+    trid.set_tile(0, 0)
+    yield
+    trid.set_tile(0, 0)
+
+
+def test_prediction_and_plan_fields():
+    us, plan = trid.model_gtsv(torch.float64, trid.TRID_FORM_S, [256, 256, 256], 2, 1)
+    assert us > 0 and plan["us"] == pytest.approx(us, rel=1e-3)
+    for k in ("kernel", "M", "L", "P", "threads", "nblocks", "bytes", "t_bytes_us", "t_lat_us"):
+        assert k in plan
+    assert plan["bytes"] == 3 * 8 * 256 ** 3  # s, d in, x out
+    assert plan["kernel"] == "strided" and plan["P"] * plan["M"] >= 256
+
+
+def test_prediction_grows_with_the_bytes():
+    small, _ = trid.model_gtsv(torch.float64, trid.TRID_FORM_S, [256, 256, 64], 2, 1)
+    large, _ = trid.model_gtsv(torch.float64, trid.TRID_FORM_S, [256, 256, 256], 2, 4)
+    arrays, _ = trid.model_gtsv(torch.float64, trid.TRID_FORM_ARRAYS, [256, 256, 256], 2, 4)
+    f32, _ = trid.model_gtsv(torch.float32, trid.TRID_FORM_S, [256, 256, 256], 2, 4)
+    assert small < large < arrays
+    assert f32 < large
+
+
+def test_prediction_follows_the_forced_tile_plan():
+    _, auto = trid.model_gtsv(torch.float32, trid.TRID_FORM_S, [1024, 1024], 1, 1)
+    trid.set_tile(32, 0)
+    _, forced = trid.model_gtsv(torch.float32, trid.TRID_FORM_S, [1024, 1024], 1, 1)
+    assert forced["M"] == 32 and forced["M"] != auto["M"]
+
+
+def test_model_rejects_what_the_solver_rejects():
+    with pytest.raises(trid.TridError):
+        trid.model_gtsv(torch.float64, 7, [256], 0, 1)
+    with pytest.raises(trid.TridError):
+        trid.model_gtsv(torch.float64, trid.TRID_FORM_S, [9000], 0, 1)  # beyond one workgroup's line
+    with pytest.raises(trid.TridError):
+        trid.model_gtsv(torch.float64, trid.TRID_FORM_S, [64, 64], 2, 1)  # no such axis
+
+
+def test_autotune_report_is_empty_before_tuning():
+    import threading
+
+    out = {}
+    th = threading.Thread(target=lambda: out.update(rep=trid.autotune_report()))  # a fresh handle
+    th.start()
+    th.join()
+    assert out["rep"] == []
