@@ -48,6 +48,7 @@ struct ResGeom {
     int tp;         // 1: one pad element after every m points of a row
     int region;     // elements per array (multiple of 4)
     int nsteps;
+    int cl;         // HV: 2 = a, b, c staged in LDS as three more arrays; 1 = b only
 };
 
 // LDS position of point (y, x); M is the tile size (g.m), a constant in kernels.
@@ -381,9 +382,11 @@ struct HvCoef {
     T dt, theta;
 };
 
-template <typename T, int kRM, int STAGE>
-__device__ __forceinline__ void hv_x_phase(const ResGeom &g, const HvCoef<T> &cf, i64 mb, const T *src, T *R,
-                                           T *Z) {
+// CL = 2: a, b, c staged in LDS (CA, CB, CC, same layout as U) instead of read
+// from memory in every phase; CL = 1: b only (it is read in all four phases).
+template <typename T, int kRM, int STAGE, int CL>
+__device__ __forceinline__ void hv_x_phase(const ResGeom &g, const HvCoef<T> &cf, i64 mb, const T *src, T *R, T *Z,
+                                           const T *CA, const T *CB, const T *CC) {
     const int nt = blockDim.x, t = threadIdx.x;
     const int nx = g.nx, ny = g.ny, la = nt / g.px;
     const T dt = cf.dt, tdt = cf.theta * cf.dt, hdt = T(0.5) * cf.dt;
@@ -416,8 +419,19 @@ __device__ __forceinline__ void hv_x_phase(const ResGeom &g, const HvCoef<T> &cf
 #pragma unroll
         for (int k = 0; k < kRM; ++k) {
             const bool v = live && x0 + k < nx;
-            const T ak = load_if(cf.a, e0 + k, v, mb), bk = load_if(cf.b, e0 + k, v, mb);
-            const T ck = load_if(cf.c, e0 + k, v, mb);
+            T ak, bk, ck;
+            if constexpr (CL == 2) {
+                ak = load_if(CA, base + k, v, base);
+                ck = load_if(CC, base + k, v, base);
+            } else {
+                ak = load_if(cf.a, e0 + k, v, mb);
+                ck = load_if(cf.c, e0 + k, v, mb);
+            }
+            if constexpr (CL >= 1) {
+                bk = load_if(CB, base + k, v, base);
+            } else {
+                bk = load_if(cf.b, e0 + k, v, mb);
+            }
             const T f1 = ak * (vc[k] - T(2) * vc[k + 1] + vc[k + 2]);
             const T f = ck * ((vn[k + 2] - vs[k + 2] - vn[k] + vs[k]) * T(0.25)) + f1 +
                         bk * (vs[k + 1] - T(2) * vc[k + 1] + vn[k + 1]);
@@ -441,9 +455,9 @@ __device__ __forceinline__ void hv_x_phase(const ResGeom &g, const HvCoef<T> &cf
     }
 }
 
-template <typename T, int kRM, int STAGE>
+template <typename T, int kRM, int STAGE, int CL>
 __device__ __forceinline__ void hv_y_phase(const ResGeom &g, const HvCoef<T> &cf, i64 mb, const T *src,
-                                           const T *own, T *dst) {
+                                           const T *own, T *dst, const T *CB) {
     const int nt = blockDim.x, t = threadIdx.x;
     const int nx = g.nx, ny = g.ny, lb = nt / g.py;
     const T tdt = cf.theta * cf.dt;
@@ -474,7 +488,7 @@ __device__ __forceinline__ void hv_y_phase(const ResGeom &g, const HvCoef<T> &cf
         for (int k = 0; k < kRM; ++k) {
             const int y = y0 + k;
             const bool v = live && y < ny;
-            const T bk = load_if(cf.b, mb + (i64)y * nx + xa, v, mb);
+            const T bk = CL >= 1 ? load_if(CB, off[k], v, off[k]) : load_if(cf.b, mb + (i64)y * nx + xa, v, mb);
             const T ok = load_if(own, off[k], v, off[k]);
             sv[k] = tdt * bk;
             rd[k] = v ? ok - tdt * bk * (col[k] - T(2) * col[k + 1] + col[k + 2]) : T(0);
@@ -494,29 +508,36 @@ __device__ __forceinline__ void hv_y_phase(const ResGeom &g, const HvCoef<T> &cf
 // coefficients need up to 256 VGPRs (FP64, 14-row tiles).
 constexpr int kHvMaxThreads = 512;
 
-template <typename T, int kRM>
+template <typename T, int kRM, int CL>
 __global__ __launch_bounds__(kHvMaxThreads) void k_hv_resident(ResGeom g, HvCoef<T> cf, T *__restrict__ u_all) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *U = reinterpret_cast<T *>(smem_raw);
     T *R = U + g.region;
     T *Z = R + g.region;
+    T *CB = Z + g.region, *CA = CB + g.region, *CC = CA + g.region;  // CL >= 1: CB; CL = 2: all
     const int nt = blockDim.x, t = threadIdx.x;
     const int nx = g.nx, npts = nx * g.ny;
     const i64 mb = (i64)blockIdx.x * npts;
     T *um = u_all + mb;
     for (int e = t; e < npts; e += nt) {
         const int y = e / nx, x = e - y * nx;
-        U[res_at<kRM>(g, y, x)] = um[e];
+        const int o = res_at<kRM>(g, y, x);
+        U[o] = um[e];
+        if constexpr (CL >= 1) CB[o] = cf.b[mb + e];
+        if constexpr (CL == 2) {
+            CA[o] = cf.a[mb + e];
+            CC[o] = cf.c[mb + e];
+        }
     }
     __syncthreads();
     for (int it = 0; it < g.nsteps; ++it) {
-        hv_x_phase<T, kRM, 0>(g, cf, mb, U, R, Z);
+        hv_x_phase<T, kRM, 0, CL>(g, cf, mb, U, R, Z, CA, CB, CC);
         __syncthreads();
-        hv_y_phase<T, kRM, 0>(g, cf, mb, U, R, R);
+        hv_y_phase<T, kRM, 0, CL>(g, cf, mb, U, R, R, CB);
         __syncthreads();
-        hv_x_phase<T, kRM, 1>(g, cf, mb, R, R, Z);
+        hv_x_phase<T, kRM, 1, CL>(g, cf, mb, R, R, Z, CA, CB, CC);
         __syncthreads();
-        hv_y_phase<T, kRM, 1>(g, cf, mb, R, Z, U);
+        hv_y_phase<T, kRM, 1, CL>(g, cf, mb, R, Z, U, CB);
         __syncthreads();
     }
     for (int e = t; e < npts; e += nt) {
@@ -575,9 +596,8 @@ int cf_fields(int M, int P) {
 }
 
 // Layout search for tile size M.
-bool search_layout_m(const ResidentReq &r, int M, ResGeom *out, size_t *bytes) {
+bool search_layout_m(const ResidentReq &r, int M, int narr, ResGeom *out, size_t *bytes) {
     const int w = r.f64 ? 8 : 4;
-    const int narr = (r.s || r.hv) ? 3 : 2;  // u, d (, s); HV: u, r, z
     const int px = tiles_of(r.nx, M), py = tiles_of(r.ny, M);
     if (px > 16 || py > 16) return false;
     const size_t tabs =  // constant s: the factor tables
@@ -633,8 +653,21 @@ bool search_layout(const ResidentReq &r, ResGeom *out, size_t *bytes) {
     };
     std::stable_sort(order, order + 4, [&](int a, int b) { return padded(kTileRows[a]) < padded(kTileRows[b]); });
 
-    for (int i : order)
-        if (search_layout_m(r, kTileRows[i], out, bytes)) return true;
+    // arrays: u, d (, s); HV: u, r, z, and a, b, c too where they fit
+    for (int i : order) {
+        if (r.hv && search_layout_m(r, kTileRows[i], 6, out, bytes)) {
+            out->cl = 2;
+            return true;
+        }
+        if (r.hv && search_layout_m(r, kTileRows[i], 4, out, bytes)) {
+            out->cl = 1;
+            return true;
+        }
+        if (search_layout_m(r, kTileRows[i], (r.s || r.hv) ? 3 : 2, out, bytes)) {
+            out->cl = 0;
+            return true;
+        }
+    }
     return false;
 }
 
@@ -676,9 +709,9 @@ hipError_t go(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_t 
     return hipGetLastError();
 }
 
-template <typename T, int M>
+template <typename T, int M, int CL>
 hipError_t go_hv(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_t s) {
-    auto kern = k_hv_resident<T, M>;
+    auto kern = k_hv_resident<T, M, CL>;
     if (bytes > 64 * 1024) {
         static bool raised = false;
         if (!raised) {
@@ -696,7 +729,11 @@ hipError_t go_hv(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream
 
 template <int M>
 hipError_t go_t(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_t s) {
-    if (r.hv) return r.f64 ? go_hv<double, M>(r, g, bytes, s) : go_hv<float, M>(r, g, bytes, s);
+    if (r.hv) {
+        if (g.cl == 2) return r.f64 ? go_hv<double, M, 2>(r, g, bytes, s) : go_hv<float, M, 2>(r, g, bytes, s);
+        if (g.cl == 1) return r.f64 ? go_hv<double, M, 1>(r, g, bytes, s) : go_hv<float, M, 1>(r, g, bytes, s);
+        return r.f64 ? go_hv<double, M, 0>(r, g, bytes, s) : go_hv<float, M, 0>(r, g, bytes, s);
+    }
     if (r.f64) return r.s ? go<double, true, M>(r, g, bytes, s) : go<double, false, M>(r, g, bytes, s);
     return r.s ? go<float, true, M>(r, g, bytes, s) : go<float, false, M>(r, g, bytes, s);
 }
