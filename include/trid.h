@@ -206,7 +206,8 @@ int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, doub
  * application (Alg. 4, Section V): explicit predictor stencils alternating
  * with line solves along x and y.  u, a, b, c are device arrays of dtype dt
  * and shape (batch, ny, nx), x contiguous (dims = {nx, ny}); a, b, c are the
- * per-point coefficients, with unit spacing and zero values outside the mesh.
+ * per-point coefficients (read only; u must not overlap them), with unit
+ * spacing and zero values outside the mesh.
  * With F1 = a D_xx, F2 = b D_yy, F0 = c D_xy (D_xy the 4-point cross stencil
  * over 4) and F = F0 + F1 + F2, one step of size tau is
  *   Y0 = U + tau F(U)

@@ -585,6 +585,7 @@ int trid_hv_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *a, const
     if (flags & ~(unsigned)TRID_ADI_STREAM) return trid::handle_fail(h, TRID_ERR_ARG, "unknown flag");
     if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
     if (!u || !a || !b || !c) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    if (u == a || u == b || u == c) return trid::handle_fail(h, TRID_ERR_ARG, "u may not alias a, b or c");
     if (nsteps < 0) return trid::handle_fail(h, TRID_ERR_ARG, "nsteps must be >= 0");
     if (!(tau >= 0.0) || !(theta > 0.0) || tau > 1e300 || theta > 1e300)
         return trid::handle_fail(h, TRID_ERR_ARG, "dt must be >= 0 and theta > 0, both finite");

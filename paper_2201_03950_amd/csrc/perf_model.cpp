@@ -62,8 +62,8 @@ const LinesParams &lines_params() {
 
 const VarlenParams &varlen_params() {
     static const VarlenParams p{
-        /*t0_us*/ 18.71, /*bw_gbs*/ 3750.0,    /*lat_us*/ 0.0,   /*cu_gbs*/ 500.0,
-        /*row_ns*/ 271.4, /*f64_factor*/ 4.0, /*lvl_ns*/ 1986.8, /*thomas_ns*/ 50.0,
+        /*t0_us*/ 15.31,  /*bw_gbs*/ 3084.0,   /*lat_us*/ 3.663,  /*cu_gbs*/ 2000.0,
+        /*row_ns*/ 321.6, /*f64_factor*/ 3.501, /*lvl_ns*/ 1236.9, /*thomas_ns*/ 103.7,
     };
     return p;
 }
@@ -110,17 +110,20 @@ ModelTerms model_varlen(const int64_t *off, std::vector<int> ids, int prec, cons
     ModelTerms t;
     const double per_row = prec == 0 ? 40.0 : (prec == 1 ? 20.0 : 28.0);  // a, b, c, d in, x out
     const double f = prec == 1 ? 1.0 : p.f64_factor;
-    double sum = 0, mx = 0, rows = 0;
+    // the longest item is bounded by the largest rows and reduced-solve cost
+    // of any item (the packing puts the longest systems first)
+    double sum = 0, rows = 0, rmax = 0, redmax = 0;
     for (size_t i = 0; i < item_pmax.size(); ++i) {
         double irows = 0;
         for (int k = item_begin[i]; k < item_begin[i + 1]; ++k) irows += (double)(off[ids[k] + 1] - off[ids[k]]);
         const int pm = item_pmax[i];
         const double red = v.thomas ? pm * p.thomas_ns : log2_ceil(pm) * p.lvl_ns;
-        const double c = p.lat_us + irows * per_row / (p.cu_gbs * 1e3) + (v.M * p.row_ns * f + red) * 1e-3;
-        sum += c;
-        mx = std::max(mx, c);
+        sum += p.lat_us + irows * per_row / (p.cu_gbs * 1e3) + (v.M * p.row_ns * f + red) * 1e-3;
         rows += irows;
+        rmax = std::max(rmax, irows);
+        redmax = std::max(redmax, red);
     }
+    const double mx = p.lat_us + rmax * per_row / (p.cu_gbs * 1e3) + (v.M * p.row_ns * f + redmax) * 1e-3;
     t.bytes = per_row * rows;
     t.t_bytes = t.bytes / (p.bw_gbs * 1e3);
     const int b = std::max(1, std::min(blocks, (int)item_pmax.size()));

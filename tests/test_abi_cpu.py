@@ -56,6 +56,7 @@ def _dims(*v):
 
 
 FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+U = ctypes.c_void_p(0x3000)  # a distinct fake array (entry points that reject aliasing)
 
 
 @pytest.mark.parametrize(
@@ -157,18 +158,21 @@ def test_refine_and_adjoint_argument_checks(lib, h):
 def test_hv_argument_checks(lib, h):
     d = _dims(8, 4)
     th = 0.5 + 3 ** 0.5 / 6
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, 0.1, th, d, 2, 0, 0) == 0  # no steps: no-op
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, None, 0.1, th, d, 2, 1, 0) == 1
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, -0.1, th, d, 2, 1, 0) == 1
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, float("inf"), th, d, 2, 1, 0) == 1
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, 0.1, 0.0, d, 2, 1, 0) == 1
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, 0.1, float("nan"), d, 2, 1, 0) == 1
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, 0.1, th, d, 2, -1, 0) == 1
-    assert lib.trid_hv_step(h, 7, FAKE, FAKE, FAKE, FAKE, 0.1, th, d, 2, 1, 0) == 1
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, 0.1, th, d, 0, 1, 0) == 1  # empty batch
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, 0.1, th, _dims(9000, 4), 1, 1, 0) == 4
-    assert lib.trid_hv_step(None, 1, FAKE, FAKE, FAKE, FAKE, 0.1, th, d, 2, 1, 0) == 1
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, 0.1, th, d, 2, 1, 1) == 1  # graph flag: not for HV
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, 0.1, th, d, 2, 0, 0) == 0  # no steps: no-op
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, None, 0.1, th, d, 2, 1, 0) == 1
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, -0.1, th, d, 2, 1, 0) == 1
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, float("inf"), th, d, 2, 1, 0) == 1
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, 0.1, 0.0, d, 2, 1, 0) == 1
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, 0.1, float("nan"), d, 2, 1, 0) == 1
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, 0.1, th, d, 2, -1, 0) == 1
+    assert lib.trid_hv_step(h, 7, U, FAKE, FAKE, FAKE, 0.1, th, d, 2, 1, 0) == 1
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, 0.1, th, d, 0, 1, 0) == 1  # empty batch
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, 0.1, th, _dims(9000, 4), 1, 1, 0) == 4
+    assert lib.trid_hv_step(None, 1, U, FAKE, FAKE, FAKE, 0.1, th, d, 2, 1, 0) == 1
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, 0.1, th, d, 2, 1, 1) == 1  # graph flag: not for HV
+    other = ctypes.c_void_p(0x2000)
+    assert lib.trid_hv_step(h, 1, FAKE, FAKE, other, other, 0.1, th, d, 2, 1, 0) == 1  # u aliases a
+    assert b"alias" in lib.trid_last_error(h)
 
 
 def test_forced_allocation_failure(lib, h, monkeypatch):
@@ -178,7 +182,7 @@ def test_forced_allocation_failure(lib, h, monkeypatch):
     assert b"TRID_FAIL_ALLOC" in lib.trid_last_error(h)
     # contiguous lines beyond TRID_MAX_LINE need the chunked solve's workspace
     assert lib.trid_gtsv_batched_s(h, 1, FAKE, FAKE, 1, _dims(9000), 0, 1) == 2
-    assert lib.trid_hv_step(h, 1, FAKE, FAKE, FAKE, FAKE, 0.1, 0.8, _dims(8, 4), 1, 1, 2) == 2  # per-step path (its workspace)
+    assert lib.trid_hv_step(h, 1, U, FAKE, FAKE, FAKE, 0.1, 0.8, _dims(8, 4), 1, 1, 2) == 2  # per-step path (its workspace)
 
 
 def test_plan_cache_environment(lib, tmp_path, monkeypatch):
