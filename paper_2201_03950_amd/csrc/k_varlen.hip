@@ -214,9 +214,11 @@ __global__ __launch_bounds__(NT) void k_varlen_plain(VarlenArgs g) {
         varlen_assign<M, NT>(g, item, s_sys, s_p, s_base, s_cnt, sys, p, P, n);
         const bool act = sys >= 0;
         T ra[M], rb[M], rc[M], rd[M];
-        // with small tiles the next array's loads are issued before this one
-        // is staged (registers allow it); otherwise one array at a time
-        constexpr bool pipe = M * sizeof(T) <= 64;
+        // the next array's loads are issued before this one is staged where
+        // registers allow it: small tiles, and 512-thread blocks (one block
+        // per CU in any case, so up to 256 VGPRs cost no occupancy) of the PCR
+        // variant; otherwise one array at a time
+        constexpr bool pipe = M * sizeof(T) <= 64 || (NT >= 512 && M * sizeof(T) <= 128 && !THOMAS);
         T vn[M];
         varlen_load<T, M, NT>(vn, arr[0], s_base, s_cnt);
 #pragma unroll
