@@ -42,8 +42,10 @@ def _field_err(x, ref):
 # column, lines past one tile with ragged tails and padded tiles (33: 5 tiles
 # of 8 in 8 lanes), the largest resident line (128), and meshes that take the
 # per-step kernels by default (x lines of 300 points; 128 x 128 FP64 is
-# beyond one workgroup's LDS)
-SHAPES = [(40, 20), (100, 50), (1, 1), (1, 9), (9, 1), (37, 13), (33, 70), (128, 40), (300, 7), (128, 128)]
+# beyond one workgroup's LDS); 16 tiles per y line (x 128) with one pass or
+# two passes of the workgroup over the lines
+SHAPES = [(40, 20), (100, 50), (1, 1), (1, 9), (9, 1), (37, 13), (33, 70), (128, 40), (300, 7), (128, 128),
+          (64, 128), (8, 128), (40, 128)]
 
 
 def _kernels(trid, fn):
