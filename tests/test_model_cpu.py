@@ -58,3 +58,31 @@ def test_autotune_report_is_empty_before_tuning():
     th.start()
     th.join()
     assert out["rep"] == []
+
+
+def _cpp_params(struct_fn):
+    """The constants of lines_params() / varlen_params() as written in perf_model.cpp."""
+    import os
+    import re
+
+    src = open(os.path.join(os.path.dirname(trid.__file__), "csrc", "perf_model.cpp")).read()
+    body = src[src.index(struct_fn):]
+    body = body[:body.index("};")]
+    return [float(v) for v in re.findall(r"/\*\w+\*/\s*([-0-9.eE]+)", body)]
+
+
+def test_calibration_mirror_matches_the_library():
+    """The refit script's mirror of the line model reproduces the library's predictions
+    with the library's constants (so a refit's constants mean the same thing)."""
+    from paper_2201_03950_amd import model_calibrate as mc
+
+    p = _cpp_params("const LinesParams &lines_params()")
+    assert len(p) == len(mc.LINE_NAMES)
+    cases = [(torch.float64, trid.TRID_FORM_S, [256, 256, 256], 2, 1), (torch.float32, trid.TRID_FORM_ARRAYS,
+             [1024], 0, 512), (torch.float64, trid.TRID_FORM_ARRAYS, [64, 2048], 1, 4),
+             (torch.float32, trid.TRID_FORM_S, [4096], 0, 64)]
+    for dt, form, dims, axis, batch in cases:
+        us, plan = trid.model_gtsv(dt, form, dims, axis, batch)
+        rec = {"plan": plan, "dtype": str(dt)[6:], "dims": dims, "axis": axis, "form": form}
+        assert mc._pred_lines(p, rec) == pytest.approx(us, rel=1e-3)
+    assert len(_cpp_params("const VarlenParams &varlen_params()")) == len(mc.VARLEN_NAMES)
