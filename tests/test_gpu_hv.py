@@ -43,9 +43,10 @@ def _field_err(x, ref):
 # of 8 in 8 lanes), the largest resident line (128), and meshes that take the
 # per-step kernels by default (x lines of 300 points; 128 x 128 FP64 is
 # beyond one workgroup's LDS); 16 tiles per y line (x 128) with one pass or
-# two passes of the workgroup over the lines
+# two passes of the workgroup over the lines; 100 x 56 FP64 (14-row tiles with
+# a, b, c read from memory: the variant whose registers spill)
 SHAPES = [(40, 20), (100, 50), (1, 1), (1, 9), (9, 1), (37, 13), (33, 70), (128, 40), (300, 7), (128, 128),
-          (64, 128), (8, 128), (40, 128)]
+          (64, 128), (8, 128), (40, 128), (100, 56)]
 
 
 def _kernels(trid, fn):
