@@ -175,6 +175,20 @@ def test_hv_argument_checks(lib, h):
     assert b"alias" in lib.trid_last_error(h)
 
 
+def test_model_and_report_argument_checks(lib, h):
+    us = ctypes.c_double()
+    buf = ctypes.create_string_buffer(64)
+    assert lib.trid_model_gtsv(h, 1, 1, 3, _dims(64, 64, 64), 2, 1, ctypes.byref(us), buf, len(buf)) == 0
+    assert us.value > 0 and buf.value.startswith(b"{")
+    assert lib.trid_model_gtsv(h, 1, 1, 3, _dims(64, 64, 64), 2, 1, None, None, 0) == 1  # no output
+    assert lib.trid_model_gtsv(h, 1, 5, 3, _dims(64, 64, 64), 2, 1, ctypes.byref(us), None, 0) == 1  # form
+    assert lib.trid_model_gtsv(h, 9, 1, 3, _dims(64, 64, 64), 2, 1, ctypes.byref(us), None, 0) == 1  # dtype
+    assert lib.trid_model_gtsv(None, 1, 1, 1, _dims(64), 0, 1, ctypes.byref(us), None, 0) == 1
+    assert lib.trid_autotune_report(h, buf, len(buf)) == 0 and buf.value == b"[]"
+    assert lib.trid_autotune_report(h, buf, 2) == 1  # too small for "[]"
+    assert lib.trid_autotune_report(h, None, 64) == 1
+
+
 def test_forced_allocation_failure(lib, h, monkeypatch):
     """TRID_FAIL_ALLOC makes every workspace allocation fail before any HIP call."""
     monkeypatch.setenv("TRID_FAIL_ALLOC", "1")
