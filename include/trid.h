@@ -176,7 +176,9 @@ int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t d_dt, const float *
  * longest first, from a device counter.  The schedule (work list, tile plan
  * per length class) is built on the first call for a given offsets content
  * and cached in the handle; with the environment variable TRID_AUTOTUNE=1 the
- * tile plan is chosen by timing the candidates on this call's data.
+ * tile plan is chosen by timing candidates on this call's data: the
+ * TRID_AUTOTUNE_TOP (default 3; 0 = all) plans that the performance model
+ * (trid_model_gtsv's model, applied to the packed work items) ranks fastest.
  * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED, TRID_ERR_ALLOC, TRID_ERR_HIP. */
 int trid_gtsv_varlen(trid_handle_t h, trid_prec_t p, const void *a, const void *b, const void *c,
                      const void *d, void *x, const int64_t *offsets_host, int64_t nsys);
@@ -308,9 +310,10 @@ int trid_model_gtsv(trid_handle_t h, trid_dtype_t dt, int form, int ndim, const 
  * item NT, reduced solve ("pcr" / "thomas"), split flag, the persistent
  * workgroups of its launch (blocks; blocks_small for the short systems of a
  * split plan), the model's predicted time pred_us and the measured time
- * meas_us (-1 for plans the tuner did not time).  With TRID_AUTOTUNE_TOP=k (default 3) the tuner times only the k
- * plans the model ranks best; k = 0 times every plan.  An empty array if no
- * tuning has run.  Errors: TRID_ERR_ARG (NULL buffer or too small). */
+ * meas_us (-1 for plans the tuner did not time).  With TRID_AUTOTUNE_TOP=k
+ * (default 3) the tuner times only the k plans the model ranks best; k = 0
+ * times every plan.  An empty array if no tuning has run.
+ * Errors: TRID_ERR_ARG (NULL buffer or too small). */
 int trid_autotune_report(trid_handle_t h, char *buf, size_t len);
 
 /* ------------------------------------------------------------ plan cache -- */
