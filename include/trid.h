@@ -178,7 +178,8 @@ int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t d_dt, const float *
  * and cached in the handle; with the environment variable TRID_AUTOTUNE=1 the
  * tile plan is chosen by timing candidates on this call's data: the
  * TRID_AUTOTUNE_TOP (default 3; 0 = all) plans that the performance model
- * (trid_model_gtsv's model, applied to the packed work items) ranks fastest.
+ * (its uneven-batch part: per work item, rows, tile sweep and reduced solve)
+ * ranks fastest.
  * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED, TRID_ERR_ALLOC, TRID_ERR_HIP. */
 int trid_gtsv_varlen(trid_handle_t h, trid_prec_t p, const void *a, const void *b, const void *c,
                      const void *d, void *x, const int64_t *offsets_host, int64_t nsys);
