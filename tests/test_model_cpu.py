@@ -86,3 +86,42 @@ def test_calibration_mirror_matches_the_library():
         rec = {"plan": plan, "dtype": str(dt)[6:], "dims": dims, "axis": axis, "form": form}
         assert mc._pred_lines(p, rec) == pytest.approx(us, rel=1e-3)
     assert len(_cpp_params("const VarlenParams &varlen_params()")) == len(mc.VARLEN_NAMES)
+
+
+def test_calibration_fit_runs_on_a_recorded_sweep(tmp_path, capsys):
+    """The refit path of the calibration script on a small synthetic record set
+    (measurements = the library's own predictions, so the fit must recover
+    accuracy close to 1)."""
+    import json
+
+    import numpy as np
+
+    from paper_2201_03950_amd import model_calibrate as mc
+
+    rng = np.random.default_rng(0)
+    recs = []
+    for dt in (torch.float64, torch.float32):
+        for form in (trid.TRID_FORM_S, trid.TRID_FORM_ARRAYS):
+            for axis, dims in ((0, [256]), (1, [256, 256]), (2, [64, 64, 128])):
+                for batch in (4, 64):
+                    us, plan = trid.model_gtsv(dt, form, dims, axis, batch)
+                    recs.append({"kind": "lines", "dtype": str(dt)[6:], "form": form, "axis": axis, "n": dims[-1],
+                                 "size": batch * int(np.prod(dims)), "dims": dims, "batch": batch, "force_M": 0,
+                                 "meas_us": us, "pred_us": us, "plan": plan})
+    pv = _cpp_params("const VarlenParams &varlen_params()")
+    for mix in mc.CAL_MIXES + ("held_a", "held_b"):
+        lens = [int(v) for v in rng.integers(32, 2048, 300)]
+        for prec in (0, 1):
+            plans = []
+            for M, NT in ((8, 1024), (16, 512), (32, 256)):
+                q = {"M": M, "NT": NT, "reduced": "pcr", "split": 0, "blocks": 256, "blocks_small": 0}
+                q["meas_us"] = mc._pred_varlen(pv, prec, mc._varlen_launches(lens, q))
+                plans.append(q)
+            recs.append({"kind": "varlen", "mix": mix, "prec": prec, "plans": plans, "lens": lens})
+    path = tmp_path / "sweep.jsonl"
+    path.write_text("".join(json.dumps(r) + "\n" for r in recs))
+    mc.fit(str(path))
+    out = capsys.readouterr().out
+    assert "LinesParams" in out and "VarlenParams" in out
+    accs = [float(x) for x in __import__("re").findall(r"'mean': ([0-9.]+)", out)]
+    assert len(accs) == 4 and min(accs) > 0.9
