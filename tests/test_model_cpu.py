@@ -9,8 +9,21 @@ torch = pytest.importorskip("torch")
 import paper_2201_03950_amd as trid  # noqa: E402
 
 
+@pytest.fixture(scope="module", autouse=True)
+def _library():
+    import os
+
+    from paper_2201_03950_amd import _binding
+
+    if not os.path.exists(_binding.LIB_PATH):
+        from paper_2201_03950_amd import build
+
+        build.build()
+    _binding.load_library()
+
+
 @pytest.fixture(autouse=True)
-def _auto_plan():
+def _auto_plan(_library):
     trid.set_tile(0, 0)
     yield
     trid.set_tile(0, 0)
