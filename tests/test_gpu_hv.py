@@ -77,20 +77,22 @@ def test_hv_matches_oracle(trid, orc, dt, nx, ny, stream):
 
 
 @pytest.mark.parametrize("stream", [False, True], ids=["default", "stream"])
-def test_hv_slv_batch_sampled(trid, orc, stream):
-    """The 100 x 50 mesh at batch 3000 (the largest SLV configuration), FP64, in the
-    launch configuration the bench times: the oracle recomputes a sample of the
-    meshes, which are independent."""
-    nx, ny, batch, steps, tau = 100, 50, 3000, 3, 0.25
-    u, a, b, c = gen.hv_slv((nx, ny), batch)
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("nx,ny", [(100, 50), (40, 20)], ids=["100x50", "40x20"])
+def test_hv_slv_batch_sampled(trid, orc, stream, dt, nx, ny):
+    """The SLV meshes at batch 3000 (the largest SLV configuration), in the launch
+    configuration the bench times: the oracle recomputes a sample of the meshes,
+    which are independent."""
+    batch, steps, tau = 3000, 3, 0.25
+    u, a, b, c = (v.astype(dt) for v in gen.hv_slv((nx, ny), batch))
     tu = _t(u)
     trid.hv_step(tu, _t(a), _t(b), _t(c), tau, THETA, steps, stream=stream)
-    out = tu.cpu().numpy()
+    out = tu.cpu().numpy().astype(np.float64)
     pick = np.array([0, 1, 1499, 2998, 2999])
-    ref = orc.hv_step(u[pick], a[pick], b[pick], c[pick], tau, THETA, steps)
+    ref = orc.hv_step(*(v[pick].astype(np.float64) for v in (u, a, b, c)), tau, THETA, steps)
     err = _field_err(out[pick], ref)
-    print("hv sampled stream=%d err=%.2e" % (stream, err))
-    assert err <= TOL[np.float64]
+    print("hv sampled %dx%d %s stream=%d err=%.2e" % (nx, ny, np.dtype(dt).name, stream, err))
+    assert err <= TOL[dt]
 
 
 def test_hv_resident_matches_streamed_over_many_steps(trid):
