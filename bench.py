@@ -787,6 +787,26 @@ def ingest_pmc(fetch_dir, write_dir):
     print("copy calibration factors: fetch %.4f, write %.4f" % (kf, kw))
 
 
+def host_cpu():
+    """Model name and logical CPU count of the host (from /proc/cpuinfo), and the
+    CPUs this process may run on."""
+    model, logical = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model == "unknown":
+                    model = line.split(":", 1)[1].strip()
+                if line.startswith("processor"):
+                    logical += 1
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 0
+    return {"model": model, "logical_cpus": logical, "usable_cpus": usable}
+
+
 def cpu_baseline(budget_s=12.0, max_steps=60):
     """The oracle (never tuned) on the same 256^3 FP64 workload, a bounded number of steps."""
     from oracle import oracle
@@ -808,7 +828,7 @@ def cpu_baseline(budget_s=12.0, max_steps=60):
     el1 = time.perf_counter() - t1
     oracle.set_num_threads(cores)
     return {"value": round(3 * 65536 * steps / el, 1), "unit": "solves/s",
-            "cores": cores, "kind": "oracle",
+            "cores": cores, "kind": "oracle", "host": host_cpu(),
             "sample": "%d ADI step(s) of the 256^3 FP64 workload (s=0.2), %.1f s wall" % (steps, el),
             "value_1_thread": round(3 * 65536 / el1, 1)}
 
@@ -837,8 +857,8 @@ def main():
         ingest_pmc(*args.ingest_pmc)
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only; --gpus %d is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not run)" % args.gpus, file=sys.stderr)
+        print("bench.py: only one GPU is measured; --gpus %d is not supported "
+              "(sharding over several GPUs is a design, not built or run)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 

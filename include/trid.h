@@ -38,6 +38,16 @@
  *             trid_last_error() returns the text of the handle's last error.
  *   Threads:  one handle per host thread; a handle may be used with any
  *             stream of the device that was current when it was first used.
+ *             A handle's calls share its workspace, work counters and
+ *             schedules, so they never overlap: when trid_set_stream switches
+ *             to another stream, work enqueued there afterwards waits for the
+ *             work already enqueued on the previous stream (not across a graph
+ *             capture: a caller capturing a graph keeps one stream per handle,
+ *             or uses one handle per stream).
+ *   Caches:   captured graphs and uneven-batch schedules are cached per handle
+ *             and keyed on the device pointers; each cache keeps a bounded
+ *             number of entries and evicts the least recently used one
+ *             (trid_cache_report).
  */
 #ifndef TRID_H
 #define TRID_H
@@ -89,7 +99,10 @@ int trid_create(trid_handle_t *h);
  * graphs.  NULL is accepted (no-op). */
 int trid_destroy(trid_handle_t h);
 
-/* Select the stream later calls enqueue on (NULL = null stream). */
+/* Select the stream later calls enqueue on (NULL = null stream).  If the
+ * handle has enqueued work on the previous stream, the new stream is made to
+ * wait for it (an event), unless either stream is capturing a graph.
+ * Errors: TRID_ERR_ARG (NULL handle), TRID_ERR_HIP. */
 int trid_set_stream(trid_handle_t h, trid_stream_t stream);
 
 /* Text of the handle's last error ("" if none); valid until the next call on h.
@@ -179,10 +192,20 @@ int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t d_dt, const float *
  * tile plan is chosen by timing candidates on this call's data: the
  * TRID_AUTOTUNE_TOP (default 3; 0 = all) plans that the performance model
  * (its uneven-batch part: per work item, rows, tile sweep and reduced solve)
- * ranks fastest.
+ * ranks fastest.  The timed runs write x, or, when x is d, a workspace array
+ * of the handle, so an in-place solve still returns A^{-1} d.
  * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED, TRID_ERR_ALLOC, TRID_ERR_HIP. */
 int trid_gtsv_varlen(trid_handle_t h, trid_prec_t p, const void *a, const void *b, const void *c,
                      const void *d, void *x, const int64_t *offsets_host, int64_t nsys);
+
+/* As trid_gtsv_varlen with the offsets in DEVICE memory (int64[nsys + 1]).
+ * The schedule is built on the host, so the call copies the offsets to the
+ * host after the work already enqueued on the handle's stream and waits for
+ * that copy (the call synchronises the stream once; it cannot be captured
+ * into a graph).  Then as trid_gtsv_varlen.
+ * Errors: as trid_gtsv_varlen. */
+int trid_gtsv_varlen_dev(trid_handle_t h, trid_prec_t p, const void *a, const void *b, const void *c,
+                         const void *d, void *x, const int64_t *offsets_dev, int64_t nsys);
 
 /* ------------------------------------------------------------------- ADI -- */
 
@@ -255,12 +278,17 @@ int trid_gtsv_batched_s_adjoint(trid_handle_t h, trid_dtype_t dt, const void *s,
                                 void *g, void *gs, int ndim, const int64_t *dims, int axis,
                                 int64_t batch);
 
-/* One ADI step (trid_adi_step with per-point s, one step) in reverse: given
- * the checkpoint u_t (the field before the step) and u_bar = dL/du_{t+1},
+/* One ADI step (trid_adi_step, one step, no graph) in reverse: given the
+ * checkpoint u_t (the field before the step) and u_bar = dL/du_{t+1},
  * recomputes the step's intermediates from u_t, overwrites u_bar with
- * dL/du_t and ACCUMULATES dL/ds of this step into s_bar.  s must not be NULL.
- * Workspace is owned by the handle. */
-int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s,
+ * dL/du_t and ACCUMULATES dL/ds of this step into s_bar.  s is the per-point
+ * diffusion number (dtype dt), or NULL for the constant s0 (finite); with a
+ * constant s0, s_bar receives the per-point derivative dL/ds_i at s = s0
+ * everywhere, whose sum over the mesh is dL/ds0.  s_bar may be NULL when the
+ * s gradient is not wanted.  Workspace is owned by the handle.
+ * Errors: TRID_ERR_ARG (NULL u_t or u_bar, ndim not 2 or 3, non-finite s0,
+ * ...), TRID_ERR_UNSUPPORTED, TRID_ERR_ALLOC, TRID_ERR_HIP. */
+int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s, double s0,
                           void *u_bar, void *s_bar, int ndim, const int64_t *dims, int64_t batch);
 
 /* One ADI step with per-point s (as trid_adi_step, one step, no graph) that
@@ -316,6 +344,13 @@ int trid_model_gtsv(trid_handle_t h, trid_dtype_t dt, int form, int ndim, const 
  * times every plan.  An empty array if no tuning has run.
  * Errors: TRID_ERR_ARG (NULL buffer or too small). */
 int trid_autotune_report(trid_handle_t h, char *buf, size_t len);
+
+/* The handle's caches as JSON text: {"adi_graphs": n, "adi_graph_cap": n,
+ * "varlen_schedules": n, "varlen_schedule_cap": n, "varlen_graphs": n,
+ * "varlen_graph_cap": n} -- captured ADI runs, uneven-batch schedules, and
+ * captured uneven-batch launches (summed over schedules; the cap is per
+ * schedule).  Host only.  Errors: TRID_ERR_ARG (NULL buffer or too small). */
+int trid_cache_report(trid_handle_t h, char *buf, size_t len);
 
 /* ------------------------------------------------------------ plan cache -- */
 

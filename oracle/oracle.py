@@ -58,7 +58,6 @@ def _load():
             "orc_gtsv": ([P, P, P, P, I, LP, I, L], I),
             "orc_gtsv_f32": ([P, P, P, P, I, LP, I, L], I),
             "orc_gtsv_varlen": ([P, P, P, P, LP, L], I),
-            "orc_gtsv_varlen_f32": ([P, P, P, P, LP, L], I),
             "orc_pcr_line": ([L, P, P, P, P], I),
             "orc_tiled_thomas_line": ([L, P, P, P, P, L], I),
             "orc_laplacian": ([P, P, I, LP, L], I),
@@ -153,17 +152,6 @@ def gtsv_varlen(a, b, c, d, offsets):
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
     _check(lib.orc_gtsv_varlen(_ptr(a), _ptr(b), _ptr(c), _ptr(x), offp, len(off) - 1), "gtsv_varlen")
-    return x
-
-
-def gtsv_varlen_f32(a, b, c, d, offsets):
-    lib = _load()
-    a, b, c = (np.ascontiguousarray(v, dtype=np.float32) for v in (a, b, c))
-    x = np.ascontiguousarray(d, dtype=np.float32).copy()
-    off = np.ascontiguousarray(offsets, dtype=np.int64)
-    offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_long))
-    _check(lib.orc_gtsv_varlen_f32(_ptr(a), _ptr(b), _ptr(c), _ptr(x), offp, len(off) - 1),
-           "gtsv_varlen_f32")
     return x
 
 

@@ -18,7 +18,7 @@
  *   - the adjoint of the line solve and of one ADI step (not in the paper: the
  *     reverse-mode derivative of the same computation).
  *
- * Readings of the paper that this file fixes (each also listed in the design doc):
+ * Readings of the paper that this file fixes:
  *   R1 eq. (1) right-hand side is d_i;
  *   R2 Alg. 1 leaves u_{N-1} implicit: u_{N-1} = d*_{N-1};
  *   R3 c_{N-1} and a_0 are never read (treated as 0);
@@ -178,28 +178,6 @@ int orc_gtsv_varlen(const double *a, const double *b, const double *c, double *d
         for (idx_t k = 0; k < nsys; ++k) {
             idx_t s = off[k];
             thomas_line(off[k + 1] - s, a + s, b + s, c + s, d + s, 1, cs, ds);
-        }
-        free(cs);
-        free(ds);
-    }
-    return 0;
-}
-
-int orc_gtsv_varlen_f32(const float *a, const float *b, const float *c, float *d,
-                        const idx_t *off, idx_t nsys) {
-    idx_t nmax = 0;
-    for (idx_t k = 0; k < nsys; ++k) {
-        if (off[k + 1] - off[k] < 1) return 1;
-        if (off[k + 1] - off[k] > nmax) nmax = off[k + 1] - off[k];
-    }
-#pragma omp parallel
-    {
-        float *cs = (float *)malloc(sizeof(float) * (size_t)(nmax > 0 ? nmax : 1));
-        float *ds = (float *)malloc(sizeof(float) * (size_t)(nmax > 0 ? nmax : 1));
-#pragma omp for schedule(dynamic, 16)
-        for (idx_t k = 0; k < nsys; ++k) {
-            idx_t s = off[k];
-            thomas_line_f32(off[k + 1] - s, a + s, b + s, c + s, d + s, 1, cs, ds);
         }
         free(cs);
         free(ds);

@@ -22,6 +22,8 @@ from ._binding import (  # noqa: F401
     gtsv_s_adjoint,
     gtsv_s_refine,
     gtsv_varlen,
+    gtsv_varlen_dev,
+    cache_report,
     model_gtsv,
     autotune_report,
     TRID_FORM_ARRAYS,

@@ -46,14 +46,16 @@ SIGNATURES = {
     "trid_gtsv_batched_refine": ([_H, _I, _P, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_s_refine": ([_H, _I, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_varlen": ([_H, _I, _P, _P, _P, _P, _P, _I64P, _I64], _I),
+    "trid_gtsv_varlen_dev": ([_H, _I, _P, _P, _P, _P, _P, _P, _I64], _I),
     "trid_adi_step": ([_H, _I, _P, _P, _D, _I, _I64P, _I64, _I, ctypes.c_uint], _I),
     "trid_gtsv_batched_adjoint": ([_H, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_s_adjoint": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_model_gtsv": ([_H, _I, _I, _I, _I64P, _I, _I64, ctypes.POINTER(ctypes.c_double), ctypes.c_char_p,
                          ctypes.c_size_t], _I),
     "trid_autotune_report": ([_H, ctypes.c_char_p, ctypes.c_size_t], _I),
+    "trid_cache_report": ([_H, ctypes.c_char_p, ctypes.c_size_t], _I),
     "trid_hv_step": ([_H, _I, _P, _P, _P, _P, _D, _D, _I64P, _I64, _I, ctypes.c_uint], _I),
-    "trid_adi_step_adjoint": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I64], _I),
+    "trid_adi_step_adjoint": ([_H, _I, _P, _P, _D, _P, _P, _I, _I64P, _I64], _I),
     "trid_adi_step_keep": ([_H, _I, _P, _P, _I, _I64P, _I64, _P, _P, _P], _I),
     "trid_adi_step_adjoint_kept": ([_H, _I, _P, _P, _P, _P, _P, _P, _P, _I, _I64P, _I64], _I),
     "trid_plan_load": ([_H, ctypes.c_char_p], _I),
@@ -208,6 +210,17 @@ def autotune_report():
     return json.loads(buf.value.decode())
 
 
+def cache_report():
+    """Sizes and capacities of this thread's handle caches (captured graphs,
+    uneven-batch schedules)."""
+    import json
+
+    h = handle()
+    buf = ctypes.create_string_buffer(1024)
+    _check(load_library().trid_cache_report(h, buf, len(buf)), h)
+    return json.loads(buf.value.decode())
+
+
 def gtsv(a, b, c, d, axis):
     """Solve all lines of ``axis`` in place on d (eqs. (1)-(2), Alg. 1 / eq. (7))."""
     _dev(a, b, c, d)
@@ -290,6 +303,20 @@ def gtsv_varlen(prec, a, b, c, d, x, offsets):
     return x
 
 
+def gtsv_varlen_dev(prec, a, b, c, d, x, offsets):
+    """As gtsv_varlen with ``offsets`` an int64 tensor on the GPU (nsys + 1 entries)."""
+    import torch
+
+    _dev(a, b, c, d, x, offsets)
+    if offsets.dtype != torch.int64 or offsets.dim() != 1 or offsets.numel() < 2:
+        raise ValueError("offsets: a 1-D int64 tensor of nsys + 1 entries")
+    h = handle()
+    lib = _prep(h)
+    _check(lib.trid_gtsv_varlen_dev(h, int(prec), a.data_ptr(), b.data_ptr(), c.data_ptr(),
+                                    d.data_ptr(), x.data_ptr(), offsets.data_ptr(), offsets.numel() - 1), h)
+    return x
+
+
 def adi_step(u, s=None, s0=0.0, nsteps=1, graph=False, stream=False):
     """``nsteps`` ADI steps (Alg. 3) in place on u; s per point (tensor) or constant s0.
 
@@ -349,15 +376,19 @@ def gtsv_s_adjoint(s, x, g, gs, axis):
     return g, gs
 
 
-def adi_step_adjoint(u_t, s, u_bar, s_bar):
-    """One ADI step in reverse from checkpoint u_t: u_bar := dL/du_t, s_bar += dL/ds."""
+def adi_step_adjoint(u_t, s, u_bar, s_bar, s0=0.0):
+    """One ADI step in reverse from checkpoint u_t: u_bar := dL/du_t, s_bar += dL/ds.
+
+    s is a per-point tensor, or None for the constant s0 (then s_bar receives the
+    per-point derivative at s = s0; its sum is dL/ds0).  s_bar may be None."""
     _dev(u_t, s, u_bar, s_bar)
     _same(u_t, s, u_bar, s_bar)
     h = handle()
     lib = _prep(h)
     nd, dims, batch = _mesh(u_t)
-    _check(lib.trid_adi_step_adjoint(h, _dtype_code(u_t), u_t.data_ptr(), s.data_ptr(),
-                                     u_bar.data_ptr(), s_bar.data_ptr(), nd, dims, batch), h)
+    _check(lib.trid_adi_step_adjoint(h, _dtype_code(u_t), u_t.data_ptr(),
+                                     s.data_ptr() if s is not None else None, float(s0), u_bar.data_ptr(),
+                                     s_bar.data_ptr() if s_bar is not None else None, nd, dims, batch), h)
     return u_bar, s_bar
 
 

@@ -16,6 +16,7 @@
 #include "../../include/trid.h"
 #include "dispatch.hpp"
 #include "ext.hpp"
+#include "graph_cache.hpp"
 #include "long_lines.hpp"
 #include "resident.hpp"
 
@@ -25,28 +26,37 @@ namespace {
 
 std::string g_create_error;
 
+// Identity of a captured ADI run: everything the captured launches depend on,
+// including the forced tile plan (trid_set_tile).
 struct GraphKey {
     const void *u, *s;
     double s0;
     int dt, ndim;
     i64 nx, ny, nz, batch;
     int nsteps;
+    int force_M, force_L;
     hipStream_t stream;
     bool operator<(const GraphKey &o) const {
-        return std::tie(u, s, s0, dt, ndim, nx, ny, nz, batch, nsteps, stream) <
-               std::tie(o.u, o.s, o.s0, o.dt, o.ndim, o.nx, o.ny, o.nz, o.batch, o.nsteps, o.stream);
+        return std::tie(u, s, s0, dt, ndim, nx, ny, nz, batch, nsteps, force_M, force_L, stream) <
+               std::tie(o.u, o.s, o.s0, o.dt, o.ndim, o.nx, o.ny, o.nz, o.batch, o.nsteps, o.force_M, o.force_L,
+                        o.stream);
     }
 };
+
+// Captured ADI runs kept per handle (least recently used evicted beyond this).
+constexpr size_t kAdiGraphCap = 16;
 
 }  // namespace
 
 struct trid_handle_s {
     hipStream_t stream = nullptr;
     hipStream_t capture_stream = nullptr;
+    bool used = false;                // work has been enqueued on `stream`
+    hipEvent_t order_ev = nullptr;    // orders work across a stream switch
     std::string err;
     void *ws = nullptr;
     size_t ws_bytes = 0;
-    std::map<GraphKey, hipGraphExec_t> graphs;
+    trid::LruMap<GraphKey, hipGraphExec_t> graphs{kAdiGraphCap};
     trid::ExtState ext;  // state of the extension entry points (refine, varlen, adjoint, plans)
 };
 
@@ -98,7 +108,10 @@ int check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, int64_t
 
 int run_long_lines(trid_handle_t h, const trid::LineReq &r);
 
+void drop_adi_graph(const GraphKey &k, hipGraphExec_t g) { trid::destroy_graph_exec(g, k.stream); }
+
 int run_lines(trid_handle_t h, const trid::LineReq &r) {
+    h->used = true;
     if (r.n > TRID_MAX_LINE) return run_long_lines(h, r);
     trid::LinePlan pl;
     std::string msg;
@@ -127,7 +140,12 @@ int run_lines(trid_handle_t h, const trid::LineReq &r) {
 
 namespace trid {
 
-hipStream_t handle_stream(trid_handle_t h) { return h->stream; }
+hipStream_t handle_stream(trid_handle_t h) {
+    h->used = true;  // every caller of this enqueues work on the stream
+    return h->stream;
+}
+size_t handle_adi_graphs(trid_handle_t h) { return h->graphs.size(); }
+size_t handle_adi_graph_cap() { return kAdiGraphCap; }
 ExtState &handle_ext(trid_handle_t h) { return h->ext; }
 int handle_fail(trid_handle_t h, int code, const std::string &msg) { return fail(h, code, msg); }
 int handle_hip_fail(trid_handle_t h, hipError_t e, const char *what) { return hip_fail(h, e, what); }
@@ -149,8 +167,7 @@ int handle_workspace(trid_handle_t h, size_t bytes, void **ptr) {
         if (h->ws) {
             hipError_t e = hipStreamSynchronize(h->stream);
             if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
-            for (auto &kv : h->graphs) hipGraphExecDestroy(kv.second);
-            h->graphs.clear();
+            h->graphs.clear(drop_adi_graph);
             hipFree(h->ws);
             h->ws = nullptr;
             h->ws_bytes = 0;
@@ -173,6 +190,7 @@ namespace {
 // Contiguous lines longer than TRID_MAX_LINE: chunk pass, reduced lines, solve
 // pass, with the reduced rows in the handle's workspace.
 int run_long_lines(trid_handle_t h, const trid::LineReq &r) {
+    h->used = true;
     void *ws = nullptr;
     int rc = trid::handle_workspace(h, trid::long_lines_workspace(r), &ws);
     if (rc) return rc;
@@ -191,7 +209,7 @@ int run_long_lines(trid_handle_t h, const trid::LineReq &r) {
 
 extern "C" {
 
-int trid_version(void) { return 10000; }
+int trid_version(void) { return 10100; }
 
 int trid_create(trid_handle_t *h) {
     if (!h) {
@@ -220,20 +238,45 @@ int trid_destroy(trid_handle_t h) {
     if (!h) return TRID_OK;
     if (const char *path = getenv("TRID_PLAN_CACHE"))
         if (!h->ext.tuned.empty()) trid_plan_save(h, path);
-    if (h->ws || !h->graphs.empty() || h->capture_stream || h->ext.has_device_state()) {
+    if (h->ws || h->graphs.size() || h->capture_stream || h->ext.has_device_state()) {
         hipStreamSynchronize(h->stream);
-        for (auto &kv : h->graphs) hipGraphExecDestroy(kv.second);
+        h->graphs.clear(drop_adi_graph);
         h->ext.release();
         if (h->ws) hipFree(h->ws);
         if (h->capture_stream) hipStreamDestroy(h->capture_stream);
     }
+    if (h->order_ev) hipEventDestroy(h->order_ev);
     delete h;
     return TRID_OK;
 }
 
 int trid_set_stream(trid_handle_t h, trid_stream_t stream) {
     if (!h) return TRID_ERR_ARG;
-    h->stream = static_cast<hipStream_t>(stream);
+    hipStream_t ns = static_cast<hipStream_t>(stream);
+    if (ns == h->stream) return TRID_OK;
+    if (h->used) {
+        // The handle's workspace, work counters and schedules are shared by its
+        // calls: work enqueued on the new stream waits for the work already
+        // enqueued on the old one, so calls of one handle never overlap.  (Not
+        // possible across a graph capture; a capturing caller keeps one stream.)
+        hipStreamCaptureStatus c0 = hipStreamCaptureStatusNone, c1 = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(h->stream, &c0);
+        if (e == hipSuccess) e = hipStreamIsCapturing(ns, &c1);
+        if (e != hipSuccess) return hip_fail(h, e, "hipStreamIsCapturing");
+        if (c0 == hipStreamCaptureStatusNone && c1 == hipStreamCaptureStatusNone) {
+            if (!h->order_ev) {
+                e = hipEventCreateWithFlags(&h->order_ev, hipEventDisableTiming);
+                if (e != hipSuccess) {
+                    h->order_ev = nullptr;
+                    return hip_fail(h, e, "hipEventCreate");
+                }
+            }
+            e = hipEventRecord(h->order_ev, h->stream);
+            if (e == hipSuccess) e = hipStreamWaitEvent(ns, h->order_ev, 0);
+            if (e != hipSuccess) return hip_fail(h, e, "stream switch ordering");
+        }
+    }
+    h->stream = ns;
     return TRID_OK;
 }
 
@@ -379,6 +422,7 @@ int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, doub
         if (rc) return rc;
     }
     if (nsteps == 0) return TRID_OK;
+    h->used = true;
     const bool f64 = dt == TRID_F64;
     const i64 nx = dims[0], ny = dims[1], nz = ndim == 3 ? dims[2] : 1;
     if (ndim == 2 && !(flags & TRID_ADI_STREAM)) {
@@ -408,9 +452,10 @@ int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, doub
         if (rc == TRID_OK) h->err.clear();
         return rc;
     }
-    GraphKey key{u, s, s ? 0.0 : s0, (int)dt, ndim, nx, ny, nz, batch, nsteps, h->stream};
-    auto it = h->graphs.find(key);
-    if (it == h->graphs.end()) {
+    GraphKey key{u, s, s ? 0.0 : s0, (int)dt, ndim, nx, ny, nz, batch, nsteps, h->ext.force_M, h->ext.force_L,
+                 h->stream};
+    hipGraphExec_t *it = h->graphs.find(key);
+    if (!it) {
         hipError_t e;
         if (!h->capture_stream) {
             e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
@@ -433,9 +478,9 @@ int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, doub
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         hipGraphDestroy(graph);
         if (e != hipSuccess) return hip_fail(h, e, "hipGraphInstantiate");
-        it = h->graphs.emplace(key, exec).first;
+        it = h->graphs.insert(key, exec, drop_adi_graph);
     }
-    hipError_t e = hipGraphLaunch(it->second, h->stream);
+    hipError_t e = hipGraphLaunch(*it, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
     h->err.clear();
     return TRID_OK;

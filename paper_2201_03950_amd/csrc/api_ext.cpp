@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -36,11 +37,10 @@ void ExtState::release() {
     if (ws2) hipFree(ws2);
     ws2 = nullptr;
     ws2_bytes = 0;
-    for (auto &kv : varlen) {
-        varlen_free(kv.second);
-        delete kv.second;
-    }
-    varlen.clear();
+    varlen.clear([](const std::string &, VarlenSchedule *sc) {
+        varlen_free(sc);
+        delete sc;
+    });
     if (capture_stream) hipStreamDestroy(capture_stream);
     capture_stream = nullptr;
 }
@@ -320,8 +320,8 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
     hipStream_t st = trid::handle_stream(h);
     const int p = (int)prec;
     const std::string skey = varlen_sched_key(off, nsys, p);
-    auto it = xs.varlen.find(skey);
-    if (it == xs.varlen.end()) {
+    trid::VarlenSchedule **found = xs.varlen.find(skey);
+    if (!found) {
         const std::string pkey = varlen_plan_key(off, nsys, p);
         std::vector<trid::VarlenVariant> cands;
         for (const auto &v : trid::varlen_variants(p))
@@ -345,6 +345,16 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
         const bool tune = autotune_requested() && plans.size() > 1;
         trid::VarlenSchedule *best = nullptr;
         if (tune) {
+            // Candidates are timed on this call's inputs.  Each timing runs the
+            // solve several times; when x is d (an in-place solve), a repeated
+            // run would solve again with its own output, so the timed runs then
+            // write a workspace array instead, and the real solve follows once.
+            void *xt = x;
+            if (x == d) {
+                const size_t bytes = (size_t)off[nsys] * (p == 1 ? sizeof(float) : sizeof(double));
+                int rc = trid::handle_workspace2(h, bytes, &xt);
+                if (rc) return rc;
+            }
             bool best_split = false;
             // rank the plans by the model, time the best few
             std::vector<double> pred(plans.size());
@@ -372,7 +382,7 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
                 auto *sc = new trid::VarlenSchedule();
                 hipError_t e = trid::varlen_build(off, nsys, p, pl.v, sc, pl.split ? &small : nullptr);
                 float us = 0.f;
-                if (e == hipSuccess) e = time_schedule(*sc, a, b, c, d, x, st, &us);
+                if (e == hipSuccess) e = time_schedule(*sc, a, b, c, d, xt, st, &us);
                 if (e != hipSuccess) {
                     trid::varlen_free(sc);
                     delete sc;
@@ -417,14 +427,19 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
                 return trid::handle_hip_fail(h, e, "uneven batch: schedule");
             }
         }
-        it = xs.varlen.emplace(skey, best).first;
+        // an evicted schedule may still be in use by work on the stream
+        found = xs.varlen.insert(skey, best, [&](const std::string &, trid::VarlenSchedule *old) {
+            (void)hipStreamSynchronize(st);
+            trid::varlen_free(old);
+            delete old;
+        });
     }
-    trid::VarlenSchedule &sc = *it->second;
+    trid::VarlenSchedule &sc = **found;
     // one persistent launch, replayed from a captured graph per (pointers, stream)
-    auto gkey = std::make_tuple(a, b, c, d, x, st);
-    auto git = sc.graphs.find(gkey);
+    const trid::VarlenSchedule::GraphKey gkey = std::make_tuple(a, b, c, d, x, st);
+    hipGraphExec_t *git = sc.graphs.find(gkey);
     hipError_t e;
-    if (git == sc.graphs.end()) {
+    if (!git) {
         if (!xs.capture_stream) {
             e = hipStreamCreateWithFlags(&xs.capture_stream, hipStreamNonBlocking);
             if (e != hipSuccess) {
@@ -445,10 +460,47 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         hipGraphDestroy(graph);
         if (e != hipSuccess) return trid::handle_hip_fail(h, e, "hipGraphInstantiate");
-        git = sc.graphs.emplace(gkey, exec).first;
+        git = sc.graphs.insert(gkey, exec, [](const trid::VarlenSchedule::GraphKey &k, hipGraphExec_t g) {
+            trid::destroy_graph_exec(g, std::get<5>(k));
+        });
     }
-    e = xs.timer.time_recorded("varlen", st, [&] { return hipGraphLaunch(git->second, st); });
+    e = xs.timer.time_recorded("varlen", st, [&] { return hipGraphLaunch(*git, st); });
     if (e != hipSuccess) return trid::handle_hip_fail(h, e, "uneven batch: launch");
+    return TRID_OK;
+}
+
+int trid_gtsv_varlen_dev(trid_handle_t h, trid_prec_t prec, const void *a, const void *b, const void *c,
+                         const void *d, void *x, const int64_t *offsets_dev, int64_t nsys) {
+    if (!h) return TRID_ERR_ARG;
+    if (!offsets_dev) return trid::handle_fail(h, TRID_ERR_ARG, "NULL pointer");
+    if (nsys < 1 || nsys > ((int64_t)1 << 30)) return trid::handle_fail(h, TRID_ERR_ARG, "nsys out of range");
+    if (prec != TRID_PREC_F64 && prec != TRID_PREC_F32 && prec != TRID_PREC_F32_REFINE64)
+        return trid::handle_fail(h, TRID_ERR_ARG, "bad precision");
+    if (!a || !b || !c || !d || !x) return trid::handle_fail(h, TRID_ERR_ARG, "NULL pointer");
+    // the schedule is built and looked up on the host: read the offsets after
+    // the work already enqueued on the stream (which may have written them)
+    std::vector<int64_t> off((size_t)nsys + 1);
+    hipStream_t st = trid::handle_stream(h);
+    hipError_t e = hipMemcpyAsync(off.data(), offsets_dev, off.size() * sizeof(int64_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return trid::handle_hip_fail(h, e, "uneven batch: reading the offsets");
+    return trid_gtsv_varlen(h, prec, a, b, c, d, x, off.data(), nsys);
+}
+
+int trid_cache_report(trid_handle_t h, char *buf, size_t len) {
+    if (!h) return TRID_ERR_ARG;
+    if (!buf || len < 2) return trid::handle_fail(h, TRID_ERR_ARG, "buffer too small");
+    trid::ExtState &xs = trid::handle_ext(h);
+    size_t vgraphs = 0;
+    xs.varlen.for_each([&](const std::string &, trid::VarlenSchedule *sc) { vgraphs += sc->graphs.size(); });
+    char out[320];
+    const int nw = snprintf(out, sizeof out,
+                            "{\"adi_graphs\": %zu, \"adi_graph_cap\": %zu, \"varlen_schedules\": %zu, "
+                            "\"varlen_schedule_cap\": %zu, \"varlen_graphs\": %zu, \"varlen_graph_cap\": %zu}",
+                            trid::handle_adi_graphs(h), trid::handle_adi_graph_cap(), xs.varlen.size(), xs.varlen.cap,
+                            vgraphs, trid::VarlenSchedule().graphs.cap);
+    if (nw < 0 || (size_t)nw + 1 > len) return trid::handle_fail(h, TRID_ERR_ARG, "buffer too small");
+    std::memcpy(buf, out, (size_t)nw + 1);
     return TRID_OK;
 }
 
@@ -665,19 +717,36 @@ int trid_hv_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *a, const
     return TRID_OK;
 }
 
-int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s, void *u_bar,
+int trid_adi_step_adjoint(trid_handle_t h, trid_dtype_t dt, const void *u_t, const void *s, double s0, void *u_bar,
                           void *s_bar, int ndim, const int64_t *dims, int64_t batch) {
     if (!h) return TRID_ERR_ARG;
-    if (!u_t || !s || !u_bar || !s_bar) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    if (!u_t || !u_bar) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
+    if (!s && !(std::fabs(s0) <= 1e300)) return trid::handle_fail(h, TRID_ERR_ARG, "s0 must be finite");
     AdiGeom g;
     int rc = adi_geom(h, dt, ndim, dims, batch, &g);
     if (rc) return rc;
     const size_t slot = (g.bytes + 255) & ~(size_t)255;
+    // W[1..3]: forward outputs, W[4]: lambda, then the constant s (s NULL) and
+    // the discarded s gradient (s_bar NULL)
+    const int nslots = 4 + (s ? 0 : 1) + (s_bar ? 0 : 1);
     void *ws = nullptr;
-    rc = trid::handle_workspace2(h, 4 * slot, &ws);
+    rc = trid::handle_workspace2(h, nslots * slot, &ws);
     if (rc) return rc;
     char *wb = static_cast<char *>(ws);
-    void *W[5] = {nullptr, wb, wb + slot, wb + 2 * slot, wb + 3 * slot};  // W[1..3]: forward outputs, W[4]: lambda
+    void *W[5] = {nullptr, wb, wb + slot, wb + 2 * slot, wb + 3 * slot};
+    int next = 4;
+    if (!s) {
+        // the constant diffusion number as a per-point array: the reverse pass
+        // then returns dL/ds_i at s = s0 for every point (their sum is dL/ds0)
+        void *sc = wb + (next++) * slot;
+        const trid::i64 pts = g.nx * g.ny * g.nz * g.batch;
+        hipError_t e = trid::handle_ext(h).timer.time("adj_fill_s", trid::handle_stream(h), [&] {
+            return trid::launch_fill(sc, g.f64, s0, pts, trid::handle_stream(h));
+        });
+        if (e != hipSuccess) return trid::handle_hip_fail(h, e, "ADI adjoint: fill launch");
+        s = sc;
+    }
+    if (!s_bar) s_bar = wb + (next++) * slot;
     // recompute the forward step from the checkpoint: W1 = X^-1 (2 s L u_t), W[k+1] = A_k^-1 W[k]
     const char *names[3] = {"adj_rhs_x", "adj_fwd_solve", "adj_fwd_solve"};
     rc = adi_forward_parts(h, g, u_t, s, W, nullptr, names);

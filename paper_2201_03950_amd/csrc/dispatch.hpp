@@ -123,4 +123,7 @@ struct StencilAdjReq {
 };
 hipError_t launch_stencil_adjoint(const StencilAdjReq &r, hipStream_t s);
 
+// p[0..n) = v in dtype FP64 (f64) or FP32.
+hipError_t launch_fill(void *p, bool f64, double v, i64 n, hipStream_t s);
+
 }  // namespace trid

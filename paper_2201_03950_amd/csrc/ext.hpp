@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "dispatch.hpp"
+#include "graph_cache.hpp"
 
 typedef struct trid_handle_s *trid_handle_t;
 
@@ -119,8 +120,9 @@ struct ExtState {
     int force_L = 0;  // forced lines per block (0: automatic)
     // tuned plans: key -> plan
     std::map<std::string, TunedPlan> tuned;
-    // uneven-batch schedules keyed by a hash of the offsets
-    std::map<std::string, VarlenSchedule *> varlen;
+    // uneven-batch schedules keyed by a hash of the offsets (least recently
+    // used evicted beyond the capacity)
+    LruMap<std::string, VarlenSchedule *> varlen{32};
     std::vector<TuneRecord> last_tune;  // the most recent autotuning run
     // scratch for adjoint / refinement entry points
     void *ws2 = nullptr;
@@ -137,7 +139,7 @@ struct ExtState {
         if (force_L) r->force_L = force_L;
     }
     bool has_device_state() const {
-        return ws2 != nullptr || !varlen.empty() || !timer.pool.empty() || !timer.pending.empty() ||
+        return ws2 != nullptr || varlen.size() || !timer.pool.empty() || !timer.pending.empty() ||
                capture_stream != nullptr;
     }
     void release();
@@ -153,5 +155,7 @@ int handle_run_lines(trid_handle_t h, const LineReq &r);
 int handle_workspace(trid_handle_t h, size_t bytes, void **ptr);
 bool alloc_failure_forced();  // TRID_FAIL_ALLOC is set: workspace allocations fail
 int handle_workspace2(trid_handle_t h, size_t bytes, void **ptr);
+size_t handle_adi_graphs(trid_handle_t h);  // captured ADI runs held by the handle
+size_t handle_adi_graph_cap();              // and their maximum number
 
 }  // namespace trid

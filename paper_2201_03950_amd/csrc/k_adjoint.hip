@@ -75,4 +75,21 @@ hipError_t launch_stencil_adjoint(const StencilAdjReq &r, hipStream_t st) {
     return r.ndim == 3 ? go<float, 3>(r, st) : go<float, 2>(r, st);
 }
 
+// p[0..n) = v (grid-stride loop).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T *__restrict__ p, T v, i64 n) {
+    const i64 step = (i64)gridDim.x * 256;
+    for (i64 k = (i64)blockIdx.x * 256 + threadIdx.x; k < n; k += step) p[k] = v;
+}
+
+hipError_t launch_fill(void *p, bool f64, double v, i64 n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)std::min<i64>((n + 255) / 256, 1 << 16);
+    if (f64)
+        launch(k_fill<double>, dim3(nb), dim3(256), 0, st, static_cast<double *>(p), v, n);
+    else
+        launch(k_fill<float>, dim3(nb), dim3(256), 0, st, static_cast<float *>(p), (float)v, n);
+    return hipGetLastError();
+}
+
 }  // namespace trid

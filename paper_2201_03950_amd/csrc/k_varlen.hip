@@ -530,8 +530,9 @@ hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b,
 }
 
 void varlen_free(VarlenSchedule *sc) {
-    for (auto &kv : sc->graphs) (void)hipGraphExecDestroy(kv.second);
-    sc->graphs.clear();
+    sc->graphs.clear([](const VarlenSchedule::GraphKey &k, hipGraphExec_t g) {
+        destroy_graph_exec(g, std::get<5>(k));
+    });
     if (sc->dev) (void)hipFree(sc->dev);
     sc->dev = nullptr;
     if (sc->next) {

@@ -8,6 +8,8 @@
 #include <tuple>
 #include <vector>
 
+#include "graph_cache.hpp"
+
 namespace trid {
 
 using i64 = int64_t;
@@ -33,10 +35,10 @@ struct VarlenSchedule {
     // split schedule: the systems too long for a small-block variant run in
     // this launch, the rest in `next` (launched right after, same arrays)
     VarlenSchedule *next = nullptr;
-    // captured launches keyed by (a, b, c, d, x, stream)
-    std::map<std::tuple<const void *, const void *, const void *, const void *, void *, hipStream_t>,
-             hipGraphExec_t>
-        graphs;
+    // captured launches keyed by (a, b, c, d, x, stream), least recently used
+    // evicted beyond the capacity
+    using GraphKey = std::tuple<const void *, const void *, const void *, const void *, void *, hipStream_t>;
+    LruMap<GraphKey, hipGraphExec_t> graphs{8};
 };
 
 const std::vector<VarlenVariant> &varlen_variants(int prec);

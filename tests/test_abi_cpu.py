@@ -139,14 +139,40 @@ def test_varlen_argument_checks(lib, h):
     assert lib.trid_gtsv_varlen(h, 9, FAKE, FAKE, FAKE, FAKE, FAKE, off, 1) == 1  # bad precision
     assert lib.trid_gtsv_varlen(h, 2, FAKE, FAKE, FAKE, FAKE, FAKE, off, 1) == 1  # x aliases d (refine)
     assert lib.trid_gtsv_varlen(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, None, 1) == 1
+    # device offsets: checked before the offsets are read
+    assert lib.trid_gtsv_varlen_dev(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, None, 1) == 1
+    assert lib.trid_gtsv_varlen_dev(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 0) == 1  # nsys
+    assert lib.trid_gtsv_varlen_dev(h, 9, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1) == 1  # precision
+    assert lib.trid_gtsv_varlen_dev(h, 0, None, FAKE, FAKE, FAKE, FAKE, FAKE, 1) == 1
+    assert lib.trid_gtsv_varlen_dev(None, 0, FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 1) == 1
+
+
+def test_cache_report(lib, h):
+    """A new handle holds no captured graphs or schedules; the caps are positive."""
+    import json
+
+    buf = ctypes.create_string_buffer(512)
+    assert lib.trid_cache_report(h, buf, len(buf)) == 0
+    rep = json.loads(buf.value.decode())
+    assert rep["adi_graphs"] == rep["varlen_schedules"] == rep["varlen_graphs"] == 0
+    assert min(rep["adi_graph_cap"], rep["varlen_schedule_cap"], rep["varlen_graph_cap"]) > 0
+    assert lib.trid_cache_report(h, buf, 8) == 1  # too small
+    assert lib.trid_cache_report(h, None, 64) == 1
+    assert lib.trid_cache_report(None, buf, len(buf)) == 1
 
 
 def test_refine_and_adjoint_argument_checks(lib, h):
     d = _dims(8, 8)
     assert lib.trid_gtsv_batched_refine(h, 1, FAKE, FAKE, FAKE, FAKE, FAKE, 2, d, 0, 1) == 1  # x aliases d
     assert lib.trid_gtsv_batched_s_refine(h, 5, FAKE, FAKE, ctypes.c_void_p(0x2000), 2, d, 0, 1) == 1
-    assert lib.trid_adi_step_adjoint(h, 1, FAKE, None, FAKE, FAKE, 3, _dims(8, 8, 8), 1) == 1
-    assert lib.trid_adi_step_adjoint(h, 1, FAKE, FAKE, FAKE, FAKE, 1, _dims(8), 1) == 1
+    assert lib.trid_adi_step_adjoint(h, 1, None, FAKE, 0.2, FAKE, FAKE, 3, _dims(8, 8, 8), 1) == 1  # no u_t
+    assert lib.trid_adi_step_adjoint(h, 1, FAKE, FAKE, 0.2, None, FAKE, 3, _dims(8, 8, 8), 1) == 1  # no u_bar
+    assert lib.trid_adi_step_adjoint(h, 1, FAKE, FAKE, 0.2, FAKE, FAKE, 1, _dims(8), 1) == 1
+    # constant s (s NULL) needs a finite s0
+    assert lib.trid_adi_step_adjoint(h, 1, FAKE, None, float("nan"), FAKE, FAKE, 3, _dims(8, 8, 8), 1) == 1
+    assert lib.trid_adi_step_adjoint(h, 1, FAKE, None, float("inf"), FAKE, None, 3, _dims(8, 8, 8), 1) == 1
+    assert b"s0" in lib.trid_last_error(h)
+    assert lib.trid_adi_step_adjoint(h, 7, FAKE, None, 0.2, FAKE, None, 3, _dims(8, 8, 8), 1) == 1  # dtype
     assert lib.trid_adi_step_keep(h, 1, FAKE, FAKE, 3, _dims(8, 8, 8), 1, FAKE, FAKE, None) == 1  # 3D needs w3
     assert lib.trid_adi_step_keep(h, 1, FAKE, None, 3, _dims(8, 8, 8), 1, FAKE, FAKE, FAKE) == 1
     assert lib.trid_adi_step_keep(h, 1, FAKE, FAKE, 1, _dims(8), 1, FAKE, FAKE, None) == 1

@@ -150,3 +150,29 @@ def test_kept_step_argument_checks(trid):
         trid.adi_step_keep(u, s, w, w, torch.empty_like(u))  # aliasing intermediates
     with pytest.raises(trid.TridError):
         trid.adi_step_keep(u, s, u, torch.empty_like(u), torch.empty_like(u))  # w1 aliases u
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("dims,batch", [((20, 17, 13), 2), ((41, 30), 3), ((33, 9, 40), 1)])
+def test_adi_step_adjoint_constant_s_matches_oracle(trid, orc, dt, dims, batch):
+    """s NULL: the step with the constant s0; s_bar receives dL/ds_i at s = s0
+    (the oracle's per-point gradient with every s_i = s0), s_bar NULL skips it."""
+    rng = np.random.default_rng(5 + sum(dims))
+    shape = gen.mesh_shape(dims, batch)
+    s0 = float(dt(0.2))  # the value the FP32 path computes with
+    u = rng.uniform(0, 1, shape).astype(dt)
+    ubar = rng.standard_normal(shape).astype(dt)
+    sbar0 = rng.standard_normal(shape).astype(dt)
+    ub_ref, sb_ref = orc.adi_step_adjoint(u, np.full(shape, s0), ubar, sbar0)
+    tub, tsb = _t(ubar), _t(sbar0)
+    trid.adi_step_adjoint(_t(u), None, tub, tsb, s0=s0)
+    tol = 1e-11 if dt == np.float64 else 1e-5
+    assert _nerr(tub.cpu().numpy().astype(np.float64), ub_ref) <= tol
+    assert _nerr(tsb.cpu().numpy().astype(np.float64), sb_ref) <= tol
+    tub2 = _t(ubar)
+    trid.adi_step_adjoint(_t(u), None, tub2, None, s0=s0)
+    assert torch.equal(tub, tub2)
+    # the constant step's own reverse equals the per-point one with s = s0 everywhere
+    tub3, tsb3 = _t(ubar), _t(sbar0)
+    trid.adi_step_adjoint(_t(u), _t(np.full(shape, s0, dtype=dt)), tub3, tsb3)
+    assert torch.equal(tub, tub3) and torch.equal(tsb, tsb3)

@@ -178,3 +178,51 @@ def test_varlen_autotune_pruned_by_the_model(trid, orc, monkeypatch, top):
     assert len(timed) == (len(rep) if top == 0 else min(top, len(rep)))
     assert timed == rep[:len(timed)]
     assert _sys_err(x.cpu().numpy(), ref, off) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_varlen_autotune_in_place(trid, orc, monkeypatch, prec):
+    """With autotuning, the candidate timings must not run on an in-place call's
+    own output: x = d still returns A^{-1} d."""
+    a32, b32, c32, d64, off = gen.varlen_batch(1200, 32, 4096, seed=131 if prec == "f64" else 132)
+    p = trid.PREC_F64 if prec == "f64" else trid.PREC_F32
+    d_in = d64.astype(np.float32).astype(np.float64) if prec == "f32" else d64
+    ref = orc.gtsv_varlen(a32, b32, c32, d_in, off)
+    a, b, c, d, _ = _run(trid, p, a32, b32, c32, d64)
+    monkeypatch.setenv("TRID_AUTOTUNE", "1")
+    monkeypatch.setenv("TRID_AUTOTUNE_TOP", "3")
+    trid.gtsv_varlen(p, a, b, c, d, d, off)
+    assert any(q["meas_us"] >= 0 for q in trid.autotune_report())  # the call did tune
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert _sys_err(d.cpu().numpy().astype(np.float64), ref, off) <= tol
+
+
+@pytest.mark.parametrize("prec", ["f64", "refine"])
+def test_varlen_device_offsets(trid, orc, prec):
+    """Offsets in device memory give the same result as the host offsets (same schedule)."""
+    a32, b32, c32, d64, off = gen.varlen_batch(700, 1, 3000, seed=133)
+    p = trid.PREC_F64 if prec == "f64" else trid.PREC_F32_REFINE64
+    ref = orc.gtsv_varlen(a32, b32, c32, d64, off)
+    a, b, c, d, x = _run(trid, p, a32, b32, c32, d64)
+    trid.gtsv_varlen(p, a, b, c, d, x, off)
+    x2 = torch.zeros_like(x)
+    trid.gtsv_varlen_dev(p, a, b, c, d, x2, _t(off))
+    assert torch.equal(x, x2)
+    assert _sys_err(x2.cpu().numpy(), ref, off) <= (1e-12 if prec == "f64" else 1e-9)
+
+
+def test_varlen_two_streams_share_one_schedule(trid, orc):
+    """Calls of one handle on two streams share the schedule's work counter; the
+    stream switch orders them, so both solves are complete."""
+    a32, b32, c32, d64, off = gen.varlen_batch(4000, 32, 8192, seed=134)
+    ref = orc.gtsv_varlen(a32, b32, c32, d64, off)
+    a, b, c, d, x = _run(trid, trid.PREC_F64, a32, b32, c32, d64)
+    xs = [torch.zeros_like(x) for _ in range(4)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    for k, xk in enumerate(xs):
+        with torch.cuda.stream(streams[k % 2]):
+            trid.gtsv_varlen(trid.PREC_F64, a, b, c, d, xk, off)
+    torch.cuda.synchronize()
+    for xk in xs:
+        assert _sys_err(xk.cpu().numpy(), ref, off) <= 1e-12
