@@ -227,6 +227,28 @@ int trid_gtsv_varlen_dev(trid_handle_t h, trid_prec_t p, const void *a, const vo
 int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, double s0, int ndim,
                   const int64_t *dims, int64_t batch, int nsteps, unsigned flags);
 
+/* Size of the device array that trid_adi_step_noalloc uses as its workspace
+ * (one mesh-sized array of the step's dtype must fit). */
+#define TRID_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* trid_adi_step for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same steps with the same kernels, but the d workspace is a statically sized
+ * device array of TRID_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends, instead of the handle's allocated
+ * workspace; the call makes no hipMalloc / hipFree and records no events.
+ * Meshes whose d array (points x dtype size) exceeds that size are
+ * TRID_ERR_UNSUPPORTED; 2D meshes that take the LDS-resident loop need no
+ * workspace at all.  flags: 0 or TRID_ADI_STREAM (TRID_ADI_GRAPH is
+ * TRID_ERR_ARG: instantiating a graph allocates; a caller may capture this
+ * call into its own graph instead).  Every call on one GPU, from any handle or
+ * thread, uses that GPU's one array: calls that overlap in time on one GPU
+ * race and give wrong results; serialise them (one stream, or events).
+ * Nothing in the array needs to start at zero: each step writes it before
+ * reading it.  Errors: as trid_adi_step. */
+int trid_adi_step_noalloc(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, double s0, int ndim,
+                          const int64_t *dims, int64_t batch, int nsteps, unsigned flags);
+
 /* `nsteps` Hundsdorfer-Verwer ADI steps of u_t = a u_xx + b u_yy + c u_xy in
  * place on u: the synthetic stand-in for the call structure of the SLV
  * application (Alg. 4, Section V): explicit predictor stencils alternating

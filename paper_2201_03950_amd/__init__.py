@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     adi_step_adjoint,
     adi_step_adjoint_kept,
     adi_step_keep,
+    adi_step_noalloc,
     gtsv,
     gtsv_adjoint,
     gtsv_const,

@@ -48,6 +48,7 @@ SIGNATURES = {
     "trid_gtsv_varlen": ([_H, _I, _P, _P, _P, _P, _P, _I64P, _I64], _I),
     "trid_gtsv_varlen_dev": ([_H, _I, _P, _P, _P, _P, _P, _P, _I64], _I),
     "trid_adi_step": ([_H, _I, _P, _P, _D, _I, _I64P, _I64, _I, ctypes.c_uint], _I),
+    "trid_adi_step_noalloc": ([_H, _I, _P, _P, _D, _I, _I64P, _I64, _I, ctypes.c_uint], _I),
     "trid_gtsv_batched_adjoint": ([_H, _I, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_s_adjoint": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_model_gtsv": ([_H, _I, _I, _I, _I64P, _I, _I64, ctypes.POINTER(ctypes.c_double), ctypes.c_char_p,
@@ -329,6 +330,20 @@ def adi_step(u, s=None, s0=0.0, nsteps=1, graph=False, stream=False):
     _check(lib.trid_adi_step(h, _dtype_code(u), u.data_ptr(), s.data_ptr() if s is not None else None,
                              float(s0), nd, dims, batch, int(nsteps),
                              (TRID_ADI_GRAPH if graph else 0) | (TRID_ADI_STREAM if stream else 0)), h)
+    return u
+
+
+def adi_step_noalloc(u, s=None, s0=0.0, nsteps=1, stream=False):
+    """As adi_step, with the workspace in the library's static device scratch
+    (no device allocation; meshes up to TRID_NOALLOC_SCRATCH_BYTES of d)."""
+    _dev(u, s)
+    _same(u, s)
+    h = handle()
+    lib = _prep(h)
+    nd, dims, batch = _mesh(u)
+    _check(lib.trid_adi_step_noalloc(h, _dtype_code(u), u.data_ptr(), s.data_ptr() if s is not None else None,
+                                     float(s0), nd, dims, batch, int(nsteps),
+                                     TRID_ADI_STREAM if stream else 0), h)
     return u
 
 

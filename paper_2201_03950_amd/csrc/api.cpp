@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -339,7 +340,8 @@ int trid_gtsv_batched_s(trid_handle_t h, trid_dtype_t dt, const void *s, void *d
 
 // Enqueue the launches of `nsteps` ADI steps on stream `st`.
 static int adi_enqueue(trid_handle_t h, bool f64, void *u, const void *s, double s0, int ndim,
-                       i64 nx, i64 ny, i64 nz, i64 batch, int nsteps, void *dws, hipStream_t st) {
+                       i64 nx, i64 ny, i64 nz, i64 batch, int nsteps, void *dws, hipStream_t st,
+                       bool timed = true) {
     trid::AdiReq ar;
     ar.f64 = f64;
     ar.ndim = ndim;
@@ -394,7 +396,7 @@ static int adi_enqueue(trid_handle_t h, bool f64, void *u, const void *s, double
         return cmz ? trid::launch_const_lines(rz, cmz, st) : trid::launch_lines(rz, pz, st);
     };
     trid::KernelTimer notimer;  // graph capture records no events
-    trid::KernelTimer &tm = (st == h->stream) ? h->ext.timer : notimer;
+    trid::KernelTimer &tm = (timed && st == h->stream) ? h->ext.timer : notimer;
     for (int it = 0; it < nsteps; ++it) {
         hipError_t e = tm.time("adi_stencil_x", st, run_x);
         if (e != hipSuccess) return hip_fail(h, e, "stencil + x-solve launch");
@@ -487,3 +489,87 @@ int trid_adi_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, doub
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------ no-allocation step --
+//
+// The mesh-sized d workspace of the per-step ADI kernels lives, for
+// trid_adi_step_noalloc, in this statically sized device array: each GPU the
+// library runs on holds its own copy from module load until the process ends.
+// In host code `scratch` names a host-side stand-in, not a device address, so
+// the address is looked up once per device (hipGetSymbolAddress, with that
+// device current) and only that looked-up address is ever passed to kernels.
+static __device__ __align__(256) unsigned char scratch[TRID_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the first
+// call on that device).
+int noalloc_scratch(trid_handle_t h, void **ptr) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(h, TRID_ERR_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(h, e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return TRID_OK;
+}
+
+}  // namespace
+
+extern "C" int trid_adi_step_noalloc(trid_handle_t h, trid_dtype_t dt, void *u, const void *s, double s0, int ndim,
+                                     const int64_t *dims, int64_t batch, int nsteps, unsigned flags) {
+    if (!h) return TRID_ERR_ARG;
+    if (!dtype_ok(dt)) return fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!u) return fail(h, TRID_ERR_ARG, "u is NULL");
+    if (ndim != 2 && ndim != 3) return fail(h, TRID_ERR_ARG, "ADI needs ndim 2 or 3");
+    if (nsteps < 0) return fail(h, TRID_ERR_ARG, "nsteps must be >= 0");
+    if (flags & ~(unsigned)TRID_ADI_STREAM)
+        return fail(h, TRID_ERR_ARG, "flags: only TRID_ADI_STREAM (a captured graph would allocate)");
+    i64 inner, n, outer;
+    for (int ax = 0; ax < ndim; ++ax) {
+        int rc = check_mesh(h, ndim, dims, ax, batch, &inner, &n, &outer);
+        if (rc) return rc;
+    }
+    if (nsteps == 0) return TRID_OK;
+    const bool f64 = dt == TRID_F64;
+    const i64 nx = dims[0], ny = dims[1], nz = ndim == 3 ? dims[2] : 1;
+    if (ndim == 2 && !(flags & TRID_ADI_STREAM)) {  // the LDS-resident loop uses no scratch
+        trid::ResidentReq rr;
+        rr.f64 = f64;
+        rr.u = u;
+        rr.s = s;
+        rr.s0 = s0;
+        rr.nx = nx;
+        rr.ny = ny;
+        rr.batch = batch;
+        rr.nsteps = nsteps;
+        if (trid::resident_fits(rr)) {
+            h->used = true;
+            hipError_t e = trid::launch_resident(rr, h->stream);
+            if (e != hipSuccess) return hip_fail(h, e, "resident ADI launch");
+            h->err.clear();
+            return TRID_OK;
+        }
+    }
+    const size_t bytes = (size_t)(nx * ny * nz * batch) * (f64 ? 8 : 4);
+    if (bytes > (size_t)TRID_NOALLOC_SCRATCH_BYTES)
+        return fail(h, TRID_ERR_UNSUPPORTED, "mesh larger than the no-allocation scratch (TRID_NOALLOC_SCRATCH_BYTES)");
+    void *dws = nullptr;
+    int rc = noalloc_scratch(h, &dws);
+    if (rc) return rc;
+    h->used = true;
+    rc = adi_enqueue(h, f64, u, s, s0, ndim, nx, ny, nz, batch, nsteps, dws, h->stream, /*timed=*/false);
+    if (rc == TRID_OK) h->err.clear();
+    return rc;
+}
+

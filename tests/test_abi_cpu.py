@@ -215,6 +215,19 @@ def test_model_and_report_argument_checks(lib, h):
     assert lib.trid_autotune_report(h, None, 64) == 1
 
 
+def test_noalloc_step_argument_checks(lib, h):
+    """Checked on the host before any HIP call: the graph flag (a graph would
+    allocate) and meshes whose d exceeds the static scratch (64 MiB)."""
+    assert lib.trid_adi_step_noalloc(h, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, 1, 1) == 1  # graph flag
+    assert lib.trid_adi_step_noalloc(h, 1, None, None, 0.2, 3, _dims(8, 8, 8), 1, 1, 0) == 1
+    assert lib.trid_adi_step_noalloc(h, 1, FAKE, None, 0.2, 1, _dims(8), 1, 1, 0) == 1
+    assert lib.trid_adi_step_noalloc(h, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, 0, 0) == 0  # no steps
+    assert lib.trid_adi_step_noalloc(h, 1, FAKE, None, 0.2, 3, _dims(256, 256, 129), 1, 1, 0) == 4
+    assert b"scratch" in lib.trid_last_error(h)
+    assert lib.trid_adi_step_noalloc(h, 0, FAKE, None, 0.2, 3, _dims(256, 256, 257), 1, 1, 0) == 4  # FP32
+    assert lib.trid_adi_step_noalloc(None, 1, FAKE, None, 0.2, 3, _dims(8, 8, 8), 1, 1, 0) == 1
+
+
 def test_forced_allocation_failure(lib, h, monkeypatch):
     """TRID_FAIL_ALLOC makes every workspace allocation fail before any HIP call."""
     monkeypatch.setenv("TRID_FAIL_ALLOC", "1")
