@@ -607,6 +607,9 @@ def extra_varlen(trid):
     ta, tb, tc, td = (torch.from_numpy(v).cuda() for v in (a32, b32, c32, d64))
     a64, b64, c64 = (v.double() for v in (ta, tb, tc))
     x64 = torch.empty_like(td)
+    tune = {}
+    trid.gtsv_varlen(trid.PREC_F64, a64, b64, c64, td, x64, off)  # the autotuned first call
+    tune["f64"] = trid.autotune_report()
     trid.timing_enable(True)
     time_calls(lambda: trid.gtsv_varlen(trid.PREC_F64, a64, b64, c64, td, x64, off), 10)
     kt = trid.timing_read()
@@ -616,7 +619,23 @@ def extra_varlen(trid):
     byts = alg_bytes("arrays", 8, rows)
     res["f64"] = {"ms": round(kern * 1e3, 4), "solves_per_s": round((len(off) - 1) / kern, 1),
                   "gbs": round(byts / kern / 1e9, 1), "frac": round(byts / kern / 1e9 / PEAK_GBS, 4)}
+    # plain FP32 (d rounded to FP32)
+    td32 = td.float()
+    x32 = torch.empty_like(td32)
+    trid.gtsv_varlen(trid.PREC_F32, ta, tb, tc, td32, x32, off)
+    tune["f32"] = trid.autotune_report()
+    trid.timing_enable(True)
+    time_calls(lambda: trid.gtsv_varlen(trid.PREC_F32, ta, tb, tc, td32, x32, off), 10)
+    kt = trid.timing_read()
+    trid.timing_enable(False)
+    cnt, ms = kt["varlen"]
+    kern = ms / cnt * 1e-3
+    byts = alg_bytes("arrays", 4, rows)
+    res["f32"] = {"ms": round(kern * 1e3, 4), "solves_per_s": round((len(off) - 1) / kern, 1),
+                  "gbs": round(byts / kern / 1e9, 1), "frac": round(byts / kern / 1e9 / PEAK_GBS, 4)}
     x = torch.empty_like(td)
+    trid.gtsv_varlen(trid.PREC_F32_REFINE64, ta, tb, tc, td, x, off)
+    tune["f32_refine64"] = trid.autotune_report()
     trid.timing_enable(True)
     time_calls(lambda: trid.gtsv_varlen(trid.PREC_F32_REFINE64, ta, tb, tc, td, x, off), 10)
     kt = trid.timing_read()
@@ -630,7 +649,9 @@ def extra_varlen(trid):
     byts = 28 * rows
     res["f32_refine64"] = {"ms": round(kern * 1e3, 4), "solves_per_s": round((len(off) - 1) / kern, 1),
                            "gbs": round(byts / kern / 1e9, 1), "frac": round(byts / kern / 1e9 / PEAK_GBS, 4),
-                           "err_vs_f64_max": float(e.max()), "err_vs_f64_median": float(np.median(e))}
+                           "err_vs_f64_max": float(e.max()), "err_vs_f64_median": float(np.median(e)),
+                           "time_vs_f64": round(kern * 1e3 / res["f64"]["ms"], 3)}
+    res["autotune"] = tune
     with tempfile.TemporaryDirectory() as tmp:  # the autotuned plans
         path = os.path.join(tmp, "plans.json")
         trid.plan_save(path)

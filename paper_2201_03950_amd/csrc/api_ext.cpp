@@ -339,7 +339,7 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
         for (const auto &v : cands) plans.push_back({v, false});
         if (maxlen > (int64_t)small.M * small.NT)
             for (const auto &v : cands)
-                if (v.NT > small.NT) plans.push_back({v, true});
+                if (v.NT > small.NT && !v.wave) plans.push_back({v, true});
         auto tuned = xs.tuned.find(pkey);
         auto tuned_small = xs.tuned.find(pkey + "/small");
         const bool tune = autotune_requested() && plans.size() > 1;
@@ -371,6 +371,7 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
                 tr.M = plans[i].v.M;
                 tr.NT = plans[i].v.NT;
                 tr.thomas = plans[i].v.thomas;
+                tr.wave = plans[i].v.wave;
                 tr.split = plans[i].split ? 1 : 0;
                 tr.blocks = trid::varlen_blocks(p, plans[i].v);
                 tr.blocks_small = plans[i].split ? trid::varlen_blocks(p, small) : 0;
@@ -406,7 +407,7 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
                     delete sc;
                 }
             }
-            xs.tuned[pkey] = {best->M, best->NT, best->thomas};
+            xs.tuned[pkey] = {best->M, best->NT, best->thomas, best->wave};
             if (best_split)
                 xs.tuned[pkey + "/small"] = {small.M, small.NT, small.thomas};
             else
@@ -415,7 +416,8 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
             trid::VarlenVariant v = cands.front();
             if (tuned != xs.tuned.end())
                 for (const auto &c2 : cands)
-                    if (c2.M == tuned->second.M && c2.NT == tuned->second.NT && c2.thomas == tuned->second.thomas)
+                    if (c2.M == tuned->second.M && c2.NT == tuned->second.NT && c2.thomas == tuned->second.thomas &&
+                        c2.wave == tuned->second.wave)
                         v = c2;
             const bool split = tuned_small != xs.tuned.end() && tuned_small->second.M == small.M &&
                                tuned_small->second.NT == small.NT && maxlen > (int64_t)small.M * small.NT;
@@ -824,7 +826,8 @@ int trid_autotune_report(trid_handle_t h, char *buf, size_t len) {
         snprintf(item, sizeof item,
                  "%s{\"M\": %d, \"NT\": %d, \"reduced\": \"%s\", \"split\": %d, \"blocks\": %d, "
                  "\"blocks_small\": %d, \"pred_us\": %.3f, \"meas_us\": %.3f}",
-                 i ? ", " : "", rec[i].M, rec[i].NT, rec[i].thomas ? "thomas" : "pcr", rec[i].split, rec[i].blocks,
+                 i ? ", " : "", rec[i].M, rec[i].NT, rec[i].wave ? "wave" : (rec[i].thomas ? "thomas" : "pcr"),
+                 rec[i].split, rec[i].blocks,
                  rec[i].blocks_small, rec[i].pred_us, rec[i].meas_us);
         o << item;
     }
@@ -853,7 +856,7 @@ int trid_plan_save(trid_handle_t h, const char *path) {
     size_t i = 0;
     for (auto &kv : x.tuned) {
         f << "  \"" << kv.first << "\": {\"M\": " << kv.second.M << ", \"NT\": " << kv.second.NT
-          << ", \"reduced\": \"" << (kv.second.thomas ? "thomas" : "pcr") << "\"}"
+          << ", \"reduced\": \"" << (kv.second.wave ? "wave" : (kv.second.thomas ? "thomas" : "pcr")) << "\"}"
           << (++i < x.tuned.size() ? "," : "") << "\n";
     }
     f << " }\n}\n";
@@ -873,10 +876,12 @@ int trid_plan_load(trid_handle_t h, const char *path) {
         if (mpos == std::string::npos || npos == std::string::npos || q1 == std::string::npos) continue;
         const std::string key = line.substr(q0 + 1, q1 - q0 - 1);
         const int M = std::atoi(line.c_str() + mpos + 4), NT = std::atoi(line.c_str() + npos + 5);
-        // "reduced": "thomas" selects the Thomas reduced solve (absent: PCR)
+        // "reduced": "thomas" selects the Thomas reduced solve, "wave" the
+        // wavefront-level kernels (absent: PCR across the work item)
         const int thomas = line.find("\"thomas\"") != std::string::npos ? 1 : 0;
+        const int wave = line.find("\"wave\"") != std::string::npos ? 1 : 0;
         if (key.rfind("varlen/", 0) != 0 || M <= 0 || NT <= 0) continue;  // unknown keys are ignored
-        x.tuned[key] = {M, NT, thomas};
+        x.tuned[key] = {M, NT, thomas, wave};
     }
     return TRID_OK;
 }

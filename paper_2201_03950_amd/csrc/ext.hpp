@@ -102,15 +102,16 @@ struct KernelTimer {
     }
 };
 
-// A tuned uneven-batch plan: tile rows, threads per work item, reduced solve.
+// A tuned uneven-batch plan: tile rows, threads per work item, reduced solve
+// (thomas), wavefront-level kernel (wave).
 struct TunedPlan {
-    int M = 0, NT = 0, thomas = 0;
+    int M = 0, NT = 0, thomas = 0, wave = 0;
 };
 
 // One plan the uneven-batch autotuner considered: the model's prediction and,
 // when it was among those timed, the measured time (else < 0).
 struct TuneRecord {
-    int M = 0, NT = 0, thomas = 0, split = 0;
+    int M = 0, NT = 0, thomas = 0, split = 0, wave = 0;
     int blocks = 0, blocks_small = 0;  // persistent workgroups of the launch(es)
     double pred_us = 0, meas_us = -1;
 };

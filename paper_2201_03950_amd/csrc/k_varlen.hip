@@ -355,10 +355,13 @@ hipError_t launch_persistent(K kernel, int nt, size_t lds, const VarlenSchedule 
 }  // namespace
 
 // The (M, NT) variants compiled for each precision.
+// The first variant whose tiles hold the longest system is the default plan.
 const std::vector<VarlenVariant> &varlen_variants(int prec) {
-    static const std::vector<VarlenVariant> f64 = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}, {16, 512, 1}, {32, 256, 1}};
-    static const std::vector<VarlenVariant> f32 = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}, {16, 512, 1}, {32, 256, 1}};
-    static const std::vector<VarlenVariant> ref = {{8, 1024}, {16, 512}, {32, 256}, {8, 256}};
+    static const std::vector<VarlenVariant> f64 = {{16, 512, 0, 1}, {8, 1024}, {16, 512}, {32, 256},
+                                                   {8, 256}, {16, 512, 1}, {32, 256, 1}};
+    static const std::vector<VarlenVariant> f32 = {{16, 512, 0, 1}, {32, 256, 0, 1}, {8, 1024}, {16, 512}, {32, 256},
+                                                   {8, 256}, {16, 512, 1}, {32, 256, 1}};
+    static const std::vector<VarlenVariant> ref = {{16, 512, 0, 1}, {8, 1024}, {16, 512}, {32, 256}, {8, 256}};
     return prec == 0 ? f64 : (prec == 1 ? f32 : ref);
 }
 
@@ -405,6 +408,7 @@ auto with_kernel(int prec, int M, int NT, int thomas, F &&f) -> decltype(f(k_var
 }  // namespace
 
 int varlen_blocks(int prec, const VarlenVariant &v) {
+    if (v.wave) return varlen_wave_blocks(prec, v.M);
     return with_kernel(prec, v.M, v.NT, v.thomas, [&](auto k, int nt, size_t lds) { return occupancy_blocks(k, nt, lds); });
 }
 
@@ -496,6 +500,7 @@ hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const V
                         const VarlenVariant *small) {
     std::vector<int> all(nsys);
     std::iota(all.begin(), all.end(), 0);
+    if (v.wave) return varlen_wave_build(offsets_host, all, prec, v, sc);
     if (!small) return build_ids(offsets_host, all, prec, v, sc);
     const i64 cap = (i64)small->M * small->NT;  // longest system the small-block variant holds
     std::vector<int> lng, shr;
@@ -510,6 +515,7 @@ hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const V
 
 hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b, const void *c, const void *d,
                          void *x, hipStream_t s) {
+    if (sc.wave) return varlen_wave_launch(sc, a, b, c, d, x, s);
     VarlenArgs g;
     g.a = a;
     g.b = b;

@@ -103,7 +103,51 @@ ModelTerms model_lines(const LineReq &r, const LinePlan &pl) {
     return t;
 }
 
+// Wavefront variants: a work item is a workgroup's wavefront slots; its cost
+// is one workgroup's stream of the item's rows plus the tile sweep and the
+// in-wavefront reduced solve (six lane-move PCR levels, lvl_ns / 4 each, as
+// they need no barrier), plus one level for the exchange of a long system.
+static ModelTerms model_varlen_wave(const int64_t *off, const std::vector<int> &ids, int prec, const VarlenVariant &v,
+                                    int blocks) {
+    const VarlenParams &p = varlen_params();
+    const int NW = varlen_wave_NW(prec, v.M);
+    std::vector<int> order, tstart, wdesc;
+    varlen_wave_pack(off, ids, v.M, NW, &order, &tstart, &wdesc);
+    ModelTerms t;
+    const double per_row = prec == 0 ? 40.0 : (prec == 1 ? 20.0 : 28.0);
+    const double f = prec == 1 ? 1.0 : p.f64_factor;
+    const size_t nitems = wdesc.size() / 4 / NW;
+    double sum = 0, rows = 0, mx = 0;
+    for (size_t i = 0; i < nitems; ++i) {
+        double irows = 0;
+        bool lng = false;
+        for (int w = 0; w < NW; ++w) {
+            const int *dsc = &wdesc[(i * NW + w) * 4];
+            if (dsc[3] > 0) {
+                lng = true;
+                if (dsc[2] == w) irows += (double)(off[order[dsc[0]] + 1] - off[order[dsc[0]]]);
+            } else {
+                for (int j = 0; j < dsc[1]; ++j) irows += (double)(off[order[dsc[0] + j] + 1] - off[order[dsc[0] + j]]);
+            }
+        }
+        const double red = (6 * p.lvl_ns / 4 + (lng ? p.lvl_ns : 0.0)) * (prec == 2 ? 2 : 1);
+        const double c = p.lat_us + irows * per_row / (p.cu_gbs * 1e3) + (v.M * p.row_ns * f + red) * 1e-3;
+        sum += c;
+        rows += irows;
+        mx = std::max(mx, c);
+    }
+    t.bytes = per_row * rows;
+    t.t_bytes = t.bytes / (p.bw_gbs * 1e3);
+    const int b = std::max(1, std::min(blocks, (int)nitems));
+    t.per_cu = std::max(1, blocks / kCUs);
+    t.rounds = (double)nitems / b;
+    t.t_lat = std::max(sum / b, mx);
+    t.us = p.t0_us + std::max(t.t_bytes, t.t_lat);
+    return t;
+}
+
 ModelTerms model_varlen(const int64_t *off, std::vector<int> ids, int prec, const VarlenVariant &v, int blocks) {
+    if (v.wave) return model_varlen_wave(off, ids, prec, v, blocks);
     const VarlenParams &p = varlen_params();
     std::vector<int> tstart, item_begin, item_pmax;
     varlen_pack(off, &ids, v, &tstart, &item_begin, &item_pmax);
