@@ -49,10 +49,8 @@ constexpr int WL = 64;  // lanes per wavefront
 struct VlwArgs {
     const void *a, *b, *c, *d;
     void *x;
-    const i64 *off;      // [nsys + 1]
-    const int *order;    // systems in packing order
-    const int *tstart;   // first lane of each system of a short wavefront (parallel to order)
-    const int4 *wdesc;   // [nitems * NW]: {first, count, w0, k}
+    const int4 *rec;     // systems in packing order: {first row (low, high 32 bits), rows, first lane}
+    const int4 *wdesc;   // [nitems * NW]: {first, count, w0 | item has a long system << 8, k}
     int *counter;        // [0]: next item, [1]: finished workgroups
     int nitems;
 };
@@ -83,33 +81,54 @@ struct LanePlace {
     bool act = false;
 };
 
-// Lane assignment of wavefront slot `dsc` = {first, count, w0, k} (wavefront w
-// of the workgroup).  Short wavefronts: the lanes find their system from the
-// systems' first lanes through a wavefront-private map in LDS.
+// A work item's wavefront slot and, for a segment of a long system, that
+// system's record; fetched one item ahead (after the previous item's barrier)
+// so the dependent loads overlap that item's tail.
+struct VlwSlot {
+    int4 dsc = {0, 0, 0, 0};
+    int4 lr = {0, 0, 0, 0};
+};
+
+template <int NW>
+__device__ __forceinline__ VlwSlot vlw_fetch(const VlwArgs &g, int item, int w) {
+    VlwSlot s;
+    if (item < g.nitems) {
+        s.dsc = g.wdesc[(i64)item * NW + w];
+        if (s.dsc.w > 0) s.lr = g.rec[s.dsc.x];
+    }
+    return s;
+}
+
+__device__ __forceinline__ i64 rec_base(int4 r) { return (i64)(((unsigned long long)(unsigned)r.y << 32) | (unsigned)r.x); }
+
+// Lane assignment of wavefront slot dsc = {first, count, w0 | flag << 8, k}
+// (wavefront w of the workgroup).  Short wavefronts: the lanes find their
+// system from the systems' first lanes through a wavefront-private map in LDS.
 template <int M>
-__device__ __forceinline__ LanePlace vlw_place(const VlwArgs &g, int4 dsc, int w, int lane, int *map) {
+__device__ __forceinline__ LanePlace vlw_place(const VlwArgs &g, const VlwSlot &sl, int w, int lane, int *map) {
     LanePlace L;
+    const int4 dsc = sl.dsc;
     if (dsc.y <= 0) return L;  // empty slot: identity tiles
     if (dsc.w > 0) {           // a segment of a long system
-        L.sys = g.order[dsc.x];
-        L.sbase = g.off[L.sys];
-        L.n = (int)(g.off[L.sys + 1] - L.sbase);
+        L.sys = dsc.x;
+        L.sbase = rec_base(sl.lr);
+        L.n = sl.lr.z;
         L.P = (L.n + M - 1) / M;
-        L.p = (w - dsc.z) * WL + lane;
+        L.p = (w - (dsc.z & 0xff)) * WL + lane;
     } else {
         map[lane] = -1;
         wave_sync();
-        if (lane < dsc.y) map[g.tstart[dsc.x + lane]] = lane;
+        if (lane < dsc.y) map[g.rec[dsc.x + lane].w] = lane;
         wave_sync();
         const int j = map[lane];
         const unsigned long long starts = __ballot(j >= 0);
         const unsigned long long below = starts & (lane == WL - 1 ? ~0ull : ((2ull << lane) - 1ull));
         if (below) {
             const int st = 63 - __builtin_clzll(below);
-            const int jj = map[st];
-            L.sys = g.order[dsc.x + jj];
-            L.sbase = g.off[L.sys];
-            L.n = (int)(g.off[L.sys + 1] - L.sbase);
+            const int4 r = g.rec[dsc.x + map[st]];
+            L.sys = dsc.x + map[st];
+            L.sbase = rec_base(r);
+            L.n = r.z;
             L.P = (L.n + M - 1) / M;
             L.p = lane - st;
         }
@@ -324,8 +343,10 @@ __device__ __forceinline__ void vlw_finish(int *counter) {
 
 // PIPE: the next array's loads are issued before the current one is staged
 // (more loads in flight, more registers).
-template <typename T, int M, int NW, bool PIPE>
-__global__ __launch_bounds__(WL *NW) void k_vlw_plain(VlwArgs g) {
+// WPE: wavefronts per SIMD the register allocation must allow (two
+// workgroups of 8 wavefronts per CU need 4).
+template <typename T, int M, int NW, bool PIPE, int WPE = 1>
+__global__ __launch_bounds__(WL *NW, WPE) void k_vlw_plain(VlwArgs g) {
     using Lds = VlwLds<M, NW, T, T>;
     __shared__ int s_next[2];
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -342,14 +363,14 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_plain(VlwArgs g) {
     if (threadIdx.x == 0) s_next[0] = atomicAdd(&g.counter[0], 1);
     __syncthreads();
     int item = s_next[0];
+    VlwSlot nxt = vlw_fetch<NW>(g, item, w);
     for (int it = 0; item < g.nitems; ++it) {
         const int par = it & 1;
         if (threadIdx.x == 0) s_next[par ^ 1] = atomicAdd(&g.counter[0], 1);
-        bool has_long = false;
-#pragma unroll
-        for (int j = 0; j < NW; ++j) has_long |= g.wdesc[(i64)item * NW + j].w > 0;
-        const int4 dsc = g.wdesc[(i64)item * NW + w];
-        const LanePlace L = vlw_place<M>(g, dsc, w, lane, map);
+        const VlwSlot sl = nxt;
+        const int4 dsc = sl.dsc;
+        const bool has_long = (dsc.z >> 8) != 0;
+        const LanePlace L = vlw_place<M>(g, sl, w, lane, map);
         vlw_ranges<M>(L, lane, s_base, s_cnt);
         T ra[M], rb[M], rc[M], rd[M];
         {
@@ -387,10 +408,14 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_plain(VlwArgs g) {
         } else {
             vlw_short<T, M>(ts, L, f, lv);
         }
-        if (has_long) __syncthreads();  // the Schur rows (and the next item's index) are visible
+        if (has_long) {  // the Schur rows and the next item's index are visible
+            __syncthreads();
+            item = s_next[par ^ 1];
+            nxt = vlw_fetch<NW>(g, item, w);
+        }
         if (dsc.w > 0) {
             T F, Lw, Lp, Fn;
-            vlw_schur_solve<T, NW>(xb, dsc.z, dsc.w, w, lane, F, Lw, Lp, Fn);
+            vlw_schur_solve<T, NW>(xb, dsc.z & 0xff, dsc.w, w, lane, F, Lw, Lp, Fn);
             f = lane == 0 ? F : y + v * F + wv * Lw;
             const T fn = dn1(f);
             lv = lane == WL - 1 ? Lw : ts.ld - ts.la * f - ts.lc * fn;
@@ -402,8 +427,11 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_plain(VlwArgs g) {
         wave_sync();
         vlw_store<T, M>(x, st, s_base, s_cnt, lane);
         wave_sync();
-        if (!has_long) __syncthreads();  // the next item's index is visible
-        item = s_next[par ^ 1];
+        if (!has_long) {  // the next item's index is visible
+            __syncthreads();
+            item = s_next[par ^ 1];
+            nxt = vlw_fetch<NW>(g, item, w);
+        }
     }
     vlw_finish(g.counter);
 }
@@ -429,20 +457,21 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
     if (threadIdx.x == 0) s_next[0] = atomicAdd(&g.counter[0], 1);
     __syncthreads();
     int item = s_next[0];
+    VlwSlot nxt = vlw_fetch<NW>(g, item, w);
     for (int it = 0; item < g.nitems; ++it) {
         const int par = it & 1;
         if (threadIdx.x == 0) s_next[par ^ 1] = atomicAdd(&g.counter[0], 1);
-        bool has_long = false;
-#pragma unroll
-        for (int j = 0; j < NW; ++j) has_long |= g.wdesc[(i64)item * NW + j].w > 0;
-        const int4 dsc = g.wdesc[(i64)item * NW + w];
+        const VlwSlot sl = nxt;
+        const int4 dsc = sl.dsc;
+        const bool has_long = (dsc.z >> 8) != 0;
         const bool lng = dsc.w > 0;
-        const LanePlace L = vlw_place<M>(g, dsc, w, lane, map);
+        const LanePlace L = vlw_place<M>(g, sl, w, lane, map);
         vlw_ranges<M>(L, lane, s_base, s_cnt);
         float ra[M], rb[M], rc[M];
         double dd[M];
         {
             float vn[M];
+            double vd[M];
             vlw_load<float, M>(vn, arr[0], s_base, s_cnt, lane);
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
@@ -450,6 +479,7 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
 #pragma unroll
                 for (int k = 0; k < M; ++k) vc[k] = vn[k];
                 if (r < 2) vlw_load<float, M>(vn, arr[r + 1], s_base, s_cnt, lane);
+                if (r == 2) vlw_load<double, M>(vd, dg, s_base, s_cnt, lane);  // in flight while c is staged
                 vlw_put<float, M>(stf, vc, lane);
                 wave_sync();
 #pragma unroll
@@ -463,8 +493,6 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
                 }
                 wave_sync();
             }
-            double vd[M];
-            vlw_load<double, M>(vd, dg, s_base, s_cnt, lane);
             vlw_put<double, M>(st, vd, lane);
             wave_sync();
 #pragma unroll
@@ -486,11 +514,17 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
                 vlw_long_chain<float, M>(ts, lane, y, v, wv, xb + 2 * w * 4);
             else
                 vlw_short<float, M>(ts, L, f, lv);
-            if (has_long) __syncthreads();
+            if (has_long) {
+                __syncthreads();
+                if (pass == 1) {  // the next item's index is visible
+                    item = s_next[par ^ 1];
+                    nxt = vlw_fetch<NW>(g, item, w);
+                }
+            }
             float Lp = 0.f, Fn = 0.f;
             if (lng) {
                 float F, Lw;
-                vlw_schur_solve<float, NW>(xb, dsc.z, dsc.w, w, lane, F, Lw, Lp, Fn);
+                vlw_schur_solve<float, NW>(xb, dsc.z & 0xff, dsc.w, w, lane, F, Lw, Lp, Fn);
                 f = lane == 0 ? F : y + v * F + wv * Lw;
                 const float fn = dn1(f);
                 lv = lane == WL - 1 ? Lw : ts.ld - ts.la * f - ts.lc * fn;
@@ -523,8 +557,11 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
         wave_sync();
         vlw_store<double, M>(x, st, s_base, s_cnt, lane);
         wave_sync();
-        if (!has_long) __syncthreads();
-        item = s_next[par ^ 1];
+        if (!has_long) {
+            __syncthreads();
+            item = s_next[par ^ 1];
+            nxt = vlw_fetch<NW>(g, item, w);
+        }
     }
     vlw_finish(g.counter);
 }
@@ -535,7 +572,7 @@ auto with_wave_kernel(int prec, int M, int NW, F &&f) -> decltype(f(k_vlw_refine
     if (prec == 2) return f(k_vlw_refine<16, 8>, 512, VlwLds<16, 8, double, float>::bytes(2));
     if (prec == 0) return f(k_vlw_plain<double, 16, 8, true>, 512, VlwLds<16, 8, double, double>::bytes(1));
     if (M == 32) return f(k_vlw_plain<float, 32, 4, true>, 256, VlwLds<32, 4, float, float>::bytes(1));
-    return f(k_vlw_plain<float, 16, 8, true>, 512, VlwLds<16, 8, float, float>::bytes(1));
+    return f(k_vlw_plain<float, 16, 8, false, 4>, 512, VlwLds<16, 8, float, float>::bytes(1));
 }
 
 template <class K>
@@ -606,6 +643,14 @@ void varlen_wave_pack(const int64_t *off, std::vector<int> ids, int M, int NW, s
         }
     }
     while (slots.size() % NW) slots.push_back({0, 0, 0, 0});
+    // flag every slot of an item that holds a long system (its workgroup
+    // exchanges Schur rows): w0 | 1 << 8
+    for (size_t it = 0; it < slots.size(); it += NW) {
+        bool lng = false;
+        for (int j = 0; j < NW; ++j) lng |= slots[it + j][3] > 0;
+        if (lng)
+            for (int j = 0; j < NW; ++j) slots[it + j][2] |= 1 << 8;
+    }
     wdesc->reserve(slots.size() * 4);
     for (const auto &s : slots) wdesc->insert(wdesc->end(), s.begin(), s.end());
 }
@@ -620,6 +665,15 @@ hipError_t varlen_wave_build(const int64_t *off, std::vector<int> ids, int prec,
     const int NW = varlen_wave_NW(prec, v.M);
     std::vector<int> order, tstart, wdesc;
     varlen_wave_pack(off, ids, v.M, NW, &order, &tstart, &wdesc);
+    // per system in packing order: first row (two 32-bit halves), rows, first lane
+    std::vector<int> rec(order.size() * 4);
+    for (size_t i = 0; i < order.size(); ++i) {
+        const unsigned long long b = (unsigned long long)off[order[i]];
+        rec[4 * i] = (int)(unsigned)(b & 0xffffffffull);
+        rec[4 * i + 1] = (int)(unsigned)(b >> 32);
+        rec[4 * i + 2] = (int)(off[order[i] + 1] - off[order[i]]);
+        rec[4 * i + 3] = tstart[i];
+    }
     sc->prec = prec;
     sc->M = v.M;
     sc->NT = WL * NW;
@@ -627,29 +681,21 @@ hipError_t varlen_wave_build(const int64_t *off, std::vector<int> ids, int prec,
     sc->wave = 1;
     sc->nsys = (i64)ids.size();
     sc->nitems = (int)(wdesc.size() / 4 / NW);
-    const i64 nall = 1 + *std::max_element(ids.begin(), ids.end());
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t b_off = sizeof(i64) * (nall + 1), b_ord = sizeof(int) * order.size(),
-                 b_ts = sizeof(int) * tstart.size(), b_wd = sizeof(int) * wdesc.size();
-    const size_t total = up(b_off) + up(b_ord) + up(b_ts) + up(b_wd) + 256;
+    const size_t b_rec = sizeof(int) * rec.size(), b_wd = sizeof(int) * wdesc.size();
+    const size_t total = up(b_rec) + up(b_wd) + 256;
     hipError_t e = hipMalloc(&sc->dev, total);
     if (e != hipSuccess) {
         sc->dev = nullptr;
         return e;
     }
     char *p = static_cast<char *>(sc->dev);
-    sc->off = reinterpret_cast<i64 *>(p);
-    p += up(b_off);
-    sc->order = reinterpret_cast<int *>(p);
-    p += up(b_ord);
-    sc->tstart = reinterpret_cast<int *>(p);
-    p += up(b_ts);
+    sc->rec = reinterpret_cast<int *>(p);
+    p += up(b_rec);
     sc->wdesc = reinterpret_cast<int *>(p);
     p += up(b_wd);
     sc->counter = reinterpret_cast<int *>(p);
-    if ((e = hipMemcpy(sc->off, off, b_off, hipMemcpyHostToDevice)) != hipSuccess) return e;
-    if ((e = hipMemcpy(sc->order, order.data(), b_ord, hipMemcpyHostToDevice)) != hipSuccess) return e;
-    if ((e = hipMemcpy(sc->tstart, tstart.data(), b_ts, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemcpy(sc->rec, rec.data(), b_rec, hipMemcpyHostToDevice)) != hipSuccess) return e;
     if ((e = hipMemcpy(sc->wdesc, wdesc.data(), b_wd, hipMemcpyHostToDevice)) != hipSuccess) return e;
     if ((e = hipMemset(sc->counter, 0, 2 * sizeof(int))) != hipSuccess) return e;
     sc->nblocks = std::max(1, std::min(varlen_wave_blocks(prec, v.M), sc->nitems));
@@ -664,9 +710,7 @@ hipError_t varlen_wave_launch(const VarlenSchedule &sc, const void *a, const voi
     g.c = c;
     g.d = d;
     g.x = x;
-    g.off = sc.off;
-    g.order = sc.order;
-    g.tstart = sc.tstart;
+    g.rec = reinterpret_cast<const int4 *>(sc.rec);
     g.wdesc = reinterpret_cast<const int4 *>(sc.wdesc);
     g.counter = sc.counter;
     g.nitems = sc.nitems;

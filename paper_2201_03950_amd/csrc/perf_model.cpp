@@ -125,7 +125,7 @@ static ModelTerms model_varlen_wave(const int64_t *off, const std::vector<int> &
             const int *dsc = &wdesc[(i * NW + w) * 4];
             if (dsc[3] > 0) {
                 lng = true;
-                if (dsc[2] == w) irows += (double)(off[order[dsc[0]] + 1] - off[order[dsc[0]]]);
+                if ((dsc[2] & 0xff) == w) irows += (double)(off[order[dsc[0]] + 1] - off[order[dsc[0]]]);
             } else {
                 for (int j = 0; j < dsc[1]; ++j) irows += (double)(off[order[dsc[0] + j] + 1] - off[order[dsc[0] + j]]);
             }

@@ -34,7 +34,8 @@ struct VarlenSchedule {
     i64 *off = nullptr;
     int *order = nullptr, *tstart = nullptr, *item_begin = nullptr, *item_pmax = nullptr;
     int *counter = nullptr;
-    int *wdesc = nullptr;  // wavefront variants: {first, count, w0, k} per wavefront slot
+    int *wdesc = nullptr;  // wavefront variants: {first, count, w0 | flag << 8, k} per wavefront slot
+    int *rec = nullptr;    // wavefront variants: {first row lo, hi, rows, first lane} per system
     float tuned_us = 0.f;  // measured time when chosen by the autotuner
     // split schedule: the systems too long for a small-block variant run in
     // this launch, the rest in `next` (launched right after, same arrays)
