@@ -247,6 +247,16 @@ def extra_workloads(trid):
     return out
 
 
+def kernel_split(trid, fn, reps=5):
+    """Mean kernel microseconds per launch name over `reps` calls of fn (timing on)."""
+    trid.timing_enable(True)
+    for _ in range(reps):
+        fn()
+    kt = trid.timing_read()
+    trid.timing_enable(False)
+    return {k: round(ms / cnt * 1e3, 2) for k, (cnt, ms) in kt.items()}
+
+
 def _err_vs(ref, x):
     """max |x - ref| / max |ref| (torch tensors, compared in FP64)."""
     ref, x = ref.double(), x.double()
@@ -302,8 +312,11 @@ def extra_2d(trid):
         t -= time_calls(lambda: td.copy_(d0), 5, warm=1)  # the reset copy is not solver time
         wb = 8 if dt == torch.float64 else 4
         byts = 2 * alg_bytes("s", wb, pts)
+        split = kernel_split(trid, xy)
         res[tag] = {"ms": round(t * 1e3, 4), "gbs": round(byts / t / 1e9, 1),
-                    "frac": round(byts / t / 1e9 / PEAK_GBS, 4), **err}
+                    "frac": round(byts / t / 1e9 / PEAK_GBS, 4), **err,
+                    "kernel_us": split,
+                    "kernel_gbs": {k: round(alg_bytes("s", wb, pts) / (v * 1e-6) / 1e9, 1) for k, v in split.items()}}
         del ts, d0, td
         torch.cuda.empty_cache()
     ts = torch.from_numpy(s32).cuda()
@@ -317,9 +330,10 @@ def extra_2d(trid):
 
     t = time_calls(xy_ref, 5, warm=1)
     byts = (4 + 4 + 8) * pts + (4 + 8 + 8) * pts  # x: s32, d32 -> x64; y: s32, x64 -> out64
+    split = kernel_split(trid, xy_ref)
     res["f32_refine64"] = {"ms": round(t * 1e3, 4), "gbs": round(byts / t / 1e9, 1),
                            "frac": round(byts / t / 1e9 / PEAK_GBS, 4),
-                           "err_vs_f64": _err_vs(x64, xo[:2])}
+                           "err_vs_f64": _err_vs(x64, xo[:2]), "kernel_us": split}
     res["refine_time_vs_f64"] = round(res["f32_refine64"]["ms"] / res["f64"]["ms"], 3)
     out["adi2d_64x1024sq_xy"] = res
     return out

@@ -164,7 +164,10 @@ int trid_gtsv_batched_s(trid_handle_t h, trid_dtype_t dt, const void *s, void *d
  * record), computes x32 = solve32(A, fp32(d)), r = d - A x32 in FP64,
  * delta = solve32(A, fp32(r)), x = x32 + delta in FP64.  d has dtype d_dt
  * (FP32 or FP64) and is read only; x (FP64) receives the result and may not
- * alias d.  Same layout and errors as trid_gtsv_batched. */
+ * alias d.  Same layout and errors as trid_gtsv_batched; contiguous lines
+ * longer than TRID_MAX_LINE run the refinement as passes around the chunked
+ * FP32 solve (FP64 residual pass, FP32 correction solve, FP64 sum) with a
+ * workspace of two FP32 mesh-sized arrays owned by the handle. */
 int trid_gtsv_batched_refine(trid_handle_t h, trid_dtype_t d_dt, const float *a, const float *b,
                              const float *c, const void *d, double *x, int ndim,
                              const int64_t *dims, int axis, int64_t batch);
@@ -180,7 +183,12 @@ int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t d_dt, const float *
  * rows [offsets[k], offsets[k+1]) of a, b, c, d and x (Section III-B's tiled
  * solver handles the long ones).  offsets_host is a HOST int64 array of
  * nsys+1 non-decreasing entries with offsets[0] = 0 and every length in
- * 1..TRID_MAX_LINE.  Precision p selects the arithmetic:
+ * 1..TRID_MAX_LONG_LINE.  Systems of up to TRID_MAX_LINE rows are tiled inside
+ * one workgroup; longer ones are cut into chunks of 2048 rows coupled through
+ * a reduced system of two rows per chunk (the chunked solve of
+ * trid_gtsv_batched, one system after the other after the persistent launch;
+ * with F32_REFINE64 as passes: FP32 chunked solve, FP64 residual, FP32 chunked
+ * correction solve, FP64 sum).  Precision p selects the arithmetic:
  *   TRID_PREC_F64:          a, b, c, d, x are double;
  *   TRID_PREC_F32:          a, b, c, d, x are float;
  *   TRID_PREC_F32_REFINE64: a, b, c are float, d and x are double.
@@ -288,7 +296,9 @@ int trid_hv_step(trid_handle_t h, trid_dtype_t dt, void *u, const void *a, const
  * ga, gb, gc (written, not accumulated) receive dL/da = -lambda_i x_{i-1},
  * dL/db = -lambda_i x_i, dL/dc = -lambda_i x_{i+1}; the entries of the ignored
  * a_0 and c_{N-1} are written as 0.  Same layout and errors as
- * trid_gtsv_batched. */
+ * trid_gtsv_batched; contiguous lines longer than TRID_MAX_LINE write the rows
+ * of A^T into a handle workspace (three mesh-sized arrays) and take the
+ * chunked solve, then the gradients pointwise. */
 int trid_gtsv_batched_adjoint(trid_handle_t h, trid_dtype_t dt, const void *a, const void *b,
                               const void *c, const void *x, void *g, void *ga, void *gb, void *gc,
                               int ndim, const int64_t *dims, int axis, int64_t batch);

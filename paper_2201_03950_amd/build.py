@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "libtrid.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["api.cpp", "api_ext.cpp", "perf_model.cpp", "k_lines.hip", "k_adi.hip", "k_const.hip", "k_refine.hip", "k_adjoint.hip", "k_varlen.hip", "k_varlen_wave.hip", "k_long.hip", "k_resident.hip", "k_hv.hip"]
+SOURCES = ["api.cpp", "api_ext.cpp", "perf_model.cpp", "k_lines.hip", "k_adi.hip", "k_const.hip", "k_refine.hip", "k_adjoint.hip", "k_varlen.hip", "k_varlen_wave.hip", "k_long.hip", "k_long_ext.hip", "k_resident.hip", "k_hv.hip"]
 
 CFLAGS = [
     "-x", "hip", "-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC",

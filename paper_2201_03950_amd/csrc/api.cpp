@@ -151,8 +151,8 @@ ExtState &handle_ext(trid_handle_t h) { return h->ext; }
 int handle_fail(trid_handle_t h, int code, const std::string &msg) { return fail(h, code, msg); }
 int handle_hip_fail(trid_handle_t h, hipError_t e, const char *what) { return hip_fail(h, e, what); }
 int handle_check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, int64_t batch,
-                      i64 *inner, i64 *n, i64 *outer) {
-    return check_mesh(h, ndim, dims, axis, batch, inner, n, outer);
+                      i64 *inner, i64 *n, i64 *outer, bool long_ok) {
+    return check_mesh(h, ndim, dims, axis, batch, inner, n, outer, long_ok);
 }
 int handle_run_lines(trid_handle_t h, const LineReq &r) { return run_lines(h, r); }
 

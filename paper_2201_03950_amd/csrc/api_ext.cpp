@@ -16,6 +16,8 @@
 #include "dispatch.hpp"
 #include "ext.hpp"
 #include "hv.hpp"
+#include "long_ext.hpp"
+#include "long_lines.hpp"
 #include "perf_model.hpp"
 #include "refine.hpp"
 #include "resident.hpp"
@@ -114,6 +116,40 @@ int trid_timing_read(trid_handle_t h, char *buf, int64_t len) {
     return TRID_OK;
 }
 
+// Contiguous lines longer than TRID_MAX_LINE: the transposed solve through the
+// chunked solve, with the transposed rows in the handle's workspace.
+static int run_long_adjoint(trid_handle_t h, const trid::LongAdjReq &q) {
+    void *ws = nullptr;
+    int rc = trid::handle_workspace2(h, trid::long_adjoint_workspace(q.f64, q.n, q.lines), &ws);
+    if (rc) return rc;
+    hipStream_t st = trid::handle_stream(h);
+    std::string msg;
+    hipError_t e = trid::handle_ext(h).timer.time_recorded(
+        "adjoint_long", st, [&] { return trid::launch_long_adjoint(q, ws, st, &msg); });
+    if (e != hipSuccess) {
+        if (!msg.empty()) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
+        return trid::handle_hip_fail(h, e, "long-line adjoint launch");
+    }
+    return TRID_OK;
+}
+
+// Contiguous lines longer than TRID_MAX_LINE: the refinement as passes around
+// the chunked FP32 solve, with x32 and the residual in the handle's workspace.
+static int run_long_refine(trid_handle_t h, const trid::LongRefineReq &q) {
+    void *ws = nullptr;
+    int rc = trid::handle_workspace2(h, trid::long_refine_workspace(q.n, q.lines), &ws);
+    if (rc) return rc;
+    hipStream_t st = trid::handle_stream(h);
+    std::string msg;
+    hipError_t e = trid::handle_ext(h).timer.time_recorded(
+        "refine_long", st, [&] { return trid::launch_long_refine(q, ws, st, &msg); });
+    if (e != hipSuccess) {
+        if (!msg.empty()) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
+        return trid::handle_hip_fail(h, e, "long-line refinement launch");
+    }
+    return TRID_OK;
+}
+
 int trid_gtsv_batched_adjoint(trid_handle_t h, trid_dtype_t dt, const void *a, const void *b,
                               const void *c, const void *x, void *g, void *ga, void *gb, void *gc,
                               int ndim, const int64_t *dims, int axis, int64_t batch) {
@@ -122,8 +158,23 @@ int trid_gtsv_batched_adjoint(trid_handle_t h, trid_dtype_t dt, const void *a, c
     if (!a || !b || !c || !x || !g || !ga || !gb || !gc)
         return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
     trid::LineReq r;
-    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer, true);
     if (rc) return rc;
+    if (r.n > TRID_MAX_LINE) {
+        trid::LongAdjReq q;
+        q.f64 = dt == TRID_F64;
+        q.a = a;
+        q.b = b;
+        q.c = c;
+        q.x = x;
+        q.g = g;
+        q.ga = ga;
+        q.gb = gb;
+        q.gc = gc;
+        q.n = r.n;
+        q.lines = r.outer;
+        return run_long_adjoint(h, q);
+    }
     r.f64 = dt == TRID_F64;
     r.mode = trid::Mode::ArraysT;
     r.out = trid::Out::AdjArrays;
@@ -145,8 +196,19 @@ int trid_gtsv_batched_s_adjoint(trid_handle_t h, trid_dtype_t dt, const void *s,
     if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
     if (!s || !x || !g || !gs) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
     trid::LineReq r;
-    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer, true);
     if (rc) return rc;
+    if (r.n > TRID_MAX_LINE) {
+        trid::LongAdjReq q;
+        q.f64 = dt == TRID_F64;
+        q.s = s;
+        q.x = x;
+        q.g = g;
+        q.gs = gs;
+        q.n = r.n;
+        q.lines = r.outer;
+        return run_long_adjoint(h, q);
+    }
     r.f64 = dt == TRID_F64;
     r.mode = trid::Mode::ST;
     r.out = trid::Out::AdjS;
@@ -179,8 +241,20 @@ int trid_gtsv_batched_refine(trid_handle_t h, trid_dtype_t d_dt, const float *a,
     if (!a || !b || !c || !d || !x) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
     if ((const void *)x == d) return trid::handle_fail(h, TRID_ERR_ARG, "x may not alias d");
     trid::RefineReq r;
-    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer, true);
     if (rc) return rc;
+    if (r.n > TRID_MAX_LINE) {
+        trid::LongRefineReq q;
+        q.a = a;
+        q.b = b;
+        q.c = c;
+        q.d = d;
+        q.d_f64 = d_dt == TRID_F64;
+        q.x = x;
+        q.n = r.n;
+        q.lines = r.outer;
+        return run_long_refine(h, q);
+    }
     r.smode = false;
     r.d_f64 = d_dt == TRID_F64;
     r.src.a = a;
@@ -198,8 +272,18 @@ int trid_gtsv_batched_s_refine(trid_handle_t h, trid_dtype_t d_dt, const float *
     if (!s || !d || !x) return trid::handle_fail(h, TRID_ERR_ARG, "NULL data pointer");
     if ((const void *)x == d) return trid::handle_fail(h, TRID_ERR_ARG, "x may not alias d");
     trid::RefineReq r;
-    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer);
+    int rc = trid::handle_check_mesh(h, ndim, dims, axis, batch, &r.inner, &r.n, &r.outer, true);
     if (rc) return rc;
+    if (r.n > TRID_MAX_LINE) {
+        trid::LongRefineReq q;
+        q.s = s;
+        q.d = d;
+        q.d_f64 = d_dt == TRID_F64;
+        q.x = x;
+        q.n = r.n;
+        q.lines = r.outer;
+        return run_long_refine(h, q);
+    }
     r.smode = true;
     r.d_f64 = d_dt == TRID_F64;
     r.src.s = s;
@@ -264,8 +348,12 @@ size_t autotune_top() {
 // (the partition of varlen_build).
 double predict_varlen_plan(const int64_t *off, int64_t nsys, int prec, const trid::VarlenVariant &v, bool split,
                            const trid::VarlenVariant &small) {
-    std::vector<int> all(nsys), lng, shr;
-    for (int64_t k = 0; k < nsys; ++k) all[k] = (int)k;
+    // the systems of the persistent launch (the longer ones take the chunked
+    // solve under every plan)
+    std::vector<int> all, lng, shr;
+    for (int64_t k = 0; k < nsys; ++k)
+        if (off[k + 1] - off[k] <= trid::kVarlenMaxTiled) all.push_back((int)k);
+    if (all.empty()) return 0.0;
     if (!split) return trid::model_varlen(off, all, prec, v, trid::varlen_blocks(prec, v)).us;
     const int64_t cap = (int64_t)small.M * small.NT;
     for (int k : all) (off[k + 1] - off[k] > cap ? lng : shr).push_back(k);
@@ -309,12 +397,16 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
     if (nsys < 1 || nsys > ((int64_t)1 << 30)) return trid::handle_fail(h, TRID_ERR_ARG, "nsys out of range");
     if (prec == TRID_PREC_F32_REFINE64 && d == x) return trid::handle_fail(h, TRID_ERR_ARG, "x may not alias d");
     if (off[0] != 0) return trid::handle_fail(h, TRID_ERR_ARG, "offsets[0] must be 0");
-    int64_t maxlen = 0;
+    int64_t maxlen = 0, nlong = 0;  // longest system of the persistent launch; systems of the chunked solve
     for (int64_t k = 0; k < nsys; ++k) {
         const int64_t len = off[k + 1] - off[k];
         if (len < 1) return trid::handle_fail(h, TRID_ERR_ARG, "every system needs at least one row");
-        if (len > TRID_MAX_LINE) return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "system longer than TRID_MAX_LINE");
-        maxlen = std::max(maxlen, len);
+        if (len > TRID_MAX_LONG_LINE)
+            return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "system longer than TRID_MAX_LONG_LINE");
+        if (len > trid::kVarlenMaxTiled)
+            ++nlong;
+        else
+            maxlen = std::max(maxlen, len);
     }
     trid::ExtState &xs = trid::handle_ext(h);
     hipStream_t st = trid::handle_stream(h);
@@ -376,6 +468,7 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
                 tr.blocks = trid::varlen_blocks(p, plans[i].v);
                 tr.blocks_small = plans[i].split ? trid::varlen_blocks(p, small) : 0;
                 tr.pred_us = pred[i];
+                tr.nlong = (int)nlong;
                 xs.last_tune.push_back(tr);
             }
             for (size_t ri = 0; ri < ntime; ++ri) {
@@ -825,10 +918,9 @@ int trid_autotune_report(trid_handle_t h, char *buf, size_t len) {
     for (size_t i = 0; i < rec.size(); ++i) {
         snprintf(item, sizeof item,
                  "%s{\"M\": %d, \"NT\": %d, \"reduced\": \"%s\", \"split\": %d, \"blocks\": %d, "
-                 "\"blocks_small\": %d, \"pred_us\": %.3f, \"meas_us\": %.3f}",
+                 "\"blocks_small\": %d, \"long\": %d, \"pred_us\": %.3f, \"meas_us\": %.3f}",
                  i ? ", " : "", rec[i].M, rec[i].NT, rec[i].wave ? "wave" : (rec[i].thomas ? "thomas" : "pcr"),
-                 rec[i].split, rec[i].blocks,
-                 rec[i].blocks_small, rec[i].pred_us, rec[i].meas_us);
+                 rec[i].split, rec[i].blocks, rec[i].blocks_small, rec[i].nlong, rec[i].pred_us, rec[i].meas_us);
         o << item;
     }
     o << "]";

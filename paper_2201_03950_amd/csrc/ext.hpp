@@ -112,6 +112,7 @@ struct TunedPlan {
 // when it was among those timed, the measured time (else < 0).
 struct TuneRecord {
     int M = 0, NT = 0, thomas = 0, split = 0, wave = 0;
+    int nlong = 0;  // systems longer than one workgroup holds (chunked solve, every plan)
     int blocks = 0, blocks_small = 0;  // persistent workgroups of the launch(es)
     double pred_us = 0, meas_us = -1;
 };
@@ -150,8 +151,9 @@ hipStream_t handle_stream(trid_handle_t h);
 ExtState &handle_ext(trid_handle_t h);
 int handle_fail(trid_handle_t h, int code, const std::string &msg);
 int handle_hip_fail(trid_handle_t h, hipError_t e, const char *what);
+// long_ok: contiguous lines up to TRID_MAX_LONG_LINE are accepted
 int handle_check_mesh(trid_handle_t h, int ndim, const int64_t *dims, int axis, int64_t batch,
-                      i64 *inner, i64 *n, i64 *outer);
+                      i64 *inner, i64 *n, i64 *outer, bool long_ok = false);
 int handle_run_lines(trid_handle_t h, const LineReq &r);
 int handle_workspace(trid_handle_t h, size_t bytes, void **ptr);
 bool alloc_failure_forced();  // TRID_FAIL_ALLOC is set: workspace allocations fail

@@ -21,6 +21,8 @@
 #include <vector>
 
 #include "dispatch.hpp"
+#include "long_ext.hpp"
+#include "long_lines.hpp"
 #include "refine_tile.hpp"
 #include "varlen.hpp"
 
@@ -496,10 +498,89 @@ hipError_t build_ids(const int64_t *offsets_host, std::vector<int> ids, int prec
 
 }  // namespace
 
+namespace {
+
+// The systems longer than kVarlenMaxTiled: their list and the chunked solve's
+// workspace (sized for the longest).
+hipError_t build_long(const int64_t *off, const std::vector<int> &ids, int prec, VarlenSchedule *sc) {
+    size_t ws = 0;
+    for (int k : ids) {
+        const i64 n = off[k + 1] - off[k];
+        sc->long_off.push_back(off[k]);
+        sc->long_len.push_back(n);
+        LineReq q;
+        q.f64 = prec == 0;
+        q.inner = 1;
+        q.n = n;
+        q.outer = 1;
+        ws = std::max(ws, prec == 2 ? long_refine_workspace(n, 1) : long_lines_workspace(q));
+    }
+    if (!ws) return hipSuccess;
+    hipError_t e = hipMalloc(&sc->long_ws, ws);
+    if (e != hipSuccess) sc->long_ws = nullptr;
+    return e;
+}
+
+// The long systems, one chunked solve each (three launches; five passes for
+// the refinement).
+hipError_t launch_long_systems(const VarlenSchedule &sc, const void *a, const void *b, const void *c, const void *d,
+                               void *x, hipStream_t s) {
+    std::string err;
+    for (size_t i = 0; i < sc.long_off.size(); ++i) {
+        const i64 o = sc.long_off[i], n = sc.long_len[i];
+        hipError_t e;
+        if (sc.prec == 2) {
+            LongRefineReq q;
+            q.a = static_cast<const float *>(a) + o;
+            q.b = static_cast<const float *>(b) + o;
+            q.c = static_cast<const float *>(c) + o;
+            q.d = static_cast<const double *>(d) + o;
+            q.d_f64 = true;
+            q.x = static_cast<double *>(x) + o;
+            q.n = n;
+            q.lines = 1;
+            e = launch_long_refine(q, sc.long_ws, s, &err);
+        } else {
+            const size_t w = sc.prec == 0 ? 8 : 4;
+            LineReq q;
+            q.f64 = sc.prec == 0;
+            q.mode = Mode::Arrays;
+            q.out = Out::Store;
+            q.a = static_cast<const char *>(a) + o * w;
+            q.b = static_cast<const char *>(b) + o * w;
+            q.c = static_cast<const char *>(c) + o * w;
+            q.d = static_cast<const char *>(d) + o * w;
+            q.x = static_cast<char *>(x) + o * w;
+            q.inner = 1;
+            q.n = n;
+            q.outer = 1;
+            e = launch_long_lines(q, sc.long_ws, s, &err);
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
 hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const VarlenVariant &v, VarlenSchedule *sc,
                         const VarlenVariant *small) {
-    std::vector<int> all(nsys);
-    std::iota(all.begin(), all.end(), 0);
+    std::vector<int> all, lng_all;
+    for (i64 k = 0; k < nsys; ++k)
+        (offsets_host[k + 1] - offsets_host[k] > kVarlenMaxTiled ? lng_all : all).push_back((int)k);
+    hipError_t e = build_long(offsets_host, lng_all, prec, sc);
+    if (e != hipSuccess) return e;
+    if (all.empty()) {  // every system takes the chunked solve
+        sc->prec = prec;
+        sc->M = v.M;
+        sc->NT = v.NT;
+        sc->thomas = v.thomas;
+        sc->wave = v.wave;
+        sc->nsys = nsys;
+        sc->nitems = 0;
+        sc->nblocks = 0;
+        return hipSuccess;
+    }
     if (v.wave) return varlen_wave_build(offsets_host, all, prec, v, sc);
     if (!small) return build_ids(offsets_host, all, prec, v, sc);
     const i64 cap = (i64)small->M * small->NT;  // longest system the small-block variant holds
@@ -507,15 +588,26 @@ hipError_t varlen_build(const int64_t *offsets_host, i64 nsys, int prec, const V
     for (int k : all) (offsets_host[k + 1] - offsets_host[k] > cap ? lng : shr).push_back(k);
     if (lng.empty()) return build_ids(offsets_host, shr, prec, *small, sc);
     if (shr.empty()) return build_ids(offsets_host, lng, prec, v, sc);
-    hipError_t e = build_ids(offsets_host, lng, prec, v, sc);
+    e = build_ids(offsets_host, lng, prec, v, sc);
     if (e != hipSuccess) return e;
     sc->next = new VarlenSchedule();
     return build_ids(offsets_host, shr, prec, *small, sc->next);
 }
 
+static hipError_t varlen_launch_tiled(const VarlenSchedule &sc, const void *a, const void *b, const void *c,
+                                      const void *d, void *x, hipStream_t s);
+
 hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b, const void *c, const void *d,
                          void *x, hipStream_t s) {
-    if (sc.wave) return varlen_wave_launch(sc, a, b, c, d, x, s);
+    if (sc.nitems > 0) {
+        hipError_t e = sc.wave ? varlen_wave_launch(sc, a, b, c, d, x, s) : varlen_launch_tiled(sc, a, b, c, d, x, s);
+        if (e != hipSuccess) return e;
+    }
+    return launch_long_systems(sc, a, b, c, d, x, s);
+}
+
+static hipError_t varlen_launch_tiled(const VarlenSchedule &sc, const void *a, const void *b, const void *c,
+                                      const void *d, void *x, hipStream_t s) {
     VarlenArgs g;
     g.a = a;
     g.b = b;
@@ -532,7 +624,7 @@ hipError_t varlen_launch(const VarlenSchedule &sc, const void *a, const void *b,
     hipError_t e = with_kernel(sc.prec, sc.M, sc.NT, sc.thomas,
                                [&](auto k, int nt, size_t lds) { return launch_persistent(k, nt, lds, sc, g, s); });
     if (e != hipSuccess || !sc.next) return e;
-    return varlen_launch(*sc.next, a, b, c, d, x, s);
+    return varlen_launch_tiled(*sc.next, a, b, c, d, x, s);
 }
 
 void varlen_free(VarlenSchedule *sc) {
@@ -541,6 +633,8 @@ void varlen_free(VarlenSchedule *sc) {
     });
     if (sc->dev) (void)hipFree(sc->dev);
     sc->dev = nullptr;
+    if (sc->long_ws) (void)hipFree(sc->long_ws);
+    sc->long_ws = nullptr;
     if (sc->next) {
         varlen_free(sc->next);
         delete sc->next;

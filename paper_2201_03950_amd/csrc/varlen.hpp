@@ -40,11 +40,20 @@ struct VarlenSchedule {
     // split schedule: the systems too long for a small-block variant run in
     // this launch, the rest in `next` (launched right after, same arrays)
     VarlenSchedule *next = nullptr;
+    // systems longer than kVarlenMaxTiled rows: solved one after another by the
+    // chunked solve (k_long.hip) after the persistent launch, with a workspace
+    // owned by the schedule (stable for captured graphs)
+    std::vector<i64> long_off, long_len;
+    void *long_ws = nullptr;
     // captured launches keyed by (a, b, c, d, x, stream), least recently used
     // evicted beyond the capacity
     using GraphKey = std::tuple<const void *, const void *, const void *, const void *, void *, hipStream_t>;
     LruMap<GraphKey, hipGraphExec_t> graphs{8};
 };
+
+// Longest system the persistent launch takes (one workgroup's tiles); longer
+// ones go to the chunked solve.
+constexpr i64 kVarlenMaxTiled = 8192;
 
 const std::vector<VarlenVariant> &varlen_variants(int prec);
 bool varlen_variant_fits(const VarlenVariant &v, i64 maxlen);

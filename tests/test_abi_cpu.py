@@ -98,8 +98,14 @@ def test_line_longer_than_limit_is_unsupported(lib, h):
     rc = lib.trid_gtsv_batched_s(h, 1, FAKE, FAKE, 1, _dims(8388609), 0, 1)
     assert rc == 4
     assert b"TRID_MAX_LONG_LINE" in lib.trid_last_error(h)
-    # the refinement and adjoint solves have no chunked form
-    rc = lib.trid_gtsv_batched_refine(h, 1, FAKE, FAKE, FAKE, FAKE, ctypes.c_void_p(0x2000), 1, _dims(8193), 0, 1)
+    # the refinement and adjoint solves take the chunked solve for contiguous
+    # lines too, and keep strided lines within one workgroup
+    rc = lib.trid_gtsv_batched_refine(h, 1, FAKE, FAKE, FAKE, FAKE, ctypes.c_void_p(0x2000), 1, _dims(8388609), 0, 1)
+    assert rc == 4
+    assert b"TRID_MAX_LONG_LINE" in lib.trid_last_error(h)
+    rc = lib.trid_gtsv_batched_refine(h, 1, FAKE, FAKE, FAKE, FAKE, ctypes.c_void_p(0x2000), 2, _dims(3, 8193), 1, 1)
+    assert rc == 4
+    rc = lib.trid_gtsv_batched_s_adjoint(h, 1, FAKE, FAKE, FAKE, FAKE, 2, _dims(3, 8193), 1, 1)
     assert rc == 4
     assert b"TRID_MAX_LINE" in lib.trid_last_error(h)
 
@@ -133,7 +139,7 @@ def test_varlen_argument_checks(lib, h):
     assert lib.trid_gtsv_varlen(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, off, 3) == 1
     off = (ctypes.c_int64 * 3)(1, 3, 7)  # offsets[0] != 0
     assert lib.trid_gtsv_varlen(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, off, 2) == 1
-    off = (ctypes.c_int64 * 2)(0, 9000)  # longer than TRID_MAX_LINE
+    off = (ctypes.c_int64 * 2)(0, 8388609)  # longer than TRID_MAX_LONG_LINE
     assert lib.trid_gtsv_varlen(h, 0, FAKE, FAKE, FAKE, FAKE, FAKE, off, 1) == 4
     off = (ctypes.c_int64 * 2)(0, 10)
     assert lib.trid_gtsv_varlen(h, 9, FAKE, FAKE, FAKE, FAKE, FAKE, off, 1) == 1  # bad precision

@@ -121,6 +121,17 @@ def varlen_batch(nsys=20000, lmin=32, lmax=8192, seed=SEEDS["varlen"]):
     float32 (these rounded values are the matrix of record); d stays float64.
     """
     lens, rng = varlen_lengths(nsys, lmin, lmax, seed)
+    return _varlen_pack(lens, rng)
+
+
+def varlen_batch_lengths(lengths, seed):
+    """Packed batch of systems with the given lengths (in that order), drawn as
+    ``varlen_batch`` draws them."""
+    return _varlen_pack(np.asarray(lengths, dtype=np.int64), np.random.default_rng(seed))
+
+
+def _varlen_pack(lens, rng):
+    nsys = len(lens)
     offsets = np.zeros(nsys + 1, dtype=np.int64)
     np.cumsum(lens, out=offsets[1:])
     total = int(offsets[-1])
