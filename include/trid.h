@@ -384,6 +384,20 @@ int trid_autotune_report(trid_handle_t h, char *buf, size_t len);
  * schedule).  Host only.  Errors: TRID_ERR_ARG (NULL buffer or too small). */
 int trid_cache_report(trid_handle_t h, char *buf, size_t len);
 
+/* The LDS layout of the resident 2D loops (trid_adi_step on small 2D meshes,
+ * hv != 0: trid_hv_step) for meshes of nx x ny points: out[0..9] = tile rows
+ * M, tiles per x line, tiles per y line, row pitch, skew added per block of M
+ * rows, pad element after every M points of a row (0/1), elements per array,
+ * HV coefficient arrays staged in LDS (0: none, 1: b, 2: a, b, c), threads
+ * per workgroup, LDS bytes per workgroup.  Point (y, x) of every array sits at
+ * y * pitch + (y / M) * skew + x + pad * (x / M) of that array; the arrays
+ * follow one another (u, then d (, s) or the HV stage arrays).  force_M = 0
+ * gives the automatic tile size; 8, 10, 12 or 14 forces one.  Host only (a
+ * layout query for tests and tools).  Errors: TRID_ERR_ARG (NULL out, len <
+ * 10, bad dtype or tile size), TRID_ERR_UNSUPPORTED (no layout fits). */
+int trid_resident_layout(trid_handle_t h, trid_dtype_t dt, int64_t nx, int64_t ny, int hv, int per_point_s,
+                         int force_M, int64_t *out, int len);
+
 /* ------------------------------------------------------------ plan cache -- */
 
 /* Load / save the tile-plan cache (JSON text: one entry per tuned key, each

@@ -55,6 +55,7 @@ SIGNATURES = {
                          ctypes.c_size_t], _I),
     "trid_autotune_report": ([_H, ctypes.c_char_p, ctypes.c_size_t], _I),
     "trid_cache_report": ([_H, ctypes.c_char_p, ctypes.c_size_t], _I),
+    "trid_resident_layout": ([_H, _I, _I64, _I64, _I, _I, _I, _I64P, _I], _I),
     "trid_hv_step": ([_H, _I, _P, _P, _P, _P, _D, _D, _I64P, _I64, _I, ctypes.c_uint], _I),
     "trid_adi_step_adjoint": ([_H, _I, _P, _P, _D, _P, _P, _I, _I64P, _I64], _I),
     "trid_adi_step_keep": ([_H, _I, _P, _P, _I, _I64P, _I64, _P, _P, _P], _I),

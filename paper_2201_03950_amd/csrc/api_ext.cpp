@@ -908,6 +908,25 @@ int trid_model_gtsv(trid_handle_t h, trid_dtype_t dt, int form, int ndim, const 
     return TRID_OK;
 }
 
+int trid_resident_layout(trid_handle_t h, trid_dtype_t dt, int64_t nx, int64_t ny, int hv, int per_point_s,
+                         int force_M, int64_t *out, int len) {
+    if (!h) return TRID_ERR_ARG;
+    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!out || len < 10) return trid::handle_fail(h, TRID_ERR_ARG, "out needs 10 entries");
+    if (force_M != 0 && force_M != 8 && force_M != 10 && force_M != 12 && force_M != 14)
+        return trid::handle_fail(h, TRID_ERR_ARG, "tile rows must be 0, 8, 10, 12 or 14");
+    trid::ResidentReq r;
+    r.f64 = dt == TRID_F64;
+    r.nx = nx;
+    r.ny = ny;
+    r.hv = hv != 0;
+    static const char one = 0;  // a non-NULL marker: the layout depends on whether s varies per point
+    r.s = (per_point_s && !r.hv) ? &one : nullptr;
+    if (!trid::resident_layout(r, force_M, out))
+        return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, "no resident layout for this mesh and tile size");
+    return TRID_OK;
+}
+
 int trid_autotune_report(trid_handle_t h, char *buf, size_t len) {
     if (!h) return TRID_ERR_ARG;
     if (!buf || len < 3) return trid::handle_fail(h, TRID_ERR_ARG, "buffer too small");

@@ -292,13 +292,14 @@ __global__ __launch_bounds__(max_threads(kRM)) void k_adi2d_resident(ResGeom g, 
             const int y = yb + t / g.px, p = t % g.px, x0 = p * kRM;
             const bool live = y < ny;
             const int ya = live ? y : 0;  // dead lanes address row 0
-            const int base = res_at<kRM>(g, ya, x0);
-            const int dn = res_at<kRM>(g, ya + 1, x0) - base, ds = base - res_at<kRM>(g, ya > 0 ? ya - 1 : 0, x0);
+            const int xc = x0 < nx ? x0 : 0;  // tiles past the line's end address column 0
+            const int base = res_at<kRM>(g, ya, xc);
+            const int dn = res_at<kRM>(g, ya + 1, xc) - base, ds = base - res_at<kRM>(g, ya > 0 ? ya - 1 : 0, xc);
             const bool hn = live && y + 1 < ny, hs = live && y > 0;
-            // guarded LDS reads fall back to the tile's own first point (always
-            // inside the array), so no lane addresses past it
+            // guarded LDS reads fall back to the tile's own first point (a point
+            // of the mesh), so no lane addresses outside the array
             T uc[kRM + 2];  // u of the tile's points and their x neighbours
-            uc[0] = load_if(U, base - 1 - g.tp, live && x0 > 0, base);
+            uc[0] = load_if(U, base - 1 - g.tp, live && x0 > 0 && x0 < nx, base);
 #pragma unroll
             for (int k = 0; k < kRM; ++k) uc[k + 1] = load_if(U, base + k, live && x0 + k < nx, base);
             uc[kRM + 1] = load_if(U, base + kRM + g.tp, live && x0 + kRM < nx, base);
@@ -394,10 +395,13 @@ __device__ __forceinline__ void hv_x_phase(const ResGeom &g, const HvCoef<T> &cf
         const int y = yb + t / g.px, p = t % g.px, x0 = p * kRM;
         const bool live = y < ny;
         const int ya = live ? y : 0;
-        const int base = res_at<kRM>(g, ya, x0);
-        const int dn = res_at<kRM>(g, ya + 1, x0) - base, ds = base - res_at<kRM>(g, ya > 0 ? ya - 1 : 0, x0);
+        // tiles past the line's end (identity tiles) address column 0, so every
+        // address, also of a guarded read's fallback, is a point of the mesh
+        const int xc = x0 < nx ? x0 : 0;
+        const int base = res_at<kRM>(g, ya, xc);
+        const int dn = res_at<kRM>(g, ya + 1, xc) - base, ds = base - res_at<kRM>(g, ya > 0 ? ya - 1 : 0, xc);
         const bool hn = live && y + 1 < ny, hs = live && y > 0;
-        const bool hw = live && x0 > 0, he = live && x0 + kRM < nx;
+        const bool hw = live && x0 > 0 && x0 < nx, he = live && x0 + kRM < nx;
         // rows y-1, y, y+1 over x0-1 .. x0+M (zero outside the mesh); guarded
         // reads fall back to the tile's own first point
         T vs[kRM + 2], vc[kRM + 2], vn[kRM + 2];
@@ -468,7 +472,7 @@ __device__ __forceinline__ void hv_y_phase(const ResGeom &g, const HvCoef<T> &cf
         T col[kRM + 2], rd[kRM], sv[kRM];
         int off[kRM];
         {
-            const bool v = live && y0 > 0;
+            const bool v = live && y0 > 0 && y0 < ny;  // the point above a tile inside the line
             const int o = res_at<kRM>(g, v ? y0 - 1 : 0, xa);
             col[0] = load_if(src, o, v, o);
         }
@@ -671,6 +675,24 @@ bool search_layout(const ResidentReq &r, ResGeom *out, size_t *bytes) {
     return false;
 }
 
+// The layout for a forced tile size (0: the automatic choice); no caching.
+bool search_layout_forced(const ResidentReq &r, int M, ResGeom *out, size_t *bytes) {
+    if (!M) return search_layout(r, out, bytes);
+    if (r.hv && search_layout_m(r, M, 6, out, bytes)) {
+        out->cl = 2;
+        return true;
+    }
+    if (r.hv && search_layout_m(r, M, 4, out, bytes)) {
+        out->cl = 1;
+        return true;
+    }
+    if (search_layout_m(r, M, (r.s || r.hv) ? 3 : 2, out, bytes)) {
+        out->cl = 0;
+        return true;
+    }
+    return false;
+}
+
 // Layouts are searched once per (nx, ny, precision, s form, HV or ADI) and kept.
 bool plan_resident(const ResidentReq &r, ResGeom *out, size_t *bytes) {
     if (r.nx < 1 || r.ny < 1 || r.nx > kMaxLine || r.ny > kMaxLine) return false;
@@ -739,6 +761,17 @@ hipError_t go_t(const ResidentReq &r, const ResGeom &g, size_t bytes, hipStream_
 }
 
 }  // namespace
+
+bool resident_layout(const ResidentReq &r, int force_M, int64_t out[10]) {
+    if (r.nx < 1 || r.ny < 1 || r.nx > kMaxLine || r.ny > kMaxLine) return false;
+    if (force_M != 0 && force_M != 8 && force_M != 10 && force_M != 12 && force_M != 14) return false;
+    ResGeom g;
+    size_t bytes = 0;
+    if (!search_layout_forced(r, force_M, &g, &bytes)) return false;
+    const int64_t v[10] = {g.m, g.px, g.py, g.ldx, g.skw, g.tp, g.region, g.cl, threads_of(g, r.hv), (int64_t)bytes};
+    for (int i = 0; i < 10; ++i) out[i] = v[i];
+    return true;
+}
 
 bool resident_fits(const ResidentReq &r) {
     ResGeom g;

@@ -25,6 +25,11 @@ struct ResidentReq {
 // Whether the request fits the resident kernel (lines of at most 128 points,
 // the mesh's arrays within one workgroup's LDS); no HIP calls.
 bool resident_fits(const ResidentReq &r);
+// The LDS layout the resident kernels use for r (tile size forced unless 0):
+// {tile rows, tiles per x line, tiles per y line, row pitch, skew per block of
+// tile rows, pad per tile, elements per array, coefficient arrays staged (HV),
+// threads per workgroup, LDS bytes}.  Host only.
+bool resident_layout(const ResidentReq &r, int force_M, int64_t out[10]);
 hipError_t launch_resident(const ResidentReq &r, hipStream_t s);
 
 }  // namespace trid
