@@ -59,6 +59,7 @@ struct LinePlan {
     int L = 0;
     int P = 0;
     bool staged = false;  // contiguous lines through LDS (axis 0)
+    bool lean = false;    // strided s-form lines, register-lean tiles (k_strided_lean)
     int ls = 0;           // staged: LDS elements per line
     size_t shmem = 0;     // dynamic LDS bytes
     i64 nblocks = 0;

@@ -25,6 +25,17 @@ constexpr int strided_max_threads(int M, int w, bool wide = false) {
 }
 constexpr size_t kMaxShmem = 64 * 1024;
 
+// Register-lean strided s-form solves (k_strided_lean): a thread keeps its
+// tile's s and d (and a wide epilogue's M prefetched words), so up to 1024
+// threads per block.  Used for lines of at least kLeanMinRows rows, where the
+// general kernel's tile state limits a block to few adjacent lines.
+constexpr int kLeanMinRows = 512;
+constexpr int lean_max_threads(int M, int w, bool wide) {
+    // 1024 threads (128 VGPRs) hold tiles of up to 64 bytes of s, and 16 FP64
+    // rows without a wide epilogue; larger tiles take 512
+    return (M * w <= 64 || (w == 8 && M == 16 && !wide)) ? 1024 : 512;
+}
+
 i64 cdiv(i64 a, i64 b) { return (a + b - 1) / b; }
 
 int pow2_floor(i64 v) {
@@ -81,6 +92,34 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
     }
     p.M = M;
     p.P = (int)P;
+    // strided lines of per-point s, long enough that the general kernel's
+    // block would hold few lines: the register-lean kernel, as many adjacent
+    // lines per block as its 1024 threads allow (longer row segments)
+    if (r.mode == Mode::S && r.inner > 1 && r.n >= kLeanMinRows && r.n * r.inner < ((i64)1 << 31) &&
+        (r.out == Out::Store || r.out == Out::Add || r.out == Out::AddKeep)) {
+        const int Ml = r.force_M ? r.force_M : 16;
+        const i64 Pl = cdiv(r.n, Ml);
+        const int lmaxt = lean_max_threads(Ml, w, wide);
+        if (Pl <= lmaxt) {
+            int L = r.force_L ? r.force_L : pow2_floor(lmaxt / Pl);
+            if (!r.force_L) {
+                if (r.inner < L) L = std::max(1, pow2_ceil(r.inner));
+                while (L > 4 && cdiv(r.inner, L) * r.outer < 512) L /= 2;
+            }
+            if ((i64)L * Pl <= lmaxt) {
+                p.M = Ml;
+                p.P = (int)Pl;
+                p.L = L;
+                p.lean = true;
+                p.shmem = (size_t)6 * L * Pl * w;
+                p.nblocks = cdiv(r.inner, L) * r.outer;
+                if (p.nblocks < (i64)1 << 31) {
+                    *pl = p;
+                    return true;
+                }
+            }
+        }
+    }
     const int regions = staged_regions(r.mode);
     const bool want_staged = r.inner == 1 && !r.force_strided &&
                              ((regions > 0 && r.out == Out::Store) || (adj_s && M <= 16)) &&
@@ -163,6 +202,30 @@ hipError_t strided_M(const LineReq &r, const LinePlan &pl, Src src, Epi epi, hip
     }
 }
 
+template <typename T, int M, int OUT>
+hipError_t go_lean(const LineReq &r, const LinePlan &pl, hipStream_t s) {
+    StridedGeom g;
+    g.inner = r.inner;
+    g.nib = cdiv(r.inner, pl.L);
+    g.n = (int)r.n;
+    g.L = pl.L;
+    g.P = pl.P;
+    constexpr int MAXT = lean_max_threads(M, (int)sizeof(T), OUT != 0);
+    launch((k_strided_lean<T, M, MAXT, OUT>), dim3((unsigned)pl.nblocks), dim3(pl.threads()), pl.shmem, s, g,
+           static_cast<const T *>(r.s), static_cast<const T *>(r.d), static_cast<T *>(r.x), static_cast<T *>(r.x2));
+    return hipGetLastError();
+}
+
+template <typename T, int OUT>
+hipError_t lean_M(const LineReq &r, const LinePlan &pl, hipStream_t s) {
+    switch (pl.M) {
+        case 8: return go_lean<T, 8, OUT>(r, pl, s);
+        case 16: return go_lean<T, 16, OUT>(r, pl, s);
+        case 32: return go_lean<T, 32, OUT>(r, pl, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T, int M, class Src>
 hipError_t go_staged(const LineReq &r, const LinePlan &pl, Src src, hipStream_t s) {
     StagedGeom g;
@@ -208,6 +271,14 @@ hipError_t launch_typed(const LineReq &r, const LinePlan &pl, hipStream_t s) {
     const T *c = static_cast<const T *>(r.c), *sp = static_cast<const T *>(r.s);
     const T *d = static_cast<const T *>(r.d);
     T *x = static_cast<T *>(r.x);
+    if (pl.lean) {
+        switch (r.out) {
+            case Out::Store: return lean_M<T, 0>(r, pl, s);
+            case Out::Add: return lean_M<T, 1>(r, pl, s);
+            case Out::AddKeep: return lean_M<T, 2>(r, pl, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (pl.staged && r.out == Out::AdjS) {
         switch (pl.M) {
             case 8: return go_staged_adj_s<T, 8>(r, pl, s);

@@ -356,6 +356,109 @@ __global__ __launch_bounds__(MAXT) void k_strided(StridedGeom gm, Src src, Epi e
     epi.template store<M>(pre, base, st, g0, gm.n, act, u);
 }
 
+// Register-lean strided solve of rows (-s, 1 + 2 s, -s): a thread keeps only
+// its tile's s and d (2 M words) in registers -- no per-row elimination state --
+// so blocks of up to 1024 threads cover more adjacent lines, and every row
+// access of a wavefront reads a longer contiguous segment.  The boundary
+// equations come from tile_ends_fn (two streaming sweeps), the reduced system
+// is solved as in k_strided, and the interior rows 1..M-2 are then solved by
+// Thomas (Alg. 1) with the tile's end values known, in place in the s and d
+// registers.  Rows are addressed by 32-bit offsets from the line's first
+// element (the host checks that a line spans less than 2^31 elements), so a
+// row's address costs no 64-bit register pair.
+// OUT: 0 x = solution; 1 x += solution; 2 x += solution and x2 = solution.
+template <typename T, int M, int MAXT, int OUT>
+__global__ __launch_bounds__(MAXT) void k_strided_lean(StridedGeom gm, const T *__restrict__ s,
+                                                       const T *__restrict__ d, T *__restrict__ x,
+                                                       T *__restrict__ x2) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sh = reinterpret_cast<T *>(smem_raw);
+    const int L = gm.L, P = gm.P, n = gm.n;
+    const int t = threadIdx.x, l = t % L, p = t / L;
+    const i64 blk = xcd_block_id();
+    const i64 ib = blk % gm.nib, ob = blk / gm.nib;
+    const i64 ii = ib * L + l;
+    const bool act = ii < gm.inner;
+    const unsigned st = (unsigned)gm.inner;
+    const i64 base = ob * (i64)n * (i64)gm.inner + (act ? ii : 0);
+    const T *sp = s + base;
+    const T *dp = d + base;
+    const int g0 = p * M;
+    T sv[M], dv[M], uo[OUT ? M : 1];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {  // rows past the line load its first row (values unused)
+        const int g = g0 + k;
+        const unsigned o = (act && g < n) ? (unsigned)g * st : 0u;
+        sv[k] = sp[o];
+        dv[k] = dp[o];
+        if constexpr (OUT != 0) uo[k] = x[base + o];
+    }
+    asm volatile("" ::: "memory");  // every load of the tile is issued before the first use
+    // rows past the line become identity rows (s = d = 0), whose solution is 0
+    // exactly, so the last row's c (coupling to them) and the first row's a
+    // (only in fa, whose coupling the reduced solve drops for the first tile)
+    // need no masks: every row is (-s, 1 + 2 s, -s)
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+        if (!(act && g0 + k < n)) sv[k] = dv[k] = T(0);
+    auto rows = [&](int k, T &a, T &b, T &c) {
+        const T sk = sv[k];
+        a = -sk;
+        b = T(1) + T(2) * sk;
+        c = -sk;
+    };
+    // each sweep regenerates the rows from s: the empty asm makes s look
+    // rewritten, so the compiler does not keep every row's (a, b, c) live
+    auto fence = [&] {
+#pragma unroll
+        for (int k = 0; k < M; ++k) asm volatile("" : "+v"(sv[k]));
+    };
+    TileEnds<T> e;
+    tile_ends_fn<T, M>(rows, dv, e, fence);
+    fence();
+    T f, lv;
+    reduced_solve<T, M>(e, sh, L * P, P, p, t, L, f, lv);
+    // interior rows with u_0 = f and u_{M-1} = lv known: c* into sv, d* into dv
+    T cprev = T(0), dprev = T(0);
+#pragma unroll
+    for (int k = 1; k < M - 1; ++k) {
+        T a, b, c;
+        rows(k, a, b, c);
+        T rhs = dv[k];
+        if (k == 1) {
+            rhs -= a * f;
+            a = T(0);
+        }
+        if (k == M - 2) {
+            rhs -= c * lv;
+            c = T(0);
+        }
+        const T r = fast_rcp(b - a * cprev);
+        cprev = c * r;
+        dprev = (rhs - a * dprev) * r;
+        sv[k] = cprev;
+        dv[k] = dprev;
+    }
+    dv[0] = f;
+    dv[M - 1] = lv;
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) dv[k] -= sv[k] * dv[k + 1];
+    T *xp = x + base;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int g = g0 + k;
+        if (act && g < n) {
+            const unsigned o = (unsigned)g * st;
+            if constexpr (OUT == 0) {
+                xp[o] = dv[k];
+            } else {
+                xp[o] = uo[k] + dv[k];
+                if constexpr (OUT == 2) x2[base + o] = dv[k];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------ staged kernel --
 
 struct StagedGeom {

@@ -81,15 +81,20 @@ __device__ __forceinline__ T row_from_upper(T v) {  // value of tile p + S
     return dpp_move<0x100 + S>(v);
 }
 
-// Result of the per-tile sweep (eq. (7)).
+// The tile's two boundary equations (eq. (7)), all the reduced solve needs:
 //   first row: fa*l_{p-1} + fb*f_p + fc*l_p = fd   (f_p, l_p: tile's first/last unknown)
 //   last row:  la*f_p + l_p + lc*f_{p+1} = ld
-//   interior:  ap[k]*f_p + u_k + cp[k]*l_p = dp[k], k = 1..M-2
-template <typename T, int M>
-struct TileState {
-    T ap[M], cp[M], dp[M];
+template <typename T>
+struct TileEnds {
     T fa, fb, fc, fd;
     T la, lc, ld;
+};
+
+// Result of the per-tile sweep: the boundary equations and the interior
+//   ap[k]*f_p + u_k + cp[k]*l_p = dp[k], k = 1..M-2
+template <typename T, int M>
+struct TileState : TileEnds<T> {
+    T ap[M], cp[M], dp[M];
 };
 
 // Forward then backward sweep of the modified Thomas algorithm on one tile.
@@ -168,7 +173,7 @@ __device__ __forceinline__ void tile_eliminate_fn(const Rows &rows, const T (&rd
 // block (it sets the number of PCR levels and barriers; lines of different
 // lengths may share a block).  Returns f (tile's first unknown) and lv (its last).
 template <typename T, int M>
-__device__ __forceinline__ void reduced_pcr(const TileState<T, M> &ts, T *__restrict__ sh, int S,
+__device__ __forceinline__ void reduced_pcr(const TileEnds<T> &ts, T *__restrict__ sh, int S,
                                             int P, int p, int slot, int pstride, T &f, T &lv,
                                             int Pu = 0) {
     if (Pu < P) Pu = P;
@@ -260,7 +265,7 @@ struct DppPcr {
 };
 
 template <typename T, int M, int P>
-__device__ __forceinline__ void reduced_pcr_dpp(const TileState<T, M> &ts, int p, T &f, T &lv) {
+__device__ __forceinline__ void reduced_pcr_dpp(const TileEnds<T> &ts, int p, T &f, T &lv) {
     T pa = row_from_lower<1>(ts.la), pc = row_from_lower<1>(ts.lc), pd = row_from_lower<1>(ts.ld);
     if (p == 0) pa = pc = pd = T(0);
     const T gsub = -ts.fa * pa;
@@ -289,7 +294,7 @@ __device__ __forceinline__ T lane_down(T v, int s) {  // value of lane + s
 }
 
 template <typename T, int M, int P>
-__device__ __forceinline__ void reduced_pcr_wave(const TileState<T, M> &ts, int p, T &f, T &lv) {
+__device__ __forceinline__ void reduced_pcr_wave(const TileEnds<T> &ts, int p, T &f, T &lv) {
     T pa = lane_up(ts.la, 1), pc = lane_up(ts.lc, 1), pd = lane_up(ts.ld, 1);
     if (p == 0) pa = pc = pd = T(0);
     const T gsub = -ts.fa * pa;
@@ -323,7 +328,7 @@ __device__ __forceinline__ void reduced_pcr_wave(const TileState<T, M> &ts, int 
 // P = 32 or 64 (a line never straddles two wavefronts); reduced_pcr otherwise.
 // Callers must not rely on a barrier inside (the lane forms have none).
 template <typename T, int M>
-__device__ __forceinline__ void reduced_solve(const TileState<T, M> &ts, T *__restrict__ sh, int S, int P,
+__device__ __forceinline__ void reduced_solve(const TileEnds<T> &ts, T *__restrict__ sh, int S, int P,
                                               int p, int slot, int pstride, T &f, T &lv) {
     if (pstride == 1) {
         switch (P) {
@@ -338,6 +343,51 @@ __device__ __forceinline__ void reduced_solve(const TileState<T, M> &ts, T *__re
         }
     }
     reduced_pcr<T, M>(ts, sh, S, P, p, slot, pstride, f, lv);
+}
+
+// The boundary equations alone, by two streaming sweeps that keep O(1) state
+// (the register-lean form of the tile sweep): forward elimination gives the
+// last row's relation to u_0 (as in tile_eliminate); a sweep from the tile's
+// end writes u_k = al_k u_{k-1} + be_k u_{M-1} + ga_k for k = M-2..1, which
+// put into row 0 gives the first row's relation.  rows(k, a, b, c) produces
+// row k; rd holds the right-hand side; between the sweeps fence() runs (a
+// caller that regenerates rows from a few registers uses it to keep the
+// compiler from holding every row's (a, b, c) in registers for the second).
+template <typename T, int M, class Rows, class Fence>
+__device__ __forceinline__ void tile_ends_fn(const Rows &rows, const T (&rd)[M], TileEnds<T> &e, Fence &&fence) {
+    static_assert(M >= 3, "tiles need at least three rows");
+    T a, b, c;
+    rows(1, a, b, c);
+    T r = fast_rcp(b);
+    T ap = a * r, cp = c * r, dp = rd[1] * r;
+#pragma unroll
+    for (int k = 2; k < M; ++k) {
+        rows(k, a, b, c);
+        r = fast_rcp(b - a * cp);
+        ap = -r * a * ap;
+        cp = r * c;
+        dp = r * (rd[k] - a * dp);
+    }
+    e.la = ap;
+    e.lc = cp;
+    e.ld = dp;
+    fence();
+    rows(M - 2, a, b, c);
+    r = fast_rcp(b);
+    T al = -a * r, be = -c * r, ga = rd[M - 2] * r;
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) {
+        rows(k, a, b, c);
+        r = fast_rcp(b + c * al);
+        be = -c * be * r;
+        ga = (rd[k] - c * ga) * r;
+        al = -a * r;
+    }
+    rows(0, a, b, c);
+    e.fa = a;
+    e.fb = b + c * al;
+    e.fc = c * be;
+    e.fd = rd[0] - c * ga;
 }
 
 // Back substitution (eq. (7)): the tile's M unknowns.
