@@ -60,6 +60,119 @@ __global__ __launch_bounds__(MAXT) void k_refine_strided(StridedGeom gm, RefPtrs
     }
 }
 
+// --------------------------------------------------------- strided, lean --
+// Rows (-s, 1 + 2 s, -s) from FP32 s on strided lines, with a thread's
+// registers holding only its tile's s, x32 and right-hand side: each FP32
+// solve finds the tile's boundary equations by two streaming sweeps
+// (tile_ends_fn), the reduced system as the other kernels do, and the
+// interior by Thomas (Alg. 1) with the tile's end values known.  d is read
+// again for the FP64 residual (from the caches: the block read it just
+// before), so it is not held in registers.  Rows past the line are identity
+// rows (s = d = 0, solution 0).  32-bit row offsets from the line's first
+// element (the host checks that a line spans less than 2^31 elements).
+template <typename TD, int M, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_refine_lean(StridedGeom gm, const float *__restrict__ s,
+                                                      const TD *__restrict__ d, double *__restrict__ x) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int L = gm.L, P = gm.P, S = L * P, n = gm.n;
+    float *red = reinterpret_cast<float *>(smem_raw);  // 6 S: reduced-solve scratch
+    float *xs = red + 6 * S;                           // S (M + 1): every tile's x32 (padded)
+    const int t = threadIdx.x, l = t % L, p = t / L;
+    const i64 blk = xcd_block_id();
+    const i64 ib = blk % gm.nib, ob = blk / gm.nib;
+    const i64 ii = ib * L + l;
+    const bool act = ii < gm.inner;
+    const unsigned st = (unsigned)gm.inner;
+    const i64 base = ob * (i64)n * (i64)gm.inner + (act ? ii : 0);
+    const float *sp = s + base;
+    const TD *dp = d + base;
+    const int g0 = p * M;
+    float sv[M], w[M], cs[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int g = g0 + k;
+        const unsigned o = (act && g < n) ? (unsigned)g * st : 0u;
+        sv[k] = sp[o];
+        w[k] = (float)dp[o];
+    }
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int k = 0; k < M; ++k)
+        if (!(act && g0 + k < n)) sv[k] = w[k] = 0.f;
+    auto rows = [&](int k, float &a, float &b, float &c) {
+        const float sk = sv[k];
+        a = -sk;
+        b = 1.f + 2.f * sk;
+        c = -sk;
+    };
+    auto fence = [&] {
+#pragma unroll
+        for (int k = 0; k < M; ++k) asm volatile("" : "+v"(sv[k]));
+    };
+    // one FP32 solve of the right-hand side in w, in place
+    auto solve32 = [&]() {
+        TileEnds<float> e;
+        tile_ends_fn<float, M>(rows, w, e, fence);
+        fence();
+        float f, lv;
+        reduced_solve<float, M>(e, red, S, P, p, t, L, f, lv);
+        float cprev = 0.f, dprev = 0.f;
+#pragma unroll
+        for (int k = 1; k < M - 1; ++k) {
+            float a, b, c;
+            rows(k, a, b, c);
+            float rhs = w[k];
+            if (k == 1) {
+                rhs -= a * f;
+                a = 0.f;
+            }
+            if (k == M - 2) {
+                rhs -= c * lv;
+                c = 0.f;
+            }
+            const float r = fast_rcp(b - a * cprev);
+            cprev = c * r;
+            dprev = (rhs - a * dprev) * r;
+            cs[k] = cprev;
+            w[k] = dprev;
+        }
+        w[0] = f;
+        w[M - 1] = lv;
+#pragma unroll
+        for (int k = M - 3; k >= 1; --k) w[k] -= cs[k] * w[k + 1];
+        fence();
+    };
+    solve32();
+    // x32 goes to LDS (tile t at t (M + 1)): the residual reads the tile's rows
+    // and the adjacent tiles' boundary rows (tiles p -+ 1 of the line are
+    // threads t -+ L) from there
+    float *xm = xs + t * (M + 1);
+#pragma unroll
+    for (int k = 0; k < M; ++k) xm[k] = w[k];
+    __syncthreads();
+    const double xprev = (p > 0) ? (double)xs[(t - L) * (M + 1) + M - 1] : 0.0;
+    const double xnext = (p + 1 < P) ? (double)xs[(t + L) * (M + 1)] : 0.0;
+    // r = d - A x32 in FP64, d read again
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int g = g0 + k;
+        const bool v = act && g < n;
+        const double dk = (double)dp[v ? (unsigned)g * st : 0u];
+        const double sk = (double)sv[k];
+        const double um = k > 0 ? (double)xm[k - 1] : xprev;
+        const double up = k < M - 1 ? (double)xm[k + 1] : xnext;
+        const double r = dk - (-sk * um + (1.0 + 2.0 * sk) * (double)xm[k] - sk * up);
+        w[k] = v ? (float)r : 0.f;
+    }
+    solve32();
+    double *xo = x + base;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int g = g0 + k;
+        if (act && g < n) xo[(unsigned)g * st] = (double)xm[k] + (double)w[k];
+    }
+}
+
 // -------------------------------------------------------------- staged --
 // x lines: the block's coefficient arrays and d are staged into LDS (tiles
 // padded to M + 1 elements); the FP64 result leaves through the same LDS area.
@@ -173,8 +286,34 @@ hipError_t go_staged(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename TD>
+hipError_t go_lean(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
+    StridedGeom g;
+    g.inner = r.inner;
+    g.nib = cdiv(r.inner, pl.L);
+    g.n = (int)r.n;
+    g.L = pl.L;
+    g.P = pl.P;
+    auto kern = k_refine_lean<TD, 16, 1024>;
+    if (pl.shmem > 64 * 1024) {
+        static bool raised = false;  // one attribute call per instantiation
+        if (!raised) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               160 * 1024);
+            if (e != hipSuccess) return e;
+            raised = true;
+        }
+    }
+    launch(kern, dim3((unsigned)pl.nblocks), dim3(pl.L * pl.P), pl.shmem, s, g, r.src.s,
+           static_cast<const TD *>(r.d), r.x);
+    return hipGetLastError();
+}
+
 template <typename TD, bool SM>
 hipError_t go_m(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
+    if constexpr (SM) {
+        if (pl.lean) return go_lean<TD>(r, pl, s);
+    }
     if (pl.staged) return pl.M == 32 ? go_staged<TD, 32, SM>(r, pl, s) : go_staged<TD, 16, SM>(r, pl, s);
     return pl.M == 32 ? go_strided<TD, 32, SM>(r, pl, s) : go_strided<TD, 16, SM>(r, pl, s);
 }
@@ -186,6 +325,30 @@ constexpr size_t kMaxShmem = 64 * 1024;
 bool plan_refine(const RefineReq &r, RefPlan *pl, std::string *err) {
     RefPlan p;
     const bool sm = r.smode;
+    // strided lines of per-point s of at least 512 rows: the register-lean
+    // kernel, 16-row tiles, as many adjacent lines as 1024 threads hold
+    if (sm && r.inner > 1 && r.n >= 512 && r.n * r.inner < ((i64)1 << 31) && (!r.force_M || r.force_M == 16)) {
+        const i64 P = cdiv(r.n, 16);
+        if (P <= 1024) {
+            int L = r.force_L ? r.force_L : pow2_floor(1024 / P);
+            if (!r.force_L) {
+                if (r.inner < L) L = std::max(1, pow2_ceil(r.inner));
+                while (L > 4 && cdiv(r.inner, L) * r.outer < 512) L /= 2;
+            }
+            if ((i64)L * P <= 1024) {
+                p.M = 16;
+                p.P = (int)P;
+                p.L = L;
+                p.lean = true;
+                p.shmem = (size_t)(6 + 17) * L * P * sizeof(float);
+                p.nblocks = cdiv(r.inner, L) * r.outer;
+                if (p.nblocks < (i64)1 << 31) {
+                    *pl = p;
+                    return true;
+                }
+            }
+        }
+    }
     // 16-row tiles up to 256 tiles per line (measured on 1024-row lines: 34%
     // faster than 32-row tiles through LDS, 3% on strided lines)
     int M = r.force_M ? r.force_M : 16;
