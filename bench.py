@@ -435,9 +435,17 @@ def extra_small_batched(trid):
                 u = torch.from_numpy(rng.uniform(0.0, 1.0, (batch, n, n, n))).to(dt).cuda()
                 t = time_calls(lambda: trid.adi_step(u, s0=0.2, nsteps=steps, graph=True), 2, warm=1)
                 pts = batch * n ** 3 * steps
+                # per-kernel split from one eager call of its own (events cost launch time)
+                trid.timing_enable(True)
+                trid.adi_step(u, s0=0.2, nsteps=steps)
+                kt = trid.timing_read()
+                trid.timing_enable(False)
+                words = {"adi_stencil_x": 2, "adi_y": 2, "adi_z_update": 3}
                 out["3d_%s_%d^3_x%d" % (tag, n, batch)] = {
                     "ms": round(t * 1e3, 3), "mpoint_steps_per_s": round(pts / t / 1e6, 1),
-                    "alg3_gbs": round(ALG3_WORDS[3] * w * pts / t / 1e9, 1)}
+                    "alg3_gbs": round(ALG3_WORDS[3] * w * pts / t / 1e9, 1),
+                    "kernel_gbs": {k: round(words[k] * w * batch * n ** 3 / (ms / cnt * 1e-3) / 1e9, 1)
+                                   for k, (cnt, ms) in kt.items() if k in words}}
                 del u
         log("small batched meshes %s done" % tag)
     return {"adi_small_batched": out}

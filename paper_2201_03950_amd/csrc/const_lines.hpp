@@ -155,7 +155,7 @@ __device__ __forceinline__ float vget<float>(const float4 &v, int j) {
 template <typename T>
 struct CStgCopy {
     const T *d;
-    template <int M, int N>
+    template <int M, int N, bool GUARD = false>
     __device__ __forceinline__ void stage(T *__restrict__ sh, const ConstStagedGeom &g, i64 o0, int nl,
                                           int *) const {
         using VT = typename Vec<T>::type;
@@ -217,7 +217,7 @@ struct CStgRhs {
     const T *u;
     T s2;  // 2 s0
     int ny, nz;
-    template <int M, int N>
+    template <int M, int N, bool GUARD = false>
     __device__ __forceinline__ void stage(T *__restrict__ sh, const ConstStagedGeom &g, i64 o0, int nl,
                                           int *) const {
         using VT = typename Vec<T>::type;
@@ -315,16 +315,19 @@ struct CStgRhs {
                 }
                 if (c == 0) left = T(0);
                 if (c == C - 1) right = T(0);
-                // ll < L always (the thread groups tile the block's L lines): rows
-                // past nl are written but never read, so the store needs no branch
+                // ll < L when the thread groups tile the block's L lines exactly
+                // (rows past nl are written but never read, so the store needs no
+                // branch); GUARD: groups past the block's L lines store nothing
                 T *dst = sh + ll * g.ls + ((c * VB) / M) * (M + 1) + ((c * VB) % M);
+                if (!GUARD || ll < g.L) {
 #pragma unroll
-                for (int e = 0; e < VB; ++e) {
-                    T acc = (jn[r] ? nx[i][e] : T(0)) + (jp[r] ? prev[e] : T(0));
-                    if (NDIM == 3) acc += zm[i][e] + zp[i][e];
-                    const T xl = e == 0 ? left : cur[e - 1];
-                    const T xr = e == VB - 1 ? right : cur[e + 1];
-                    dst[e] = s2 * (acc + xl + xr - T(2 * NDIM) * cur[e]);
+                    for (int e = 0; e < VB; ++e) {
+                        T acc = (jn[r] ? nx[i][e] : T(0)) + (jp[r] ? prev[e] : T(0));
+                        if (NDIM == 3) acc += zm[i][e] + zp[i][e];
+                        const T xl = e == 0 ? left : cur[e - 1];
+                        const T xr = e == VB - 1 ? right : cur[e + 1];
+                        dst[e] = s2 * (acc + xl + xr - T(2 * NDIM) * cur[e]);
+                    }
                 }
                 prev = cur;
                 cur = nx[i];
@@ -426,6 +429,81 @@ __global__ __launch_bounds__(256) void k_staged_dpp(ConstStagedGeom g, PcrTab<T>
             T *vp = reinterpret_cast<T *>(&v);
 #pragma unroll
             for (int j = 0; j < V; ++j) vp[j] = sp[j];
+            dst[ch] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------- staged, lane PCR --
+// x lines of P = n / M tiles, P in {3, 5, 6, 7} (Table 3's 48- to 112-point
+// lines): 64 / P whole lines per wavefront, the wavefront's last 64 % P lanes
+// idle, and the reduced system solved by PCR (Alg. 2) with lane moves through
+// the LDS crossbar and the same tabulated coefficients -- no barrier.  256
+// threads, L <= 4 (64 / P) lines per block (the planner also keeps L within
+// the lines the source's thread groups stage).
+template <typename T, int M, int P, class Src>
+__global__ __launch_bounds__(256) void k_staged_lanes(ConstStagedGeom g, PcrTab<T> tb, Src src,
+                                                      T *__restrict__ out) {
+    static_assert(P >= 3 && P <= 7 && (P & (P - 1)) != 0, "lane layout for P in {3, 5, 6, 7}");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sh = reinterpret_cast<T *>(smem_raw);
+    constexpr int n = P * M;
+    constexpr int G = 64 / P;
+    const int L = g.L;
+    int *flags = reinterpret_cast<int *>(sh + L * g.ls);
+    const int t = threadIdx.x, j = t & 63;
+    const int p = j % P, l = (t >> 6) * G + j / P;
+    const i64 o0 = xcd_block_id() * L;
+    const int nl = (int)((g.nlines - o0) < (i64)L ? (g.nlines - o0) : (i64)L);
+    src.template stage<M, n, true>(sh, g, o0, nl, flags);
+    __syncthreads();
+    const bool act = j < G * P && l < nl;
+    const int pos = (act ? l : 0) * g.ls + p * (M + 1);
+    T x[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const T val = sh[pos + k];
+        x[k] = act ? val : T(0);
+    }
+    T fd, ld;
+    const_tile_sweep<T, M>(tb, x, fd, ld);
+    T ldp = lane_up(ld, 1);
+    if (p == 0) ldp = T(0);
+    T d = tb.rg[p] * fd - tb.gA[p] * ldp - tb.gC[p] * ld;
+#pragma unroll
+    for (int lev = 0, S = 1; S < P; ++lev, S <<= 1) {
+        T dm = lane_up(d, S), dn = lane_down(d, S);
+        if (p < S) dm = T(0);
+        if (p + S >= P) dn = T(0);
+        d = tb.pr[lev][p] * d - tb.pa[lev][p] * dm - tb.pc[lev][p] * dn;
+    }
+    const T f = d;
+    T fn = lane_down(f, 1);
+    if (p + 1 >= P) fn = T(0);
+    const T lv = x[M - 1] - tb.la * f - ((p == P - 1) ? T(0) : tb.lc) * fn;
+    x[0] = f;
+    x[M - 1] = lv;
+#pragma unroll
+    for (int k = 1; k < M - 1; ++k) x[k] = x[k] - tb.apb[k] * f - tb.cpb[k] * lv;
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) sh[pos + k] = x[k];
+    }
+    __syncthreads();
+    using VT = typename Vec<T>::type;
+    constexpr int V = Vec<T>::n;
+    const int nc = nl * n / V;
+    VT *dst = reinterpret_cast<VT *>(out + o0 * n);
+#pragma unroll
+    for (int k = 0; k < M / V; ++k) {
+        const int ch = t + k * (int)blockDim.x;
+        if (ch < nc) {
+            const int e = ch * V, ll = e / n, i = e - ll * n;
+            const T *sp = sh + ll * g.ls + (i / M) * (M + 1) + (i % M);
+            VT v;
+            T *vp = reinterpret_cast<T *>(&v);
+#pragma unroll
+            for (int q = 0; q < V; ++q) vp[q] = sp[q];
             dst[ch] = v;
         }
     }

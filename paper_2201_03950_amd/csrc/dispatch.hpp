@@ -60,10 +60,11 @@ struct LinePlan {
     int P = 0;
     bool staged = false;  // contiguous lines through LDS (axis 0)
     bool lean = false;    // strided s-form lines, register-lean tiles (k_strided_lean)
+    bool lanes = false;   // 64 / P whole lines per wavefront, 256 threads (fused stencil + x)
     int ls = 0;           // staged: LDS elements per line
     size_t shmem = 0;     // dynamic LDS bytes
     i64 nblocks = 0;
-    int threads() const { return L * P; }
+    int threads() const { return lanes ? 256 : L * P; }
 };
 
 struct LineReq {

@@ -9,6 +9,10 @@
 // of lines o0 - 1 .. o0 + L is copied into LDS with 16-byte loads, and the x
 // and y neighbours of every point are read from there.  Only the two z
 // neighbours (3D) and s come from global memory, once per point each.
+//
+// Lines of P tiles, P not a power of two and at most 64, are laid out so that
+// none straddles two wavefronts (64 / P lines per wavefront); their reduced
+// systems are then solved by lane moves with no barrier.
 #include <algorithm>
 
 #include "dispatch.hpp"
@@ -21,7 +25,8 @@ struct RhsGeom {
     int n;       // x line length
     int L, P, ls;
     int ny, nz;  // lines of one mesh = ny * nz (nz = 1 in 2D)
-    int uoff;    // LDS element offset of the u window (later: staged s)
+    int uoff;    // LDS element offset of the u window
+    int soff;    // LDS element offset of the staged s (per-point s)
     int roff;    // LDS element offset of the reduced-solve scratch (first: line flags)
 };
 
@@ -54,20 +59,61 @@ __device__ __forceinline__ void copy_to_lds(T *__restrict__ dst, const T *__rest
     for (int e = done + t; e < cnt; e += nt) dst[e] = src[e];
 }
 
-template <typename T, int M, bool PP, int NDIM>
+// Staged elements back to global memory in index order (cnt <= blockDim * M):
+// all of a thread's LDS reads go out before its stores (idle slots read slot 0).
+template <typename T, int M>
+__device__ __forceinline__ void stage_out_all(T *__restrict__ dst, const T *__restrict__ src, int cnt, int n,
+                                              int ls) {
+    const int nt = blockDim.x;
+    int ll = threadIdx.x / n, i = threadIdx.x % n;
+    const int dl = nt / n, di = nt % n;
+    T v[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int e = threadIdx.x + k * nt;
+        v[k] = src[e < cnt ? staged_pos<M>(ll, i, ls) : 0];
+        ll += dl;
+        i += di;
+        if (i >= n) {
+            i -= n;
+            ++ll;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const int e = threadIdx.x + k * nt;
+        if (e < cnt) dst[e] = v[k];
+    }
+}
+
+template <typename T, int M, bool PP, int NDIM, bool WV>
 __global__ __launch_bounds__(256) void k_rhs_x(RhsGeom g, const T *__restrict__ u, const T *__restrict__ s,
                                                T s0, T *__restrict__ x) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *sh = reinterpret_cast<T *>(smem_raw);  // staged RHS, then the solution
-    T *uw = sh + g.uoff;                      // u window, then staged s
+    T *uw = sh + g.uoff;                      // u window
+    T *ss = sh + g.soff;                      // staged s (per-point s)
     T *red = sh + g.roff;
     int *flags = reinterpret_cast<int *>(red);
     const int L = g.L, P = g.P, n = g.n, ls = g.ls;
-    const int t = threadIdx.x, nt = blockDim.x, p = t % P, l = t / P;
+    const int t = threadIdx.x, nt = blockDim.x;
+    // thread -> (line l, tile p): P consecutive threads per line; with WV,
+    // 64 / P lines per wavefront and the wavefront's last 64 % P lanes idle
+    int p, l;
+    bool lane_ok = true;
+    if (WV) {
+        const int G = 64 / P, j = t & 63;
+        p = j % P;
+        l = (t >> 6) * G + j / P;
+        lane_ok = j < G * P;
+    } else {
+        p = t % P;
+        l = t / P;
+    }
     const i64 o0 = xcd_block_id() * L;
     const int nl = (int)((g.nlines - o0) < (i64)L ? (g.nlines - o0) : (i64)L);
-    const bool act = l < nl;
-    const int pos = l * ls + p * (M + 1);
+    const bool act = lane_ok && l < nl;
+    const int pos = (act ? l : 0) * ls + p * (M + 1);
 
     const i64 off = o0 * n;
     const i64 sz = (i64)g.ny * n;
@@ -118,34 +164,31 @@ __global__ __launch_bounds__(256) void k_rhs_x(RhsGeom g, const T *__restrict__ 
     }
     __syncthreads();
 
-    // RHS of every point: x, y neighbours from the window
-    T dv[M];
+    // RHS of every point: x, y neighbours from the window.  Every read is
+    // issued (idle slots and missing neighbours read in-window slots) and the
+    // unused values are selected away, so the reads overlap.
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int ll = lls[k], i = is[k];
         const bool v = t + k * nt < cnt;
-        const int f = v ? flags[ll] : 0;
-        const T *ur = uw + (ll + 1) * n + i;
-        const T c = v ? ur[0] : T(0);
+        const int f = flags[v ? ll : 0];
+        const int b = v ? (ll + 1) * n + i : n;  // b - n >= 0, b + n < (L + 2) n
+        const T c = uw[b], wm = uw[b - 1], wp = uw[b + 1], ym = uw[b - n], yp = uw[b + n];
         T acc = T(0);
         if (NDIM == 3) {
             acc += (f & 4) ? zl[k] : T(0);
             acc += (f & 8) ? zr[k] : T(0);
         }
-        acc += (v && i > 0) ? ur[-1] : T(0);
-        acc += (v && i < n - 1) ? ur[1] : T(0);
-        if (f & 1) acc += ur[-n];
-        if (f & 2) acc += ur[n];
+        acc += (v && i > 0) ? wm : T(0);
+        acc += (v && i < n - 1) ? wp : T(0);
+        acc += (f & 1) ? ym : T(0);
+        acc += (f & 2) ? yp : T(0);
         const T sk = PP ? sv[k] : s0;
-        dv[k] = T(2) * sk * (acc - T(2 * NDIM) * c);
-    }
-    __syncthreads();  // every window read is done: the window becomes the s region
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        if (t + k * nt < cnt) {
-            const int q = staged_pos<M>(lls[k], is[k], ls);
-            sh[q] = dv[k];
-            if (PP) uw[q] = sv[k];
+        const T dk = T(2) * sk * (acc - T(2 * NDIM) * c);
+        if (v) {
+            const int q = staged_pos<M>(ll, i, ls);
+            sh[q] = dk;
+            if (PP) ss[q] = sk;
         }
     }
     __syncthreads();
@@ -155,7 +198,7 @@ __global__ __launch_bounds__(256) void k_rhs_x(RhsGeom g, const T *__restrict__ 
         const int gi = p * M + k;
         const bool v = act && gi < n;
         const T dk = sh[pos + k];  // own tile slots: always inside the regions
-        const T sl = PP ? uw[pos + k] : s0;
+        const T sl = PP ? ss[pos + k] : s0;
         rd[k] = v ? dk : T(0);
         const T sk = v ? sl : T(0);
         ra[k] = (gi > 0) ? -sk : T(0);
@@ -163,13 +206,23 @@ __global__ __launch_bounds__(256) void k_rhs_x(RhsGeom g, const T *__restrict__ 
         rc[k] = (gi < n - 1) ? -sk : T(0);
     }
     T uu[M];
-    tile_solve<T, M>(ra, rb, rc, rd, red, L * P, P, p, t, 1, uu);
-    // each thread overwrites only the slots it took itself (no other thread
+    if (WV) {
+        TileState<T, M> ts;
+        tile_eliminate<T, M>(ra, rb, rc, rd, ts);
+        T f, lv;
+        reduced_pcr_lanes<T>(ts, p, P, f, lv);
+        tile_backsub<T, M>(ts, f, lv, uu);
+    } else {
+        tile_solve<T, M>(ra, rb, rc, rd, red, L * P, P, p, t, 1, uu);
+    }
+    // each thread overwrites only the slots it read itself (no other thread
     // reads them before the barrier below)
+    if (act) {
 #pragma unroll
-    for (int k = 0; k < M; ++k) sh[pos + k] = uu[k];
+        for (int k = 0; k < M; ++k) sh[pos + k] = uu[k];
+    }
     __syncthreads();
-    stage_out<T, M>(x + off, sh, cnt, n, ls);
+    stage_out_all<T, M>(x + off, sh, cnt, n, ls);
 }
 
 namespace {
@@ -179,22 +232,24 @@ constexpr size_t kMaxShmem = 160 * 1024;
 
 i64 cdiv(i64 a, i64 b) { return (a + b - 1) / b; }
 
-// LDS layout (elements): [staged RHS L*ls][u window (L+2)*n, >= L*ls with
-// per-point s][reduced scratch 6*L*P, >= L ints of flags], regions 16-byte aligned.
-size_t rhs_layout(int L, int P, int ls, int n, bool pp, int w, int *uoff, int *roff) {
+// LDS layout (elements): [staged RHS L*ls][u window (L+2)*n][staged s L*ls,
+// per-point s only][reduced scratch: 6*L*P unless the lines' reduced systems
+// are solved by lane moves, and at least L ints of flags], regions 16-byte
+// aligned.
+size_t rhs_layout(int L, int P, int ls, int n, bool pp, bool lanes, int w, int *uoff, int *soff, int *roff) {
     const int q = 16 / w;
     auto up = [&](i64 v) { return (v + q - 1) / q * q; };
-    i64 win = (i64)(L + 2) * n;
-    if (pp) win = std::max(win, (i64)L * ls);
     const i64 u0 = up((i64)L * ls);
-    const i64 r0 = up(u0 + win);
-    const i64 red = std::max((i64)6 * L * P, cdiv((i64)L * 4, w));
+    const i64 s0 = up(u0 + (i64)(L + 2) * n);
+    const i64 r0 = pp ? up(s0 + (i64)L * ls) : s0;
+    const i64 red = std::max(lanes ? (i64)0 : (i64)6 * L * P, cdiv((i64)L * 4, w));
     if (uoff) *uoff = (int)u0;
+    if (soff) *soff = (int)s0;
     if (roff) *roff = (int)r0;
     return (size_t)(r0 + red) * w;
 }
 
-template <typename T, int M, bool PP, int NDIM>
+template <typename T, int M, bool PP, int NDIM, bool WV>
 hipError_t go(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
     RhsGeom g;
     g.nlines = r.ny * r.nz * r.batch;
@@ -204,8 +259,8 @@ hipError_t go(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
     g.ls = pl.ls;
     g.ny = (int)r.ny;
     g.nz = (int)r.nz;
-    rhs_layout(pl.L, pl.P, pl.ls, g.n, PP, (int)sizeof(T), &g.uoff, &g.roff);
-    auto kern = k_rhs_x<T, M, PP, NDIM>;
+    rhs_layout(pl.L, pl.P, pl.ls, g.n, PP, WV, (int)sizeof(T), &g.uoff, &g.soff, &g.roff);
+    auto kern = k_rhs_x<T, M, PP, NDIM, WV>;
     if (pl.shmem > 64 * 1024) {
         static bool raised = false;  // one attribute call per instantiation
         if (!raised) {
@@ -221,18 +276,18 @@ hipError_t go(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, int M>
+template <typename T, int M, bool WV>
 hipError_t go_m(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
     const bool pp = r.s != nullptr;
-    if (r.ndim == 3) return pp ? go<T, M, true, 3>(r, pl, s) : go<T, M, false, 3>(r, pl, s);
-    return pp ? go<T, M, true, 2>(r, pl, s) : go<T, M, false, 2>(r, pl, s);
+    if (r.ndim == 3) return pp ? go<T, M, true, 3, WV>(r, pl, s) : go<T, M, false, 3, WV>(r, pl, s);
+    return pp ? go<T, M, true, 2, WV>(r, pl, s) : go<T, M, false, 2, WV>(r, pl, s);
 }
 
 template <typename T>
 hipError_t go_t(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
     switch (pl.M) {
-        case 8: return go_m<T, 8>(r, pl, s);
-        case 16: return go_m<T, 16>(r, pl, s);
+        case 8: return pl.lanes ? go_m<T, 8, true>(r, pl, s) : go_m<T, 8, false>(r, pl, s);
+        case 16: return pl.lanes ? go_m<T, 16, true>(r, pl, s) : go_m<T, 16, false>(r, pl, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -255,11 +310,17 @@ bool plan_rhs_x(const AdiReq &r, LinePlan *pl, std::string *err) {
         return false;
     }
     const int ls = (int)P * (M + 1);
-    int L = r.force_L ? r.force_L : std::max(1, kMaxThreads / (int)P);
+    // lines of P tiles, P not a power of two, at most 64: whole lines per
+    // wavefront (reduced systems by lane moves); otherwise P threads per line
+    const bool lanes = P <= 64 && (P & (P - 1)) != 0;
+    const int Lmax = lanes ? (kMaxThreads / 64) * (64 / (int)P) : kMaxThreads / (int)P;
+    int L = r.force_L ? r.force_L : std::max(1, Lmax);
     const bool pp = r.s != nullptr;
-    auto bytes = [&](int LL) { return rhs_layout(LL, (int)P, ls, (int)r.nx, pp, w, nullptr, nullptr); };
+    auto bytes = [&](int LL) {
+        return rhs_layout(LL, (int)P, ls, (int)r.nx, pp, lanes, w, nullptr, nullptr, nullptr);
+    };
     while (bytes(L) > kMaxShmem && L > 1) L /= 2;
-    if (bytes(L) > kMaxShmem || (i64)L * P > kMaxThreads) {
+    if (bytes(L) > kMaxShmem || L > Lmax) {
         *err = "fused stencil + x solve does not fit in LDS";
         return false;
     }
@@ -267,6 +328,7 @@ bool plan_rhs_x(const AdiReq &r, LinePlan *pl, std::string *err) {
     p.P = (int)P;
     p.L = L;
     p.staged = true;
+    p.lanes = lanes;
     p.ls = ls;
     p.shmem = bytes(L);
     p.nblocks = cdiv(r.ny * r.nz * r.batch, L);

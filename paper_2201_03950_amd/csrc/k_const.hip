@@ -1,5 +1,6 @@
 // k_const.hip -- host tables and launches of the constant-coefficient line
 // solves (strided y / z lines, staged x lines, and the ADI stencil + x solve).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -90,7 +91,7 @@ template bool make_const_tab<float>(double, double, double, int, int, ConstTab<f
 
 template <typename T>
 bool make_pcr_tab(double a, double b, double c, int M, int P, PcrTab<T> *t) {
-    if (P > kDppMaxP || (P & (P - 1)) != 0) return false;
+    if (P < 1 || P > kDppMaxP) return false;
     ConstTab<T> ct;
     if (!make_const_tab<T>(a, b, c, M, 1, &ct)) return false;  // tile tables (P = 1: no W needed)
     std::memset(static_cast<void *>(t), 0, sizeof(*t));
@@ -192,6 +193,28 @@ hipError_t go_dpp(i64 nlines, int n, const PcrTab<T> &tb, Src src, T *out, int f
     return hipGetLastError();
 }
 
+// Lines of P in {3, 5, 6, 7} tiles: 256 threads, L = 4 (64 / P) lines, or
+// fewer when the source's thread groups stage fewer (the right-hand-side
+// source gives each group of C = n / VB threads LG = M / VB lines, VB = one or
+// two 16-byte vectors).
+template <typename T, int M, int P, class Src>
+hipError_t go_lanes(i64 nlines, int n, const PcrTab<T> &tb, Src src, T *out, int force_L, hipStream_t s) {
+    ConstStagedGeom g;
+    g.nlines = nlines;
+    g.n = n;
+    constexpr int V = 16 / (int)sizeof(T);
+    const int VB = (n / V > 64 ? 2 : 1) * V;
+    int L = 4 * (64 / P);
+    L = std::min(L, (256 / (n / VB)) * (M / VB));
+    if (force_L > 0 && force_L < L) L = force_L;
+    g.L = L;
+    g.ls = P * (M + 1);
+    const size_t shm = (size_t)g.L * g.ls * sizeof(T) + (size_t)g.L * sizeof(int);
+    launch((k_staged_lanes<T, M, P, Src>), dim3((unsigned)cdiv(nlines, g.L)), dim3(256), shm, s, g, tb, src,
+           out);
+    return hipGetLastError();
+}
+
 template <typename T, int M, class Src>
 hipError_t go_dpp_p(i64 nlines, int n, const PcrTab<T> &tb, int P, Src src, T *out, int fl, hipStream_t s) {
     switch (P) {
@@ -200,6 +223,10 @@ hipError_t go_dpp_p(i64 nlines, int n, const PcrTab<T> &tb, int P, Src src, T *o
         case 4: return go_dpp<T, M, 4>(nlines, n, tb, src, out, fl, s);
         case 8: return go_dpp<T, M, 8>(nlines, n, tb, src, out, fl, s);
         case 16: return go_dpp<T, M, 16>(nlines, n, tb, src, out, fl, s);
+        case 3: return go_lanes<T, M, 3>(nlines, n, tb, src, out, fl, s);
+        case 5: return go_lanes<T, M, 5>(nlines, n, tb, src, out, fl, s);
+        case 6: return go_lanes<T, M, 6>(nlines, n, tb, src, out, fl, s);
+        case 7: return go_lanes<T, M, 7>(nlines, n, tb, src, out, fl, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -230,15 +257,19 @@ int const_M(i64 n, int force_M) {
     return 0;
 }
 
-// Tile rows for constant rows on staged x lines (DPP reduced solve): P = n / M
-// a power of two <= 16; prefer 128 bytes of tile per thread (M w = 128).
+// Tile rows for constant rows on staged x lines: P = n / M a power of two <=
+// 16 (DPP reduced solve), else P in {3, 5, 6, 7} (whole lines per wavefront,
+// lane-move reduced solve); prefer 128 bytes of tile per thread (M w = 128).
 int const_staged_M(i64 n, int w, int force_M) {
     const int pref[2] = {128 / w, 128 / w == 16 ? 32 : 16};
-    for (int M : pref) {
-        if (force_M && M != force_M) continue;
-        if (n % M) continue;
-        const i64 P = n / M;
-        if (P >= 1 && P <= kDppMaxP && (P & (P - 1)) == 0) return M;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int M : pref) {
+            if (force_M && M != force_M) continue;
+            if (n % M) continue;
+            const i64 P = n / M;
+            if (pass == 0 && P >= 1 && P <= kDppMaxP && (P & (P - 1)) == 0) return M;
+            if (pass == 1 && (P == 3 || P == 5 || P == 6 || P == 7)) return M;
+        }
     }
     return 0;
 }

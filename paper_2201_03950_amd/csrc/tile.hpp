@@ -322,6 +322,38 @@ __device__ __forceinline__ void reduced_pcr_wave(const TileEnds<T> &ts, int p, T
     lv = ts.ld - ts.la * f - ts.lc * fn;
 }
 
+// The same reduced solve with P (any value up to 64) known only at run time:
+// the line's tiles sit in P adjacent lanes of one wavefront (callers lay lines
+// out so that none straddles two wavefronts), the lane moves go through the
+// LDS crossbar, and no barrier or LDS storage is involved.
+template <typename T>
+__device__ __forceinline__ void reduced_pcr_lanes(const TileEnds<T> &ts, int p, int P, T &f, T &lv) {
+    T pa = lane_up(ts.la, 1), pc = lane_up(ts.lc, 1), pd = lane_up(ts.ld, 1);
+    if (p == 0) pa = pc = pd = T(0);
+    const T gsub = -ts.fa * pa;
+    const T gdia = ts.fb - ts.fa * pc - ts.fc * ts.la;
+    const T gsup = -ts.fc * ts.lc;
+    const T grhs = ts.fd - ts.fa * pd - ts.fc * ts.ld;
+    const T rg = fast_rcp(gdia);
+    T a = gsub * rg, c = gsup * rg, d = grhs * rg;
+    for (int S = 1; S < P; S <<= 1) {
+        T am = lane_up(a, S), cm = lane_up(c, S), dm = lane_up(d, S);
+        T an = lane_down(a, S), cn = lane_down(c, S), dn = lane_down(d, S);
+        if (p < S) am = cm = dm = T(0);
+        if (p + S >= P) an = cn = dn = T(0);
+        const T r = fast_rcp(T(1) - a * cm - c * an);
+        const T na = -r * (a * am);
+        const T nc = -r * (c * cn);
+        d = r * (d - a * dm - c * dn);
+        a = na;
+        c = nc;
+    }
+    f = d;
+    T fn = lane_down(f, 1);
+    if (p + 1 >= P) fn = T(0);
+    lv = ts.ld - ts.la * f - ts.lc * fn;
+}
+
 // Reduced solve dispatch (a uniform choice: P is the same for the whole
 // launch).  With the line's tiles in adjacent lanes (pstride 1, slot = line *
 // P + p): DPP row shifts for P a power of two <= 16, wavefront lane moves for

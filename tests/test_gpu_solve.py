@@ -338,6 +338,25 @@ def test_staged_x_every_reduced_form(trid, orc, dt, M, n):
     assert _field_err(tu.cpu().numpy().astype(np.float64), ref_u) <= TOL[dt]
 
 
+# fused stencil + x solve with whole lines per wavefront (P = nx / 8 tiles not a
+# power of two): Table 3's 48..112-point meshes and a two-lines-per-wavefront
+# length, per-point and constant s, ragged last blocks
+RHS_LANES = [((80, 7, 5), 2), ((96, 5, 3), 3), ((112, 3, 4), 2), ((48, 9, 2), 2), ((200, 4, 3), 1),
+             ((80, 11), 3)]
+
+
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("perpoint", [False, True])
+@pytest.mark.parametrize("dims,batch", RHS_LANES, ids=[str(g) for g in RHS_LANES])
+def test_rhs_x_whole_lines_per_wavefront(trid, orc, dt, perpoint, dims, batch):
+    u = gen.adi3d_field(dims, batch, seed=dims[0]).astype(dt)
+    s = (0.2 * np.random.default_rng(dims[1]).lognormal(0.0, 0.5, u.shape)).astype(dt) if perpoint else None
+    ref = orc.adi_step(u, s=s, s0=0.2, nsteps=2)
+    tu = _t(u)
+    trid.adi_step(tu, s=_t(s) if s is not None else None, s0=0.2, nsteps=2, stream=True)
+    assert _field_err(tu.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
+
+
 # x lines take the LDS-staged transposed solve: line lengths across the tile
 # sizes and the one-line-per-block limit, line counts with a ragged last block
 S_ADJ_X = [(1, 7), (2, 5), (8, 33), (9, 70), (33, 9), (64, 21), (100, 10), (128, 19), (255, 13), (256, 40),
@@ -366,7 +385,8 @@ def test_s_adjoint_x_lines(trid, orc, dt, n, lines):
 # ------------------------------------------------ constant-row fast path ----
 
 CONST_GEOMS = [((64, 96, 32), 2, 0), ((64, 96, 32), 2, 1), ((64, 96, 32), 2, 2),
-               ((256, 3), 5, 0), ((100, 256), 1, 1), ((70, 3, 128), 1, 2), ((32,), 7, 0)]
+               ((256, 3), 5, 0), ((100, 256), 1, 1), ((70, 3, 128), 1, 2), ((32,), 7, 0),
+               ((80, 7), 3, 0), ((96, 5, 3), 2, 0), ((48, 9), 4, 0), ((112, 3), 5, 0), ((160, 3), 2, 0)]
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
