@@ -61,10 +61,11 @@ struct LinePlan {
     bool staged = false;  // contiguous lines through LDS (axis 0)
     bool lean = false;    // strided s-form lines, register-lean tiles (k_strided_lean)
     bool lanes = false;   // 64 / P whole lines per wavefront, 256 threads (fused stencil + x)
+    bool vec = false;     // fused stencil + x, n = P M: 16-byte register-window staging (k_rhs_pp)
     int ls = 0;           // staged: LDS elements per line
     size_t shmem = 0;     // dynamic LDS bytes
     i64 nblocks = 0;
-    int threads() const { return lanes ? 256 : L * P; }
+    int threads() const { return (lanes || vec) ? 256 : L * P; }
 };
 
 struct LineReq {

@@ -15,6 +15,7 @@
 // systems are then solved by lane moves with no barrier.
 #include <algorithm>
 
+#include "const_lines.hpp"
 #include "dispatch.hpp"
 #include "lines.hpp"
 
@@ -225,12 +226,192 @@ __global__ __launch_bounds__(256) void k_rhs_x(RhsGeom g, const T *__restrict__ 
     stage_out_all<T, M>(x + off, sh, cnt, n, ls);
 }
 
+// Per-point s with lines of exactly P tiles of 8 rows (P a power of two up to
+// 64, or 6, 10, 12, 14 with whole lines per wavefront): the stencil part L u
+// is staged by the register-window source of the constant-row kernels (y
+// neighbours from the thread's own previous and next line, x neighbours by
+// lane moves, z neighbours and the rows by 16-byte loads, no LDS window), s
+// is read by each thread for its own tile with 16-byte loads, and the rows
+// (-s, 1 + 2 s, -s) and d = 2 s L u are formed in registers.  One barrier
+// before the solve, one before the 16-byte stores of the result.
+template <typename T, int M, int P, int NDIM>
+__global__ __launch_bounds__(256) void k_rhs_pp(ConstStagedGeom g, CStgRhs<T, NDIM> src, const T *__restrict__ s,
+                                                T *__restrict__ out) {
+    using VT = typename Vec<T>::type;
+    constexpr int V = Vec<T>::n;
+    static_assert(M % V == 0 && M >= 3, "tiles of whole 16-byte vectors");
+    constexpr bool LANES = (P & (P - 1)) != 0;
+    static_assert(P <= 64, "a line's tiles stay in one wavefront");
+    constexpr int n = P * M;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sh = reinterpret_cast<T *>(smem_raw);
+    const int L = g.L, t = threadIdx.x;
+    int p, l;
+    bool lane_ok = true;
+    if constexpr (LANES) {
+        constexpr int G = 64 / P;
+        const int j = t & 63;
+        p = j % P;
+        l = (t >> 6) * G + j / P;
+        lane_ok = j < G * P;
+    } else {
+        p = t % P;
+        l = t / P;
+    }
+    const i64 o0 = xcd_block_id() * L;
+    const int nl = (int)((g.nlines - o0) < (i64)L ? (g.nlines - o0) : (i64)L);
+    const bool act = lane_ok && l < nl;
+    // s of the thread's own tile (idle threads read the block's first tile)
+    VT sv4[M / V];
+    {
+        const VT *s4 = reinterpret_cast<const VT *>(s + (o0 + (act ? l : 0)) * n + (act ? p * M : 0));
+#pragma unroll
+        for (int q = 0; q < M / V; ++q) sv4[q] = s4[q];
+    }
+    src.template stage<M, n, LANES>(sh, g, o0, nl, nullptr);
+    __syncthreads();
+    const int pos = (act ? l : 0) * g.ls + p * (M + 1);
+    T sk[M], rd[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const T sv = vget<T>(sv4[k / V], k % V);
+        const T lu = sh[pos + k];
+        sk[k] = act ? sv : T(0);
+        rd[k] = act ? T(2) * sv * lu : T(0);
+    }
+    auto rows = [&](int k, T &a, T &b, T &c) {
+        const int gi = p * M + k;
+        a = gi > 0 ? -sk[k] : T(0);
+        b = T(1) + T(2) * sk[k];
+        c = gi < n - 1 ? -sk[k] : T(0);
+    };
+    TileState<T, M> ts;
+    tile_eliminate_fn<T, M>(rows, rd, ts);
+    T f, lv;
+    if constexpr (LANES)
+        reduced_pcr_lanes<T>(ts, p, P, f, lv);
+    else if constexpr (P <= 16)
+        reduced_pcr_dpp<T, M, P>(ts, p, f, lv);
+    else
+        reduced_pcr_wave<T, M, P>(ts, p, f, lv);
+    T uu[M];
+    tile_backsub<T, M>(ts, f, lv, uu);
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) sh[pos + k] = uu[k];
+    }
+    __syncthreads();
+    const int nc = nl * n / V;
+    VT *dst = reinterpret_cast<VT *>(out + o0 * n);
+#pragma unroll
+    for (int k = 0; k < M / V; ++k) {
+        const int ch = t + k * 256;
+        if (ch < nc) {
+            const int e = ch * V, ll = e / n, i = e - ll * n;
+            const T *sp = sh + ll * g.ls + (i / M) * (M + 1) + (i % M);
+            VT v;
+            T *vp = reinterpret_cast<T *>(&v);
+#pragma unroll
+            for (int q = 0; q < V; ++q) vp[q] = sp[q];
+            dst[ch] = v;
+        }
+    }
+}
+
 namespace {
 
 constexpr int kMaxThreads = 256;
-constexpr size_t kMaxShmem = 160 * 1024;
+constexpr int kPpM = 8;  // tile rows of k_rhs_pp
 
 i64 cdiv(i64 a, i64 b) { return (a + b - 1) / b; }
+
+// Lines per block of k_rhs_pp: 256 / P, or 4 (64 / P) whole lines per
+// wavefront, within the lines the staging source's thread groups cover (each
+// group of C = n / VB threads stages LG = M / VB lines, VB = one or two
+// 16-byte vectors).  0 when the source cannot stage them.
+int pp_lines(int n, int P, int w) {
+    const int V = 16 / w;
+    const int VB = (n / V > 64 ? 2 : 1) * V;
+    const int C = n / VB, LG = kPpM / VB;
+    if (C < 1 || C > 256 || LG < 1) return 0;
+    const int staged = (256 / C) * LG;
+    const bool lanes = (P & (P - 1)) != 0;
+    const int L = lanes ? std::min(4 * (64 / P), staged) : 256 / P;
+    return L <= staged ? L : 0;
+}
+
+bool pp_supported_P(i64 P) {
+    switch (P) {
+        case 4: case 6: case 8: case 10: case 12: case 14: case 16: case 32: case 64: return true;
+        default: return false;
+    }
+}
+
+template <typename T, int P, int NDIM>
+hipError_t go_pp(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
+    ConstStagedGeom g;
+    g.nlines = r.ny * r.nz * r.batch;
+    g.n = (int)r.nx;
+    g.L = pl.L;
+    g.ls = pl.ls;
+    CStgRhs<T, NDIM> src{static_cast<const T *>(r.u), T(1), (int)r.ny, NDIM == 3 ? (int)r.nz : 1};
+    launch(k_rhs_pp<T, kPpM, P, NDIM>, dim3((unsigned)pl.nblocks), dim3(256), pl.shmem, s, g, src,
+           static_cast<const T *>(r.s), static_cast<T *>(r.d));
+    return hipGetLastError();
+}
+
+template <typename T, int NDIM>
+hipError_t go_pp_p(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
+    switch (pl.P) {
+        case 4: return go_pp<T, 4, NDIM>(r, pl, s);
+        case 6: return go_pp<T, 6, NDIM>(r, pl, s);
+        case 8: return go_pp<T, 8, NDIM>(r, pl, s);
+        case 10: return go_pp<T, 10, NDIM>(r, pl, s);
+        case 12: return go_pp<T, 12, NDIM>(r, pl, s);
+        case 14: return go_pp<T, 14, NDIM>(r, pl, s);
+        case 16: return go_pp<T, 16, NDIM>(r, pl, s);
+        case 32: return go_pp<T, 32, NDIM>(r, pl, s);
+        case 64: return go_pp<T, 64, NDIM>(r, pl, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t go_pp_t(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
+    return r.ndim == 3 ? go_pp_p<T, 3>(r, pl, s) : go_pp_p<T, 2>(r, pl, s);
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+// k_rhs_pp takes per-point s, lines of exactly P tiles of 8 rows with a
+// supported P, 16-byte aligned arrays and 32-bit byte offsets (the staging
+// source's addressing).
+bool plan_pp(const AdiReq &r, LinePlan *pl) {
+    const int w = r.f64 ? 8 : 4;
+    if (!r.s || (r.force_M && r.force_M != kPpM) || r.nx % kPpM) return false;
+    if (r.nx * r.ny * r.nz * r.batch * w >= ((i64)1 << 32)) return false;
+    if (!aligned16(r.u) || !aligned16(r.s) || !aligned16(r.d)) return false;
+    const i64 P = r.nx / kPpM;
+    if (!pp_supported_P(P)) return false;
+    const bool lanes = (P & (P - 1)) != 0;
+    int L = pp_lines((int)r.nx, (int)P, w);
+    if (!L) return false;
+    if (lanes && r.force_L > 0 && r.force_L < L) L = r.force_L;  // fewer whole lines per wavefront
+    LinePlan p;
+    p.M = kPpM;
+    p.P = (int)P;
+    p.L = L;
+    p.staged = true;
+    p.vec = true;
+    p.lanes = lanes;
+    p.ls = (int)P * (kPpM + 1);
+    p.shmem = (size_t)L * p.ls * w;
+    p.nblocks = cdiv(r.ny * r.nz * r.batch, L);
+    if (p.nblocks >= (i64)1 << 31) return false;
+    *pl = p;
+    return true;
+}
+constexpr size_t kMaxShmem = 160 * 1024;
 
 // LDS layout (elements): [staged RHS L*ls][u window (L+2)*n][staged s L*ls,
 // per-point s only][reduced scratch: 6*L*P unless the lines' reduced systems
@@ -295,6 +476,7 @@ hipError_t go_t(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
 }  // namespace
 
 bool plan_rhs_x(const AdiReq &r, LinePlan *pl, std::string *err) {
+    if (plan_pp(r, pl)) return true;
     const int w = r.f64 ? 8 : 4;
     LinePlan p;
     // 8-row tiles: the block then holds few enough lines that several blocks
@@ -341,6 +523,7 @@ bool plan_rhs_x(const AdiReq &r, LinePlan *pl, std::string *err) {
 }
 
 hipError_t launch_rhs_x(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
+    if (pl.vec) return r.f64 ? go_pp_t<double>(r, pl, s) : go_pp_t<float>(r, pl, s);
     return r.f64 ? go_t<double>(r, pl, s) : go_t<float>(r, pl, s);
 }
 
