@@ -124,7 +124,29 @@ __global__ __launch_bounds__(64 * kConstMaxP) void k_strided_const(StridedGeom g
 struct ConstStagedGeom {
     i64 nlines;
     int n, L, ls;
+    // Block order of the 3D stencil sources (Y = 0: block b takes lines
+    // b L ..).  With Y = ny / L blocks per plane, each mesh's planes are taken
+    // in slabs of zc planes, and inside a slab the blocks of one y range run
+    // through the slab's planes one after another: a block's z-neighbour rows
+    // are the rows the previous and next block stage, and its y-neighbour rows
+    // those of the blocks zc places away, so the L2 of the XCD that runs a
+    // contiguous range of blocks serves them instead of HBM.
+    int Y = 0, ny = 1, nz = 1, zc = 1;
 };
+
+// First line of logical block b (see ConstStagedGeom).
+__device__ __forceinline__ i64 staged_block_origin(const ConstStagedGeom &g, i64 b) {
+    if (g.Y == 0) return b * g.L;
+    const i64 per_mesh = (i64)g.Y * g.nz;
+    const i64 m = b / per_mesh;
+    const int bm = (int)(b - m * per_mesh);
+    const int slab = bm / (g.Y * g.zc);
+    const int r = bm - slab * g.Y * g.zc;
+    const int z0 = slab * g.zc;
+    const int zc = g.nz - z0 < g.zc ? g.nz - z0 : g.zc;
+    const int yb = r / zc, z = z0 + (r - yb * zc);
+    return (m * g.nz + z) * (i64)g.ny + (i64)yb * g.L;
+}
 
 // Vector width (elements per 16-byte access).
 template <typename T>
@@ -155,6 +177,7 @@ __device__ __forceinline__ float vget<float>(const float4 &v, int j) {
 template <typename T>
 struct CStgCopy {
     const T *d;
+    void block_order(ConstStagedGeom &) const {}  // independent lines: natural order
     template <int M, int N, bool GUARD = false>
     __device__ __forceinline__ void stage(T *__restrict__ sh, const ConstStagedGeom &g, i64 o0, int nl,
                                           int *) const {
@@ -217,6 +240,15 @@ struct CStgRhs {
     const T *u;
     T s2;  // 2 s0
     int ny, nz;
+    // Host: slab block order (ConstStagedGeom) for 3D meshes whose planes hold
+    // whole blocks; slabs of up to 64 planes.
+    void block_order(ConstStagedGeom &g) const {
+        if (NDIM != 3 || nz < 2 || ny % g.L) return;
+        g.Y = ny / g.L;
+        g.ny = ny;
+        g.nz = nz;
+        g.zc = nz < 64 ? nz : 64;
+    }
     template <int M, int N, bool GUARD = false>
     __device__ __forceinline__ void stage(T *__restrict__ sh, const ConstStagedGeom &g, i64 o0, int nl,
                                           int *) const {
@@ -386,7 +418,7 @@ __global__ __launch_bounds__(256) void k_staged_dpp(ConstStagedGeom g, PcrTab<T>
     const int L = g.L;
     int *flags = reinterpret_cast<int *>(sh + L * g.ls);
     const int t = threadIdx.x, p = t % P, l = t / P;
-    const i64 o0 = xcd_block_id() * L;
+    const i64 o0 = staged_block_origin(g, xcd_block_id());
     const int nl = (int)((g.nlines - o0) < (i64)L ? (g.nlines - o0) : (i64)L);
     src.template stage<M, n>(sh, g, o0, nl, flags);
     __syncthreads();
@@ -453,7 +485,7 @@ __global__ __launch_bounds__(256) void k_staged_lanes(ConstStagedGeom g, PcrTab<
     int *flags = reinterpret_cast<int *>(sh + L * g.ls);
     const int t = threadIdx.x, j = t & 63;
     const int p = j % P, l = (t >> 6) * G + j / P;
-    const i64 o0 = xcd_block_id() * L;
+    const i64 o0 = staged_block_origin(g, xcd_block_id());
     const int nl = (int)((g.nlines - o0) < (i64)L ? (g.nlines - o0) : (i64)L);
     src.template stage<M, n, true>(sh, g, o0, nl, flags);
     __syncthreads();

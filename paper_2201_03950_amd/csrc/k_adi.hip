@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void k_rhs_pp(ConstStagedGeom g, CStgRhs<T, ND
         p = t % P;
         l = t / P;
     }
-    const i64 o0 = xcd_block_id() * L;
+    const i64 o0 = staged_block_origin(g, xcd_block_id());
     const int nl = (int)((g.nlines - o0) < (i64)L ? (g.nlines - o0) : (i64)L);
     const bool act = lane_ok && l < nl;
     // s of the thread's own tile (idle threads read the block's first tile)
@@ -355,6 +355,7 @@ hipError_t go_pp(const AdiReq &r, const LinePlan &pl, hipStream_t s) {
     g.L = pl.L;
     g.ls = pl.ls;
     CStgRhs<T, NDIM> src{static_cast<const T *>(r.u), T(1), (int)r.ny, NDIM == 3 ? (int)r.nz : 1};
+    src.block_order(g);
     launch(k_rhs_pp<T, kPpM, P, NDIM>, dim3((unsigned)pl.nblocks), dim3(256), pl.shmem, s, g, src,
            static_cast<const T *>(r.s), static_cast<T *>(r.d));
     return hipGetLastError();

@@ -187,6 +187,7 @@ hipError_t go_dpp(i64 nlines, int n, const PcrTab<T> &tb, Src src, T *out, int f
     if (force_L > 0 && force_L * P <= 256 && (force_L * P) % 64 == 0) nt = force_L * P;
     g.L = nt / P;
     g.ls = P * (M + 1);
+    src.block_order(g);
     const size_t shm = (size_t)g.L * g.ls * sizeof(T) + (size_t)g.L * sizeof(int);
     launch((k_staged_dpp<T, M, P, Src>), dim3((unsigned)cdiv(nlines, g.L)), dim3(g.L * P),
                        shm, s, g, tb, src, out);
@@ -209,6 +210,7 @@ hipError_t go_lanes(i64 nlines, int n, const PcrTab<T> &tb, Src src, T *out, int
     if (force_L > 0 && force_L < L) L = force_L;
     g.L = L;
     g.ls = P * (M + 1);
+    src.block_order(g);
     const size_t shm = (size_t)g.L * g.ls * sizeof(T) + (size_t)g.L * sizeof(int);
     launch((k_staged_lanes<T, M, P, Src>), dim3((unsigned)cdiv(nlines, g.L)), dim3(256), shm, s, g, tb, src,
            out);
