@@ -431,24 +431,46 @@ def extra_small_batched(trid):
                 del u0, u
         for n in (32, 48, 64, 80, 96):
             for batch in (24, 72):
-                steps = 100
-                u = torch.from_numpy(rng.uniform(0.0, 1.0, (batch, n, n, n))).to(dt).cuda()
-                t = time_calls(lambda: trid.adi_step(u, s0=0.2, nsteps=steps, graph=True), 2, warm=1)
-                pts = batch * n ** 3 * steps
-                # per-kernel split from one eager call of its own (events cost launch time)
-                trid.timing_enable(True)
-                trid.adi_step(u, s0=0.2, nsteps=steps)
-                kt = trid.timing_read()
-                trid.timing_enable(False)
-                words = {"adi_stencil_x": 2, "adi_y": 2, "adi_z_update": 3}
-                out["3d_%s_%d^3_x%d" % (tag, n, batch)] = {
-                    "ms": round(t * 1e3, 3), "mpoint_steps_per_s": round(pts / t / 1e6, 1),
-                    "alg3_gbs": round(ALG3_WORDS[3] * w * pts / t / 1e9, 1),
-                    "kernel_gbs": {k: round(words[k] * w * batch * n ** 3 / (ms / cnt * 1e-3) / 1e9, 1)
-                                   for k, (cnt, ms) in kt.items() if k in words}}
-                del u
+                out["3d_%s_%d^3_x%d" % (tag, n, batch)] = small3d_case(trid, dt, n, batch, 100, rng)
         log("small batched meshes %s done" % tag)
     return {"adi_small_batched": out}
+
+
+def small3d_case(trid, dt, n, batch, steps, rng):
+    """One 3D batched-mesh case: graph-replayed time of `steps` steps and the
+    per-kernel split of one eager call (bandwidths count each kernel's
+    algorithmic words: stencil + x 2, y 2, z + update 3)."""
+    import torch
+
+    w = 4 if dt == torch.float32 else 8
+    u = torch.from_numpy(rng.uniform(0.0, 1.0, (batch, n, n, n))).to(dt).cuda()
+    t = time_calls(lambda: trid.adi_step(u, s0=0.2, nsteps=steps, graph=True), 2, warm=1)
+    pts = batch * n ** 3 * steps
+    trid.timing_enable(True)  # events cost launch time: a call of its own
+    trid.adi_step(u, s0=0.2, nsteps=steps)
+    kt = trid.timing_read()
+    trid.timing_enable(False)
+    words = {"adi_stencil_x": 2, "adi_y": 2, "adi_z_update": 3}
+    res = {"ms": round(t * 1e3, 3), "mpoint_steps_per_s": round(pts / t / 1e6, 1),
+           "alg3_gbs": round(ALG3_WORDS[3] * w * pts / t / 1e9, 1),
+           "kernel_us": {k: round(ms / cnt * 1e3, 2) for k, (cnt, ms) in kt.items() if k in words},
+           "kernel_gbs": {k: round(words[k] * w * batch * n ** 3 / (ms / cnt * 1e-3) / 1e9, 1)
+                          for k, (cnt, ms) in kt.items() if k in words}}
+    del u
+    return res
+
+
+def extra_small3d(n):
+    """Leg factory: n^3 meshes x 72 (Table 3's largest 3D batch), FP64 and FP32,
+    20 steps, s = 0.2 -- one shape per leg so that a profile of the leg covers it alone."""
+    def leg(trid):
+        import numpy as np
+        import torch
+
+        rng = np.random.default_rng(n)
+        return {"adi3d_%dcubed_x72" % n: {tag: small3d_case(trid, dt, n, 72, 20, rng)
+                                          for dt, tag in ((torch.float64, "f64"), (torch.float32, "f32"))}}
+    return leg
 
 
 # Mesh words per point and HV step that the stand-in's kernels must move: the
@@ -779,6 +801,47 @@ def pmc_copy_calibration():
 COPY_ELEMS = 1 << 26  # 512 MiB of float64
 
 
+def pmc_read(d, counter):
+    """Per-kernel-name list of a counter's per-dispatch values (bytes) from a rocprofv3 --pmc run."""
+    import csv
+    import glob
+
+    per = {}
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+    return per
+
+
+def pmc_copy_scale(per):
+    """Known bytes of the calibration copy over what the counter reports for it
+    (the largest device-to-device copy dispatch of the run)."""
+    vals = [x for k, v in per.items() if "copyBuffer" in k for x in v]
+    return COPY_ELEMS * 8.0 / max(vals)
+
+
+def pmc_table(fetch_dir, write_dir):
+    """Markdown table: launches and copy-scaled FETCH / WRITE bytes per launch of
+    every library kernel in two rocprofv3 --pmc runs."""
+    fetch, write = pmc_read(fetch_dir, "FETCH_SIZE"), pmc_read(write_dir, "WRITE_SIZE")
+    kf, kw = pmc_copy_scale(fetch), pmc_copy_scale(write)
+    print("| kernel | launches | FETCH (MB/launch) | WRITE (MB/launch) | total (MB/launch) |")
+    print("|---|---|---|---|---|")
+    for k in sorted(fetch):
+        if "trid::" not in k:
+            continue
+        f = sum(fetch[k]) / len(fetch[k]) * kf
+        wv = write.get(k, [0.0])
+        w = sum(wv) / len(wv) * kw
+        name = k.replace("(anonymous namespace)::", "").split("(")[0].replace("trid::", "").replace("void ", "")
+        print("| `%s` | %d | %.2f | %.2f | %.2f |" % (name, len(fetch[k]),
+                                                     f / 1e6, w / 1e6, (f + w) / 1e6))
+    print("copy calibration factors: fetch %.4f, write %.4f" % (kf, kw))
+
+
 def ingest_pmc(fetch_dir, write_dir):
     """Turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) into HBM bytes per launch.
 
@@ -786,28 +849,9 @@ def ingest_pmc(fetch_dir, write_dir):
     (COPY_ELEMS float64 read and written once) to what the counter reports for it.
     Writes TRAFFIC_FILE (tagged with the current source hash) and prints a table.
     """
-    import csv
-    import glob
-
-    def read(d, counter):
-        per = {}
-        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
-            with open(path) as f:
-                for r in csv.DictReader(f):
-                    if r["Counter_Name"] != counter:
-                        continue
-                    per.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
-        return per
-
-    fetch, write = read(fetch_dir, "FETCH_SIZE"), read(write_dir, "WRITE_SIZE")
+    fetch, write = pmc_read(fetch_dir, "FETCH_SIZE"), pmc_read(write_dir, "WRITE_SIZE")
     known = COPY_ELEMS * 8.0
-
-    def copy_value(per):
-        # the calibration copy: the largest device-to-device copy dispatch of the run
-        vals = [x for k, v in per.items() if "copyBuffer" in k for x in v]
-        return max(vals)
-
-    kf, kw = known / copy_value(fetch), known / copy_value(write)
+    kf, kw = pmc_copy_scale(fetch), pmc_copy_scale(write)
     names = {"StgRhs": "adi_stencil_x", "EpiAdd": "adi_z_update", "EpiStore": "adi_y"}
     rec = {"source_hash": kernel_source_hash(), "copy_scale_fetch": kf, "copy_scale_write": kw,
            "copy_bytes": known, "kernels": {}}
@@ -879,7 +923,8 @@ def cpu_baseline(budget_s=12.0, max_steps=60):
 # The other workloads, each a function of the loaded binding returning {name: result}.
 EXTRA_LEGS = {"adi2d_64x1024sq_xy": extra_2d, "varlen_20000": extra_varlen,
               "diff_adi3d_128_20steps": extra_gradient, "long_64x1M_f64": extra_long,
-              "adi_small_batched": extra_small_batched, "hv_slv": extra_hv, "perf_model": extra_perf_model}
+              "adi_small_batched": extra_small_batched, "hv_slv": extra_hv, "perf_model": extra_perf_model,
+              "adi3d_80cubed_x72": extra_small3d(80), "adi3d_96cubed_x72": extra_small3d(96)}
 
 
 def main():
@@ -895,9 +940,15 @@ def main():
                     help="write the HBM-traffic summary from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--only", choices=sorted(EXTRA_LEGS),
                     help="run one of the other workloads alone, print its JSON and exit (for profiling)")
+    ap.add_argument("--pmc-table", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print copy-scaled HBM bytes per launch of every library kernel of two "
+                         "rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc)
+        return
+    if args.pmc_table:
+        pmc_table(*args.pmc_table)
         return
     if args.gpus != 1:
         print("bench.py: only one GPU is measured; --gpus %d is not supported "
@@ -909,11 +960,11 @@ def main():
 
     trid.load_library()
     torch.cuda.init()
+    if args.pmc_copy:
+        pmc_copy_calibration()
     if args.only:
         print(json.dumps(EXTRA_LEGS[args.only](trid)))
         return
-    if args.pmc_copy:
-        pmc_copy_calibration()
     log("main workload: 256^3 FP64 ADI, %d warmup + %d timed steps" % (args.warmup, args.steps))
     main_run = adi_main(trid, args.steps, args.warmup)
     log("main done: %.3f ms/step" % (main_run["elapsed"] / args.steps * 1e3))
