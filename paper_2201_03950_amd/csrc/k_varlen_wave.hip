@@ -227,7 +227,7 @@ __device__ __forceinline__ void pcr_level3(int S, int q, int Q, T &a, T &c, T &d
 // Reduced solve of the short systems of a wavefront: f (tile's first unknown)
 // and lv (its last) from the tile sweep's state.
 template <typename T, int M>
-__device__ __forceinline__ void vlw_short(const TileState<T, M> &ts, const LanePlace &L, T &f, T &lv) {
+__device__ __forceinline__ void vlw_short(const TileEnds<T> &ts, const LanePlace &L, T &f, T &lv) {
     T pa = up1(ts.la), pc = up1(ts.lc), pd = up1(ts.ld);
     if (L.p == 0) pa = pc = pd = T(0);
     const T gsub = -ts.fa * pa;
@@ -249,7 +249,7 @@ __device__ __forceinline__ void vlw_short(const TileState<T, M> &ts, const LaneP
 // Schur rows (lane 0: the F row, lane 63: the L row) as (sub, dia, sup, rhs)
 // into xrow[0..3] (F row) and xrow[4..7] (L row) of the exchange buffer.
 template <typename T, int M>
-__device__ __forceinline__ void vlw_long_chain(const TileState<T, M> &ts, int lane, T &y, T &v, T &w,
+__device__ __forceinline__ void vlw_long_chain(const TileEnds<T> &ts, int lane, T &y, T &v, T &w,
                                                T *__restrict__ xrow) {
     const T pa = up1(ts.la), pc = up1(ts.lc), pd = up1(ts.ld);
     T gsub = T(0), gdia = T(1), gsup = T(0), grhs = T(0), vr = T(0), wr = T(0);
@@ -500,14 +500,26 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
             wave_sync();
         }
         // two FP32 solves; the second has the FP64 residual as right-hand side
+        // and reuses the first one's tile factor (no pivots again)
         float x32[M];
         float rhs[M];
 #pragma unroll
         for (int k = 0; k < M; ++k) rhs[k] = (float)dd[k];
+        TileFactor<float, M> fct;
+        float dp[M];
 #pragma unroll
         for (int pass = 0; pass < 2; ++pass) {
-            TileState<float, M> ts;
-            tile_eliminate<float, M>(ra, rb, rc, rhs, ts);
+            TileEnds<float> ts;
+            if (pass == 0) {
+                auto rows = [&](int k, float &a, float &b, float &c) {
+                    a = ra[k];
+                    b = rb[k];
+                    c = rc[k];
+                };
+                tile_factor_fn<float, M>(rows, rhs, fct, dp, ts);
+            } else {
+                tile_factor_rhs<float, M>(fct, rhs, dp, ts);
+            }
             float f, lv, y = 0.f, v = 0.f, wv = 0.f;
             float *xb = xbuf + (pass * 2 + par) * (2 * NW * 4);
             if (lng)
@@ -530,7 +542,7 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
                 lv = lane == WL - 1 ? Lw : ts.ld - ts.la * f - ts.lc * fn;
             }
             float u[M];
-            tile_backsub<float, M>(ts, f, lv, u);
+            tile_factor_backsub<float, M>(fct, dp, f, lv, u);
             if (pass == 0) {
                 // r = d - A x32 in FP64; the neighbours of the tile's first and
                 // last rows come from the adjacent lanes, or across wavefronts

@@ -63,15 +63,30 @@ __device__ __forceinline__ void refine_tile(const RefCoef<M, SM> &cf, const doub
 #pragma unroll
     for (int k = 0; k < M; ++k) rd[k] = (float)dd[k];
     float x32[M];
-    {
+    // the tile factor of the first solve serves the correction solve too
+    // (16-row tiles; 32-row tiles sweep again, their factor would not fit
+    // in registers beside the rows)
+    constexpr bool kKeep = M <= 16;
+    TileFactor<float, kKeep ? M : 3> fct;
+    float dp[kKeep ? M : 3];
+    if constexpr (!kKeep) {
         TileState<float, M> ts;
         tile_eliminate_fn<float, M>(rows, rd, ts);
+        float f, lv;
+        if (Pu)
+            reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv, Pu);
+        else
+            reduced_solve<float, M>(ts, red, S, P, p, slot, pstride, f, lv);
+        tile_backsub<float, M>(ts, f, lv, x32);
+    } else {
+        TileEnds<float> ts;
+        tile_factor_fn<float, M>(rows, rd, fct, dp, ts);
         float f, lv;
         if (Pu)  // lines of different lengths share the block (uneven batch)
             reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv, Pu);
         else
             reduced_solve<float, M>(ts, red, S, P, p, slot, pstride, f, lv);
-        tile_backsub<float, M>(ts, f, lv, x32);
+        tile_factor_backsub<float, M>(fct, dp, f, lv, x32);
     }
     // neighbours of the tile's first and last rows for the residual
     xb[slot] = x32[0];
@@ -89,15 +104,24 @@ __device__ __forceinline__ void refine_tile(const RefCoef<M, SM> &cf, const doub
         rd[k] = (float)(dd[k] - (a * xm + b * (double)x32[k] + c * xp));
     }
     float dx[M];
-    {
+    if constexpr (!kKeep) {
         TileState<float, M> ts;
         tile_eliminate_fn<float, M>(rows, rd, ts);
+        float f, lv;
+        if (Pu)
+            reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv, Pu);
+        else
+            reduced_solve<float, M>(ts, red, S, P, p, slot, pstride, f, lv);
+        tile_backsub<float, M>(ts, f, lv, dx);
+    } else {
+        TileEnds<float> ts;
+        tile_factor_rhs<float, M>(fct, rd, dp, ts);
         float f, lv;
         if (Pu)  // lines of different lengths share the block (uneven batch)
             reduced_pcr<float, M>(ts, red, S, P, p, slot, pstride, f, lv, Pu);
         else
             reduced_solve<float, M>(ts, red, S, P, p, slot, pstride, f, lv);
-        tile_backsub<float, M>(ts, f, lv, dx);
+        tile_factor_backsub<float, M>(fct, dp, f, lv, dx);
     }
 #pragma unroll
     for (int k = 0; k < M; ++k) out[k] = (double)x32[k] + (double)dx[k];

@@ -164,6 +164,107 @@ __device__ __forceinline__ void tile_eliminate_fn(const Rows &rows, const T (&rd
     s.fd = rd[0] - c * s.dp[1];
 }
 
+// The coefficient part of the tile sweep of eq. (7), kept so that a second
+// right-hand side with the same rows (the correction solve of the mixed-
+// precision refinement) needs no pivots again: only the right-hand-side
+// recurrences and the back substitution.
+//   forward  : d'_1 = r_1 d_1, d'_k = r_k d_k - m_k d'_{k-1}   (m_k = r_k a_k)
+//   backward : d'_k -= cf_k d'_{k+1}, k = M-3 .. 1             (cf_k = r_k c_k)
+//   first row: fd = d_0 - c0 d'_1
+// The back-substitution factors follow from (m, cf) by one product each.
+template <typename T, int M>
+struct TileFactor {
+    T r[M], m[M], cf[M];
+    T fa, fb, fc, c0, la, lc;
+};
+
+// Full sweep of rows(k, a, b, c) with right-hand side rd: the factor, the
+// interior right-hand sides dp (d'_k, k = 1 .. M-2, after both sweeps) and the
+// tile's end relations.
+template <typename T, int M, class Rows>
+__device__ __forceinline__ void tile_factor_fn(const Rows &rows, const T (&rd)[M], TileFactor<T, M> &fc,
+                                               T (&dp)[M], TileEnds<T> &e) {
+    static_assert(M >= 3, "tiles need at least three rows");
+    T a, b, c;
+    rows(1, a, b, c);
+    fc.r[1] = fast_rcp(b);
+    fc.m[1] = a * fc.r[1];  // the forward u_0 factor of row 1
+    fc.cf[1] = c * fc.r[1];
+    dp[1] = rd[1] * fc.r[1];
+    T ap = fc.m[1];
+#pragma unroll
+    for (int k = 2; k < M; ++k) {
+        rows(k, a, b, c);
+        const T r = fast_rcp(b - a * fc.cf[k - 1]);
+        fc.r[k] = r;
+        fc.m[k] = r * a;
+        fc.cf[k] = r * c;
+        ap = -fc.m[k] * ap;
+        dp[k] = r * rd[k] - fc.m[k] * dp[k - 1];
+    }
+    e.la = fc.la = ap;
+    e.lc = fc.lc = fc.cf[M - 1];
+    e.ld = dp[M - 1];
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) dp[k] -= fc.cf[k] * dp[k + 1];
+    // first-row factors: final u_0 and u_{M-1} coefficients of row 1
+    T apf[M], cpf = fc.cf[M - 2];
+    apf[1] = fc.m[1];
+#pragma unroll
+    for (int k = 2; k < M - 1; ++k) apf[k] = -fc.m[k] * apf[k - 1];
+    T apF = apf[M - 2];
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) {
+        apF = apf[k] - fc.cf[k] * apF;
+        cpf = -fc.cf[k] * cpf;
+    }
+    rows(0, a, b, c);
+    fc.c0 = c;
+    e.fa = fc.fa = a;
+    e.fb = fc.fb = b - c * apF;
+    e.fc = fc.fc = -c * cpf;
+    e.fd = rd[0] - c * dp[1];
+}
+
+// A further right-hand side rd through a kept factor: dp and the end relations.
+template <typename T, int M>
+__device__ __forceinline__ void tile_factor_rhs(const TileFactor<T, M> &fc, const T (&rd)[M], T (&dp)[M],
+                                                TileEnds<T> &e) {
+    dp[1] = fc.r[1] * rd[1];
+#pragma unroll
+    for (int k = 2; k < M; ++k) dp[k] = fc.r[k] * rd[k] - fc.m[k] * dp[k - 1];
+    e.la = fc.la;
+    e.lc = fc.lc;
+    e.ld = dp[M - 1];
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) dp[k] -= fc.cf[k] * dp[k + 1];
+    e.fa = fc.fa;
+    e.fb = fc.fb;
+    e.fc = fc.fc;
+    e.fd = rd[0] - fc.c0 * dp[1];
+}
+
+// Back substitution (eq. (7)) through a factor: u_k = d'_k - ap_k u_0 - cp_k
+// u_{M-1}, the final factors ap_k, cp_k rebuilt from (m, cf).
+template <typename T, int M>
+__device__ __forceinline__ void tile_factor_backsub(const TileFactor<T, M> &fc, const T (&dp)[M], T f, T lv,
+                                                    T (&u)[M]) {
+    T apf[M];
+    apf[1] = fc.m[1];
+#pragma unroll
+    for (int k = 2; k < M - 1; ++k) apf[k] = -fc.m[k] * apf[k - 1];
+    u[0] = f;
+    u[M - 1] = lv;
+    T apF = apf[M - 2], cpF = fc.cf[M - 2];
+    u[M - 2] = dp[M - 2] - apF * f - cpF * lv;
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) {
+        apF = apf[k] - fc.cf[k] * apF;
+        cpF = -fc.cf[k] * cpF;
+        u[k] = dp[k] - apF * f - cpF * lv;
+    }
+}
+
 // Reduced solve of one line across its P tiles.
 //   sh      : LDS scratch of 6*S elements, S = number of threads of the block
 //   slot    : this thread's slot in [0, S)
