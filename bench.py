@@ -628,7 +628,68 @@ def extra_perf_model(trid):
                      "within_25pct": round(float((verrs <= 0.25).mean()), 3),
                      "top3_best_over_best": prune}
     log("model validation: uneven batches done")
+    res["adi"] = adi_model_validation(trid)
+    log("model validation: ADI and HV calls done")
     return {"perf_model": res}
+
+
+# Shapes none of which is in the ADI calibration sweep (model_calibrate.adi_cases).
+ADI_HELDOUT = [("adi", [40, 40, 40], 60, False, True), ("adi", [40, 40, 40], 60, True, True),
+               ("adi", [56, 56, 56], 30, False, True), ("adi", [72, 72, 72], 16, True, True),
+               ("adi", [144, 144, 144], 4, False, True), ("adi", [144, 144, 144], 4, True, True),
+               ("adi", [200, 200, 200], 1, False, True), ("adi", [72, 72], 800, True, True),
+               ("adi", [200, 200], 150, False, True), ("adi", [400, 400], 40, True, True),
+               ("adi", [56, 56], 1000, False, False), ("adi", [72, 72], 2000, False, False),
+               ("adi", [88, 88], 1200, False, False), ("hv", [50, 30], 1000, False, False),
+               ("hv", [50, 30], 1000, False, True), ("hv", [80, 40], 2000, False, False),
+               ("hv", [80, 40], 2000, False, True), ("hv", [120, 60], 500, False, True)]
+
+
+def adi_model_validation(trid):
+    """The performance model's predictions of whole ADI and Hundsdorfer-Verwer
+    calls (trid_model_adi / trid_model_hv: all kernels of the call) against the
+    measured kernel times, on held-out shapes, FP64 and FP32, 10 steps."""
+    import numpy as np
+    import torch
+
+    rng = np.random.default_rng(11)
+    errs, rows = [], []
+    for dt in (torch.float64, torch.float32):
+        for kind, dims, batch, pp, stream in ADI_HELDOUT:
+            shape = [batch] + list(reversed(dims))
+            u = torch.from_numpy(rng.uniform(0.0, 1.0, shape)).to(dt).cuda()
+            steps = 10
+            if kind == "adi":
+                s = (0.1 + 0.2 * torch.rand(shape, dtype=dt, device="cuda")) if pp else None
+                call = lambda: trid.adi_step(u, s=s, s0=0.2, nsteps=steps, stream=stream)  # noqa: E731
+                pred, _ = trid.model_adi(dt, dims, batch, pp, steps, stream)
+            else:
+                a = 0.1 + 0.9 * torch.rand(shape, dtype=dt, device="cuda")
+                b = 0.1 + 0.9 * torch.rand(shape, dtype=dt, device="cuda")
+                c = 0.5 * torch.sqrt(a * b) * (2 * torch.rand(shape, dtype=dt, device="cuda") - 1)
+                call = lambda: trid.hv_step(u, a, b, c, 0.25, 0.7887, steps, stream=stream)  # noqa: E731
+                pred, _ = trid.model_hv(dt, dims, batch, steps, stream)
+            trid.timing_enable(True)
+            call()
+            sync()
+            trid.timing_enable(True)
+            call()
+            meas = sum(ms for _, ms in trid.timing_read().values()) * 1e3
+            trid.timing_enable(False)
+            e = abs(pred - meas) / meas
+            errs.append(e)
+            rows.append("%s %s %s x%d%s%s pred %.0f meas %.0f us" % (
+                kind, str(dt)[6:], "x".join(map(str, dims)), batch, " s(x)" if pp else "",
+                " per-step" if stream else "", pred, meas))
+            del u
+            torch.cuda.empty_cache()
+    errs = np.array(errs)
+    order = np.argsort(-errs)
+    return {"calls": int(len(errs)), "mean_accuracy": round(1 - float(errs.mean()), 3),
+            "median_accuracy": round(1 - float(np.median(errs)), 3),
+            "within_15pct": round(float((errs <= 0.15).mean()), 3),
+            "within_25pct": round(float((errs <= 0.25).mean()), 3),
+            "worst": [rows[i] for i in order[:5]]}
 
 
 def extra_varlen(trid):

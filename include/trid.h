@@ -366,6 +366,34 @@ int trid_adi_step_adjoint_kept(trid_handle_t h, trid_dtype_t dt, const void *u_t
 int trid_model_gtsv(trid_handle_t h, trid_dtype_t dt, int form, int ndim, const int64_t *dims,
                     int axis, int64_t batch, double *us, char *json, size_t len);
 
+/* Predicted GPU time, in microseconds, of trid_adi_step (Alg. 3; dims, batch,
+ * dtype and flags as there, per_point_s != 0 for a per-point s array) over
+ * nsteps steps: the sum over the call's kernels of the model of
+ * trid_model_gtsv, extended to the fused stencil + x kernels and the
+ * constant-row line kernels (bytes over the streaming rate of the kernel's
+ * class, or its workgroup rounds times a per-round latency, whichever is
+ * larger) and to the LDS-resident 2D time loop (rounds of meshes times a load
+ * and store cost plus each step's points over the workgroup's threads) -- the
+ * counterpart of the paper's per-application predictions (Section IV-A,
+ * applied there to the ADI solver).  Only TRID_ADI_STREAM of flags changes the
+ * prediction (graph replay changes launch overhead, not kernel time).  If json
+ * is not NULL, up to len bytes of {"us": total, "kernels": [{"name", "class",
+ * "us", "launches", "bytes", "rounds", "units"}, ...]} are written (units: a
+ * resident loop's mesh points per thread and step), kernel names as
+ * trid_timing_read reports them.  Host computation only (no HIP call).
+ * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED (no kernel plan for the mesh). */
+int trid_model_adi(trid_handle_t h, trid_dtype_t dt, int ndim, const int64_t *dims, int64_t batch, int per_point_s,
+                   int nsteps, unsigned flags, double *us, char *json, size_t len);
+
+/* The same prediction for trid_hv_step (the SLV stand-in of Alg. 4's call
+ * structure, Section IV-B): the resident loop, or per step four predictor
+ * stencils and four s-form line solves (with TRID_ADI_STREAM, or when the mesh
+ * does not fit one workgroup's LDS).  dims = {nx, ny}.  json as for
+ * trid_model_adi.  Host computation only.
+ * Errors: TRID_ERR_ARG, TRID_ERR_UNSUPPORTED. */
+int trid_model_hv(trid_handle_t h, trid_dtype_t dt, const int64_t *dims, int64_t batch, int nsteps, unsigned flags,
+                  double *us, char *json, size_t len);
+
 /* The most recent autotuning run of trid_gtsv_varlen (TRID_AUTOTUNE=1) as a
  * JSON array, best predicted first: per plan its tile rows M, tiles per work
  * item NT, reduced solve ("pcr" / "thomas"), split flag, the persistent

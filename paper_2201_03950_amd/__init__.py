@@ -25,7 +25,9 @@ from ._binding import (  # noqa: F401
     gtsv_varlen,
     gtsv_varlen_dev,
     cache_report,
+    model_adi,
     model_gtsv,
+    model_hv,
     autotune_report,
     TRID_FORM_ARRAYS,
     TRID_FORM_S,

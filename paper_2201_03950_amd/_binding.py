@@ -55,6 +55,10 @@ SIGNATURES = {
                          ctypes.c_size_t], _I),
     "trid_autotune_report": ([_H, ctypes.c_char_p, ctypes.c_size_t], _I),
     "trid_cache_report": ([_H, ctypes.c_char_p, ctypes.c_size_t], _I),
+    "trid_model_adi": ([_H, _I, _I, _I64P, _I64, _I, _I, ctypes.c_uint, ctypes.POINTER(ctypes.c_double),
+                        ctypes.c_char_p, ctypes.c_size_t], _I),
+    "trid_model_hv": ([_H, _I, _I64P, _I64, _I, ctypes.c_uint, ctypes.POINTER(ctypes.c_double), ctypes.c_char_p,
+                       ctypes.c_size_t], _I),
     "trid_resident_layout": ([_H, _I, _I64, _I64, _I, _I, _I, _I64P, _I], _I),
     "trid_hv_step": ([_H, _I, _P, _P, _P, _P, _D, _D, _I64P, _I64, _I, ctypes.c_uint], _I),
     "trid_adi_step_adjoint": ([_H, _I, _P, _P, _D, _P, _P, _I, _I64P, _I64], _I),
@@ -198,6 +202,43 @@ def model_gtsv(dtype, form, dims, axis, batch=1):
     buf = ctypes.create_string_buffer(1024)
     _check(lib.trid_model_gtsv(h, code, int(form), len(dims), d, int(axis), int(batch), ctypes.byref(us), buf,
                                len(buf)), h)
+    return us.value, json.loads(buf.value.decode())
+
+
+def model_adi(dtype, dims, batch=1, per_point_s=False, nsteps=1, stream=False):
+    """Predicted kernel microseconds of ``adi_step`` on ``batch`` meshes of
+    ``dims`` = [nx, ny, (nz)] over ``nsteps`` steps, with the per-kernel split;
+    host computation only."""
+    import json
+
+    import torch
+
+    h = handle()
+    lib = load_library()
+    code = {torch.float64: TRID_F64, torch.float32: TRID_F32}[dtype]
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    us = ctypes.c_double()
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib.trid_model_adi(h, code, len(dims), d, int(batch), int(bool(per_point_s)), int(nsteps),
+                              TRID_ADI_STREAM if stream else 0, ctypes.byref(us), buf, len(buf)), h)
+    return us.value, json.loads(buf.value.decode())
+
+
+def model_hv(dtype, dims, batch=1, nsteps=1, stream=False):
+    """Predicted kernel microseconds of ``hv_step`` on ``batch`` meshes of
+    ``dims`` = [nx, ny] over ``nsteps`` steps, with the per-kernel split."""
+    import json
+
+    import torch
+
+    h = handle()
+    lib = load_library()
+    code = {torch.float64: TRID_F64, torch.float32: TRID_F32}[dtype]
+    d = (ctypes.c_int64 * 2)(*dims)
+    us = ctypes.c_double()
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib.trid_model_hv(h, code, d, int(batch), int(nsteps), TRID_ADI_STREAM if stream else 0,
+                             ctypes.byref(us), buf, len(buf)), h)
     return us.value, json.loads(buf.value.decode())
 
 

@@ -908,6 +908,88 @@ int trid_model_gtsv(trid_handle_t h, trid_dtype_t dt, int form, int ndim, const 
     return TRID_OK;
 }
 
+namespace {
+
+int model_report(trid_handle_t h, const std::vector<trid::KernelPred> &ks, double *us, char *json, size_t len) {
+    double total = 0;
+    for (const auto &k : ks) total += k.us;
+    *us = total;
+    if (json && len) {
+        std::ostringstream o;
+        char item[320];
+        snprintf(item, sizeof item, "{\"us\": %.3f, \"kernels\": [", total);
+        o << item;
+        for (size_t i = 0; i < ks.size(); ++i) {
+            snprintf(item, sizeof item,
+                     "%s{\"name\": \"%s\", \"class\": \"%s\", \"us\": %.3f, \"launches\": %d, "
+                     "\"bytes\": %.0f, \"rounds\": %.0f, \"units\": %.3f}",
+                     i ? ", " : "", ks[i].name.c_str(), ks[i].cls.c_str(), ks[i].us, ks[i].launches, ks[i].bytes,
+                     ks[i].rounds, ks[i].units);
+            o << item;
+        }
+        o << "]}";
+        const std::string txt = o.str();
+        if (txt.size() + 1 > len) return trid::handle_fail(h, TRID_ERR_ARG, "json buffer too small");
+        memcpy(json, txt.c_str(), txt.size() + 1);
+    }
+    return TRID_OK;
+}
+
+}  // namespace
+
+int trid_model_adi(trid_handle_t h, trid_dtype_t dt, int ndim, const int64_t *dims, int64_t batch, int per_point_s,
+                   int nsteps, unsigned flags, double *us, char *json, size_t len) {
+    if (!h) return TRID_ERR_ARG;
+    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
+    if (ndim != 2 && ndim != 3) return trid::handle_fail(h, TRID_ERR_ARG, "ADI needs ndim 2 or 3");
+    if (!us) return trid::handle_fail(h, TRID_ERR_ARG, "us is NULL");
+    if (nsteps < 0) return trid::handle_fail(h, TRID_ERR_ARG, "nsteps must be >= 0");
+    if (flags & ~(TRID_ADI_GRAPH | TRID_ADI_STREAM)) return trid::handle_fail(h, TRID_ERR_ARG, "unknown flags");
+    int64_t inner, n, outer;
+    for (int ax = 0; ax < ndim; ++ax) {
+        int rc = trid::handle_check_mesh(h, ndim, dims, ax, batch, &inner, &n, &outer, false);
+        if (rc) return rc;
+    }
+    // 16-byte aligned stand-ins: the plans depend on the arrays' alignment only
+    static const double pad[2] = {0, 0};
+    trid::AdiReq r;
+    r.f64 = dt == TRID_F64;
+    r.ndim = ndim;
+    r.u = pad;
+    r.d = const_cast<double *>(pad);
+    r.s = per_point_s ? pad : nullptr;
+    r.s0 = 0.2;
+    r.nx = dims[0];
+    r.ny = dims[1];
+    r.nz = ndim == 3 ? dims[2] : 1;
+    r.batch = batch;
+    trid::handle_ext(h).apply_adi_overrides(&r);
+    std::vector<trid::KernelPred> ks;
+    std::string msg;
+    if (!trid::model_adi(r, nsteps, (flags & TRID_ADI_STREAM) != 0, &ks, &msg))
+        return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
+    return model_report(h, ks, us, json, len);
+}
+
+int trid_model_hv(trid_handle_t h, trid_dtype_t dt, const int64_t *dims, int64_t batch, int nsteps, unsigned flags,
+                  double *us, char *json, size_t len) {
+    if (!h) return TRID_ERR_ARG;
+    if (dt != TRID_F32 && dt != TRID_F64) return trid::handle_fail(h, TRID_ERR_ARG, "bad dtype");
+    if (!us) return trid::handle_fail(h, TRID_ERR_ARG, "us is NULL");
+    if (nsteps < 0) return trid::handle_fail(h, TRID_ERR_ARG, "nsteps must be >= 0");
+    if (flags & ~(TRID_ADI_GRAPH | TRID_ADI_STREAM)) return trid::handle_fail(h, TRID_ERR_ARG, "unknown flags");
+    int64_t inner, n, outer;
+    for (int ax = 0; ax < 2; ++ax) {
+        int rc = trid::handle_check_mesh(h, 2, dims, ax, batch, &inner, &n, &outer, false);
+        if (rc) return rc;
+    }
+    std::vector<trid::KernelPred> ks;
+    std::string msg;
+    if (!trid::model_hv(dt == TRID_F64, dims[0], dims[1], batch, nsteps, (flags & TRID_ADI_STREAM) != 0, &ks, &msg))
+        return trid::handle_fail(h, TRID_ERR_UNSUPPORTED, msg);
+    return model_report(h, ks, us, json, len);
+}
+
 int trid_resident_layout(trid_handle_t h, trid_dtype_t dt, int64_t nx, int64_t ny, int hv, int per_point_s,
                          int force_M, int64_t *out, int len) {
     if (!h) return TRID_ERR_ARG;

@@ -114,6 +114,8 @@ int const_lines_M(const LineReq &r);
 hipError_t launch_const_lines(const LineReq &r, int M, hipStream_t s);
 int const_rhs_M(const AdiReq &r);
 hipError_t launch_const_rhs_x(const AdiReq &r, int M, hipStream_t s);
+// Launch geometry of launch_const_rhs_x (host only).
+void const_rhs_geometry(const AdiReq &r, int M, int *threads, int *L, size_t *shmem, i64 *nblocks);
 
 // Adjoint of the ADI right-hand side d = 2 s L u (per-point s), pointwise:
 //   sbar += 2 rbar (L u);   ubar += 2 L (s rbar)   (L symmetric, zero ghosts).

@@ -334,6 +334,25 @@ int const_rhs_M(const AdiReq &r) {
     return M;
 }
 
+void const_rhs_geometry(const AdiReq &r, int M, int *threads, int *L, size_t *shmem, i64 *nblocks) {
+    const int w = r.f64 ? 8 : 4, n = (int)r.nx, P = n / M;
+    int nt = 256, lines;
+    if ((P & (P - 1)) == 0) {
+        nt = (w == 8 && n / 2 <= 128) ? 128 : 256;
+        if (r.force_L > 0 && r.force_L * P <= 256 && (r.force_L * P) % 64 == 0) nt = r.force_L * P;
+        lines = nt / P;
+    } else {
+        const int V = 16 / w, VB = (n / V > 64 ? 2 : 1) * V;
+        lines = std::min(4 * (64 / P), (256 / (n / VB)) * (M / VB));
+        if (r.force_L > 0 && r.force_L < lines) lines = r.force_L;
+    }
+    const int ls = P * (M + 1);
+    *threads = nt;
+    *L = lines;
+    *shmem = (size_t)lines * ls * w + (size_t)lines * sizeof(int);
+    *nblocks = cdiv(r.ny * r.nz * r.batch, lines);
+}
+
 hipError_t launch_const_rhs_x(const AdiReq &r, int M, hipStream_t s) {
     return r.f64 ? rhs_typed<double>(r, M, s) : rhs_typed<float>(r, M, s);
 }

@@ -16,6 +16,8 @@
 // other half of the line sweep and three other mixes are the validation set.
 #include "perf_model.hpp"
 
+#include "resident.hpp"
+
 #include <algorithm>
 #include <cmath>
 
@@ -64,6 +66,16 @@ const VarlenParams &varlen_params() {
     static const VarlenParams p{
         /*t0_us*/ 15.31,  /*bw_gbs*/ 3084.0,   /*lat_us*/ 3.663,  /*cu_gbs*/ 2000.0,
         /*row_ns*/ 321.6, /*f64_factor*/ 3.501, /*lvl_ns*/ 1236.9, /*thomas_ns*/ 103.7,
+    };
+    return p;
+}
+
+// Fitted like LinesParams: on the calibration shapes of model_calibrate.py's
+// ADI sweep (the other shapes are its validation set).
+const AdiParams &adi_params() {
+    static const AdiParams p{
+        /*sx_eff*/ 1.0,      /*sx_blk_us*/ 5.534, /*cs_eff*/ 0.9303, /*cs_blk_us*/ 3.688, /*res_io_ns*/ 5296.7,
+        /*res_ns*/ 62.56,    /*res_f64*/ 1.938,   /*hv_ns*/ 852.8,    /*pred_eff*/ 0.882,
     };
     return p;
 }
@@ -176,6 +188,188 @@ ModelTerms model_varlen(const int64_t *off, std::vector<int> ids, int prec, cons
     t.t_lat = std::max(sum / b, mx);
     t.us = p.t0_us + std::max(t.t_bytes, t.t_lat);
     return t;
+}
+
+// ------------------------------------------------------------ ADI / HV --
+
+namespace {
+
+// A bandwidth-or-latency kernel: t0 + max(bytes at bw * eff, rounds * blk).
+KernelPred stream_kernel(const char *name, const char *cls, double bytes, i64 nblocks, int threads, double shmem,
+                         int M, int w, double eff, double blk_us, int launches) {
+    const LinesParams &lp = lines_params();
+    KernelPred k;
+    k.name = name;
+    k.cls = cls;
+    k.launches = launches;
+    k.bytes = bytes;
+    const int pc = per_cu(threads, shmem, M, w);
+    k.rounds = std::ceil((double)nblocks / (double)(kCUs * pc));
+    k.us = launches * (lp.t0_us + std::max(bytes / (lp.bw_gbs * eff * 1e3), k.rounds * blk_us));
+    return k;
+}
+
+KernelPred line_kernel(const char *name, const LineReq &q, int launches, std::string *err, bool *ok) {
+    const AdiParams &ap = adi_params();
+    const int w = q.f64 ? 8 : 4;
+    const int cm = const_lines_M(q);
+    if (cm) {  // k_strided_const: 64 lines x P tiles per workgroup
+        const int P = (int)(q.n / cm);
+        int words = 2 + (q.out == Out::Add ? 1 : 0);
+        const double rows = (double)q.n * (double)q.inner * (double)q.outer;
+        const i64 nb = ((q.inner + 63) / 64) * q.outer;
+        return stream_kernel(name, "const_lines", words * w * rows, nb, 64 * P, 2.0 * 8 * 64 * w, cm, w, ap.cs_eff,
+                             ap.cs_blk_us, launches);
+    }
+    LinePlan pl;
+    KernelPred k;
+    k.name = name;
+    k.cls = "lines";
+    k.launches = launches;
+    if (!plan_lines(q, &pl, err)) {
+        *ok = false;
+        return k;
+    }
+    const ModelTerms t = model_lines(q, pl);
+    k.us = launches * t.us;
+    k.bytes = t.bytes;
+    k.rounds = t.rounds;
+    return k;
+}
+
+}  // namespace
+
+bool model_adi(const AdiReq &r, int nsteps, bool stream, std::vector<KernelPred> *ks, std::string *err) {
+    const AdiParams &ap = adi_params();
+    const int w = r.f64 ? 8 : 4;
+    ks->clear();
+    if (r.ndim == 2 && !stream) {
+        ResidentReq rr;
+        rr.f64 = r.f64;
+        rr.u = const_cast<void *>(r.u);
+        rr.s = r.s;
+        rr.nx = r.nx;
+        rr.ny = r.ny;
+        rr.batch = r.batch;
+        rr.nsteps = nsteps;
+        int64_t lay[10];
+        if (resident_fits(rr) && resident_layout(rr, 0, lay)) {
+            const int threads = (int)lay[8];
+            const double bytes = (double)lay[9];
+            const int pc = std::max(1, std::min(kThreadsPerCU / threads, (int)(kLdsPerCU / bytes)));
+            KernelPred k;
+            k.name = "adi2d_resident";
+            k.cls = "resident";
+            k.launches = 1;
+            k.bytes = (2.0 + (r.s ? 1.0 : 0.0)) * w * (double)(r.nx * r.ny * r.batch);
+            k.rounds = std::ceil((double)r.batch / (double)(kCUs * pc));
+            k.units = (double)(r.nx * r.ny) / threads;
+            const double ns = ap.res_io_ns + nsteps * ap.res_ns * (r.f64 ? ap.res_f64 : 1.0);
+            k.us = lines_params().t0_us + k.rounds * k.units * ns * 1e-3;
+            ks->push_back(k);
+            return true;
+        }
+    }
+    const double pts = (double)(r.nx * r.ny * r.nz * r.batch);
+    // stencil + x
+    const int cmx = const_rhs_M(r);
+    if (cmx) {
+        int threads, L;
+        size_t shm;
+        i64 nb;
+        const_rhs_geometry(r, cmx, &threads, &L, &shm, &nb);
+        ks->push_back(stream_kernel("adi_stencil_x", "stencil_x", 2.0 * w * pts, nb, threads, (double)shm, cmx, w,
+                                    ap.sx_eff, ap.sx_blk_us, nsteps));
+    } else {
+        LinePlan px;
+        if (!plan_rhs_x(r, &px, err)) return false;
+        ks->push_back(stream_kernel("adi_stencil_x", "stencil_x", (r.s ? 3.0 : 2.0) * w * pts, px.nblocks,
+                                    px.threads(), (double)px.shmem, px.M, w, ap.sx_eff, ap.sx_blk_us, nsteps));
+    }
+    LineReq ry;
+    ry.f64 = r.f64;
+    ry.mode = r.s ? Mode::S : Mode::Const;
+    ry.ca = -r.s0;
+    ry.cb = 1.0 + 2.0 * r.s0;
+    ry.cc = -r.s0;
+    ry.s = r.s;
+    ry.d = r.d;
+    ry.x = r.ndim == 2 ? const_cast<void *>(r.u) : r.d;
+    ry.inner = r.nx;
+    ry.n = r.ny;
+    ry.outer = r.nz * r.batch;
+    ry.out = r.ndim == 2 ? Out::Add : Out::Store;
+    ry.force_M = r.force_M;
+    ry.force_L = r.force_L;
+    bool ok = true;
+    ks->push_back(line_kernel(r.ndim == 3 ? "adi_y" : "adi_y_update", ry, nsteps, err, &ok));
+    if (r.ndim == 3) {
+        LineReq rz = ry;
+        rz.inner = r.nx * r.ny;
+        rz.n = r.nz;
+        rz.outer = r.batch;
+        rz.out = Out::Add;
+        rz.x = const_cast<void *>(r.u);
+        ks->push_back(line_kernel("adi_z_update", rz, nsteps, err, &ok));
+    }
+    return ok;
+}
+
+bool model_hv(bool f64, i64 nx, i64 ny, i64 batch, int nsteps, bool stream, std::vector<KernelPred> *ks,
+              std::string *err) {
+    const AdiParams &ap = adi_params();
+    const int w = f64 ? 8 : 4;
+    ks->clear();
+    static char one = 0;  // non-NULL markers for the requests' arrays (16-byte aligned values do not matter)
+    if (!stream) {
+        ResidentReq rr;
+        rr.f64 = f64;
+        rr.u = &one;
+        rr.nx = nx;
+        rr.ny = ny;
+        rr.batch = batch;
+        rr.nsteps = nsteps;
+        rr.hv = true;
+        rr.a = rr.b = rr.c = &one;
+        int64_t lay[10];
+        if (resident_fits(rr) && resident_layout(rr, 0, lay)) {
+            const int threads = (int)lay[8];
+            const double bytes = (double)lay[9];
+            const int pc = std::max(1, std::min(kThreadsPerCU / threads, (int)(kLdsPerCU / bytes)));
+            KernelPred k;
+            k.name = "hv_resident";
+            k.cls = "hv_resident";
+            k.launches = 1;
+            k.bytes = 5.0 * w * (double)(nx * ny * batch);  // u in and out, a, b, c once
+            k.rounds = std::ceil((double)batch / (double)(kCUs * pc));
+            k.units = (double)(nx * ny) / threads;
+            const double ns = ap.res_io_ns + nsteps * ap.hv_ns * (f64 ? ap.res_f64 : 1.0);
+            k.us = lines_params().t0_us + k.rounds * k.units * ns * 1e-3;
+            ks->push_back(k);
+            return true;
+        }
+    }
+    const double pts = (double)(nx * ny * batch);
+    const i64 nb = (i64)std::ceil(pts / 256.0);
+    // predictors: 6 + 4 + 6 + 4 words per point and step; the coefficient fill once per call
+    ks->push_back(stream_kernel("hv_pred", "hv_pred", 5.0 * w * pts, nb, 256, 0.0, 8, w, ap.pred_eff, 0.0,
+                                4 * nsteps));
+    ks->back().us += stream_kernel("", "", 4.0 * w * pts, nb, 256, 0.0, 8, w, ap.pred_eff, 0.0, 1).us;
+    bool ok = true;
+    for (int axis = 0; axis < 2; ++axis) {
+        LineReq q;
+        q.f64 = f64;
+        q.mode = Mode::S;
+        q.s = &one;
+        q.d = &one;
+        q.x = &one;
+        q.out = Out::Store;
+        q.inner = axis == 0 ? 1 : nx;
+        q.n = axis == 0 ? nx : ny;
+        q.outer = axis == 0 ? ny * batch : batch;
+        ks->push_back(line_kernel(axis == 0 ? "gtsv_staged" : "gtsv_strided", q, 2 * nsteps, err, &ok));
+    }
+    return ok;
 }
 
 }  // namespace trid

@@ -5,6 +5,7 @@
 // pipeline latency per call).
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "dispatch.hpp"
@@ -36,8 +37,20 @@ struct LinesParams {
 struct VarlenParams {
     double t0_us, bw_gbs, lat_us, cu_gbs, row_ns, f64_factor, lvl_ns, thomas_ns;
 };
+// Model constants of the ADI-step kernels and of the resident time loops, on top
+// of LinesParams (t0, bw): the stencil + x kernels and the constant-row y/z
+// kernels each stream at bw * eff with a per-round latency blk_us (rounds =
+// the grid's workgroups over what the CUs hold at once); a resident loop costs,
+// per round of meshes, one mesh's points per thread (units) times io_ns for
+// its load and store plus, per step, res_ns (FP64: times res_f64; the
+// Hundsdorfer-Verwer step: hv_ns); the HV predictor stencils stream at
+// bw * pred_eff.
+struct AdiParams {
+    double sx_eff, sx_blk_us, cs_eff, cs_blk_us, res_io_ns, res_ns, res_f64, hv_ns, pred_eff;
+};
 const LinesParams &lines_params();
 const VarlenParams &varlen_params();
+const AdiParams &adi_params();
 
 struct ModelTerms {
     double us = 0;       // predicted kernel duration
@@ -56,5 +69,26 @@ ModelTerms model_lines(const LineReq &r, const LinePlan &pl);
 // `blocks` persistent workgroups (varlen_blocks).  prec as VarlenSchedule.
 ModelTerms model_varlen(const int64_t *offsets_host, std::vector<int> ids, int prec, const VarlenVariant &v,
                         int blocks);
+
+// One kernel of a modelled call: its name (as the library's kernel timer names
+// it), the call's predicted time in it (all launches), launches, bytes and
+// workgroup rounds per launch, and the class whose constants it uses.
+struct KernelPred {
+    std::string name, cls;
+    double us = 0;
+    int launches = 0;
+    double bytes = 0, rounds = 0;
+    double units = 0;  // resident loops: one mesh's points per thread and step
+};
+
+// `nsteps` ADI steps of request r (Alg. 3; the per-step kernels, or the
+// resident 2D loop where it applies and stream is false).  Host only; r's
+// pointers only decide alignment-dependent plans.
+bool model_adi(const AdiReq &r, int nsteps, bool stream, std::vector<KernelPred> *ks, std::string *err);
+// `nsteps` Hundsdorfer-Verwer steps of batch meshes of nx * ny points (the
+// SLV stand-in): resident loop, or fill + four predictors + four s-form solves
+// per step.
+bool model_hv(bool f64, i64 nx, i64 ny, i64 batch, int nsteps, bool stream, std::vector<KernelPred> *ks,
+              std::string *err);
 
 }  // namespace trid

@@ -1,7 +1,9 @@
 """Calibration of the performance model's constants (csrc/perf_model.cpp).
 
-    python -m paper_2201_03950_amd.model_calibrate sweep OUT.jsonl   # on the GPU
-    python -m paper_2201_03950_amd.model_calibrate fit OUT.jsonl     # on any host
+    python -m paper_2201_03950_amd.model_calibrate sweep OUT.jsonl       # on the GPU
+    python -m paper_2201_03950_amd.model_calibrate fit OUT.jsonl         # on any host
+    python -m paper_2201_03950_amd.model_calibrate adi-sweep OUT.jsonl   # on the GPU
+    python -m paper_2201_03950_amd.model_calibrate adi-fit OUT.jsonl     # on any host
 
 ``sweep`` measures kernel durations (dispatch-stamped events) of the batched
 line solves over both forms (s and coefficient arrays), FP64 and FP32, x/y/z
@@ -14,6 +16,14 @@ the line configurations, the uneven-batch constants on three of the mixes,
 and reports the accuracy (1 - |pred - meas| / meas) on the other half and on
 the other three mixes, as the paper does for its own model.  It prints the
 constants in the order of LinesParams and VarlenParams.
+
+``adi-sweep`` measures the kernels of whole ADI calls (Alg. 3: 3D and 2D
+meshes, constant and per-point s, FP64 and FP32, the per-step kernels and the
+LDS-resident 2D loop) and of Hundsdorfer-Verwer calls (the SLV stand-in,
+resident and per-step), each with the model's per-kernel terms
+(``model_adi`` / ``model_hv``).  ``adi-fit`` fits AdiParams on the shapes
+whose index in a seeded shuffle is even and reports the accuracy of the call
+totals on the others.
 """
 
 from __future__ import annotations
@@ -121,6 +131,125 @@ def sweep(path):
             torch.cuda.empty_cache()
         print("uneven batch %s done" % name, flush=True)
     out.close()
+
+
+# LinesParams' t0_us and bw_gbs (perf_model.cpp), which the ADI terms share
+LINES_T0_US, LINES_BW_GBS = 2.40, 6661.0
+ADI_NAMES = ["sx_eff", "sx_blk_us", "cs_eff", "cs_blk_us", "res_io_ns", "res_ns", "res_f64", "hv_ns", "pred_eff"]
+
+
+def adi_cases():
+    """The ADI sweep's shapes: (kind, dims, batch, per_point_s, stream)."""
+    cases = []
+    for n, b in ((32, 96), (48, 48), (64, 32), (80, 24), (96, 16), (112, 8), (128, 8), (160, 4), (192, 2),
+                 (256, 1)):
+        for pp in (False, True):
+            cases.append(("adi", [n, n, n], b, pp, True))
+    for n, b in ((32, 2000), (64, 1000), (96, 500), (128, 300), (256, 64), (512, 16), (1024, 4)):
+        for pp in (False, True):
+            cases.append(("adi", [n, n], b, pp, True))
+    for n in (32, 48, 64, 80, 96, 112, 128):
+        for b in (300, 3000):
+            cases.append(("adi", [n, n], b, False, False))
+    for nx, ny in ((40, 20), (100, 50), (64, 64)):
+        for b in (30, 300, 3000):
+            cases.append(("hv", [nx, ny], b, False, False))
+            cases.append(("hv", [nx, ny], b, False, True))
+    return cases
+
+
+def adi_sweep(path):
+    import numpy as np
+    import torch
+
+    import paper_2201_03950_amd as trid
+
+    trid.load_library()
+    out = open(path, "w")
+    rng = np.random.default_rng(5)
+    for dt in (torch.float64, torch.float32):
+        for kind, dims, batch, pp, stream in adi_cases():
+            if dt == torch.float64 and kind == "adi" and not stream and dims[0] > 96:
+                continue  # FP64 meshes above 96^2 do not fit one workgroup's LDS
+            shape = [batch] + list(reversed(dims))
+            u = torch.from_numpy(rng.uniform(0.0, 1.0, shape)).to(dt).cuda()
+            steps = 10
+            if kind == "adi":
+                s = (0.1 + 0.2 * torch.rand(shape, dtype=dt, device="cuda")) if pp else None
+                call = lambda: trid.adi_step(u, s=s, s0=0.2, nsteps=steps, stream=stream)  # noqa: E731
+                pred, terms = trid.model_adi(dt, dims, batch, pp, steps, stream)
+            else:
+                a = 0.1 + 0.9 * torch.rand(shape, dtype=dt, device="cuda")
+                b = 0.1 + 0.9 * torch.rand(shape, dtype=dt, device="cuda")
+                c = 0.5 * torch.sqrt(a * b) * (2 * torch.rand(shape, dtype=dt, device="cuda") - 1)
+                call = lambda: trid.hv_step(u, a, b, c, 0.25, 0.7887, steps, stream=stream)  # noqa: E731
+                pred, terms = trid.model_hv(dt, dims, batch, steps, stream)
+            trid.timing_enable(True)  # warm up with timing on, then restart the accumulators
+            call()
+            torch.cuda.synchronize()
+            trid.timing_enable(True)
+            call()
+            meas = {k: ms * 1e3 for k, (cnt, ms) in trid.timing_read().items()}
+            trid.timing_enable(False)
+            out.write(json.dumps({"kind": kind, "dtype": str(dt)[6:], "dims": dims, "batch": batch, "pp": pp,
+                                  "stream": stream, "steps": steps, "pred_us": pred, "terms": terms["kernels"],
+                                  "meas_us": meas}) + "\n")
+            del u
+            torch.cuda.empty_cache()
+        print("adi sweep %s done" % dt, flush=True)
+    out.close()
+
+
+def _pred_adi_kernel(p, k, f64):
+    """Mirror of perf_model.cpp's ADI terms for one kernel of a call."""
+    sx_eff, sx_blk, cs_eff, cs_blk, io, res_ns, res_f64, hv_ns, pred_eff = p
+    t0, bw = LINES_T0_US, LINES_BW_GBS
+    cls, L = k["class"], k["launches"]
+    if cls == "lines":
+        return k["us"]
+    if cls in ("resident", "hv_resident"):
+        ns = io + k["steps"] * (res_ns if cls == "resident" else hv_ns) * (res_f64 if f64 else 1.0)
+        return t0 + k["rounds"] * k["units"] * ns * 1e-3
+    eff, blk = {"stencil_x": (sx_eff, sx_blk), "const_lines": (cs_eff, cs_blk), "hv_pred": (pred_eff, 0.0)}[cls]
+    per = t0 + max(k["bytes"] / (bw * eff * 1e3), k["rounds"] * blk)
+    if cls == "hv_pred":  # four predictors per step and the coefficient fill (4/5 of a predictor's bytes)
+        fill = t0 + 0.8 * k["bytes"] / (bw * eff * 1e3)
+        return L * per + fill
+    return L * per
+
+
+def _pred_adi(p, r):
+    f64 = r["dtype"] == "float64"
+    return sum(_pred_adi_kernel(p, dict(k, steps=r["steps"]), f64) for k in r["terms"])
+
+
+def adi_fit(path):
+    import numpy as np
+    from scipy.optimize import least_squares
+
+    recs = [json.loads(line) for line in open(path)]
+    recs = [r for r in recs if sum(r["meas_us"].values()) > 0]
+    rng = np.random.default_rng(2027)
+    order = rng.permutation(len(recs))
+    cal = [recs[i] for i in order[0::2]]
+    val = [recs[i] for i in order[1::2]]
+    meas = lambda r: sum(r["meas_us"].values())  # noqa: E731
+    p0 = [0.8, 3.0, 0.9, 2.0, 500.0, 20.0, 1.5, 60.0, 0.75]
+    lb = [0.1, 0, 0.1, 0, 0, 0.1, 1.0, 0.1, 0.1]
+    ub = [1.0, 200, 1.0, 200, 50000, 5000, 4.0, 20000, 1.0]
+    best = None
+    for _ in range(20):  # multi-start: the max() terms make the fit multimodal
+        q0 = [rng.uniform(lo, hi) for lo, hi in zip(lb, ub)]
+        q0 = [min(max(v, lo), hi) for v, lo, hi in zip(q0, lb, ub)]
+        f = least_squares(lambda q: np.array([math.log(_pred_adi(q, r) / meas(r)) for r in cal]), q0,
+                          bounds=(lb, ub))
+        if best is None or f.cost < best.cost:
+            best = f
+    pa = best.x
+    print("AdiParams", {k: round(float(v), 4) for k, v in zip(ADI_NAMES, pa)})
+    print("  calibration", _accuracy([(_pred_adi(pa, r), meas(r)) for r in cal]))
+    print("  validation ", _accuracy([(_pred_adi(pa, r), meas(r)) for r in val]))
+    print("  library constants on all shapes", _accuracy([(r["pred_us"], meas(r)) for r in recs]))
 
 
 def _log2c(v):
@@ -254,6 +383,7 @@ def fit(path):
 
 
 if __name__ == "__main__":
-    if len(sys.argv) != 3 or sys.argv[1] not in ("sweep", "fit"):
+    cmds = {"sweep": sweep, "fit": fit, "adi-sweep": adi_sweep, "adi-fit": adi_fit}
+    if len(sys.argv) != 3 or sys.argv[1] not in cmds:
         sys.exit(__doc__)
-    sweep(sys.argv[2]) if sys.argv[1] == "sweep" else fit(sys.argv[2])
+    cmds[sys.argv[1]](sys.argv[2])

@@ -138,3 +138,80 @@ def test_calibration_fit_runs_on_a_recorded_sweep(tmp_path, capsys):
     assert "LinesParams" in out and "VarlenParams" in out
     accs = [float(x) for x in __import__("re").findall(r"'mean': ([0-9.]+)", out)]
     assert len(accs) == 4 and min(accs) > 0.9
+
+
+ADI_CASES = [("adi", [256, 256, 256], 1, False, True), ("adi", [128, 128, 128], 2, True, True),
+             ("adi", [80, 80, 80], 72, False, True), ("adi", [1024, 1024], 4, True, True),
+             ("adi", [64, 64], 3000, False, False), ("adi", [200, 200], 10, False, False),
+             ("hv", [100, 50], 3000, False, False), ("hv", [100, 50], 300, False, True),
+             ("hv", [300, 200], 4, False, False)]
+
+
+def _adi_model(dt, kind, dims, batch, pp, stream, steps):
+    if kind == "adi":
+        return trid.model_adi(dt, dims, batch, pp, steps, stream)
+    return trid.model_hv(dt, dims, batch, steps, stream)
+
+
+def test_adi_calibration_mirror_matches_the_library():
+    """The calibration script's mirror of the ADI / HV terms reproduces the
+    library's predictions with the library's constants."""
+    from paper_2201_03950_amd import model_calibrate as mc
+
+    p = _cpp_params("const AdiParams &adi_params()")
+    assert len(p) == len(mc.ADI_NAMES)
+    lp = _cpp_params("const LinesParams &lines_params()")
+    assert (mc.LINES_T0_US, mc.LINES_BW_GBS) == (lp[0], lp[1])
+    for dt in (torch.float64, torch.float32):
+        for kind, dims, batch, pp, stream in ADI_CASES:
+            us, js = _adi_model(dt, kind, dims, batch, pp, stream, 10)
+            assert js["us"] == pytest.approx(us, rel=1e-4)
+            rec = {"dtype": str(dt)[6:], "steps": 10, "terms": js["kernels"]}
+            assert mc._pred_adi(p, rec) == pytest.approx(us, rel=1e-3)
+
+
+def test_adi_model_follows_the_call_structure():
+    # 3D: the three per-step kernels, launched once per step, under the timer's names
+    us1, js1 = trid.model_adi(torch.float64, [256, 256, 256], 1, False, 1)
+    us4, js4 = trid.model_adi(torch.float64, [256, 256, 256], 1, False, 4)
+    assert [k["name"] for k in js1["kernels"]] == ["adi_stencil_x", "adi_y", "adi_z_update"]
+    assert us4 == pytest.approx(4 * us1, rel=1e-6)
+    assert all(k["launches"] == 4 for k in js4["kernels"])
+    # the stencil + x kernel moves 2 words per point with constant s, 3 with per-point s
+    assert js1["kernels"][0]["bytes"] == 2 * 8 * 256 ** 3
+    _, jp = trid.model_adi(torch.float64, [256, 256, 256], 1, True, 1)
+    assert jp["kernels"][0]["bytes"] == 3 * 8 * 256 ** 3
+    # 2D meshes that fit one workgroup's LDS: one resident launch unless forced per step
+    _, jr = trid.model_adi(torch.float32, [64, 64], 3000, False, 120)
+    _, js = trid.model_adi(torch.float32, [64, 64], 3000, False, 120, stream=True)
+    assert [k["name"] for k in jr["kernels"]] == ["adi2d_resident"]
+    assert [k["name"] for k in js["kernels"]] == ["adi_stencil_x", "adi_y_update"]
+    _, jh = trid.model_hv(torch.float64, [100, 50], 3000, 50, stream=True)
+    assert [k["name"] for k in jh["kernels"]] == ["hv_pred", "gtsv_staged", "gtsv_strided"]
+    assert [k["launches"] for k in jh["kernels"]] == [200, 100, 100]
+
+
+def test_adi_model_argument_checks():
+    import ctypes
+
+    from paper_2201_03950_amd import _binding as B
+
+    ERR_ARG = 1
+    lib = B.load_library()
+    h = B.handle()
+    dims = (ctypes.c_int64 * 3)(32, 32, 32)
+    us = ctypes.c_double()
+    buf = ctypes.create_string_buffer(4096)
+    ok = lib.trid_model_adi(h, B.TRID_F64, 3, dims, 2, 0, 5, 0, ctypes.byref(us), buf, len(buf))
+    assert ok == 0 and us.value > 0
+    assert lib.trid_model_adi(h, 7, 3, dims, 2, 0, 5, 0, ctypes.byref(us), buf, len(buf)) == ERR_ARG
+    assert lib.trid_model_adi(h, B.TRID_F64, 4, dims, 2, 0, 5, 0, ctypes.byref(us), buf, len(buf)) == ERR_ARG
+    assert lib.trid_model_adi(h, B.TRID_F64, 3, dims, 2, 0, -1, 0, ctypes.byref(us), buf, len(buf)) == ERR_ARG
+    assert lib.trid_model_adi(h, B.TRID_F64, 3, dims, 2, 0, 5, 1 << 9, ctypes.byref(us), buf,
+                              len(buf)) == ERR_ARG
+    assert lib.trid_model_adi(h, B.TRID_F64, 3, dims, 2, 0, 5, 0, None, buf, len(buf)) == ERR_ARG
+    assert lib.trid_model_adi(h, B.TRID_F64, 3, dims, 2, 0, 5, 0, ctypes.byref(us), buf, 16) == ERR_ARG
+    assert lib.trid_model_adi(h, B.TRID_F64, 3, dims, 2, 0, 5, 0, ctypes.byref(us), None, 0) == 0
+    d2 = (ctypes.c_int64 * 2)(100, 50)
+    assert lib.trid_model_hv(h, B.TRID_F32, d2, 30, 5, 0, ctypes.byref(us), buf, len(buf)) == 0
+    assert lib.trid_model_hv(h, B.TRID_F32, d2, 0, 5, 0, ctypes.byref(us), buf, len(buf)) != 0
