@@ -342,9 +342,10 @@ def test_staged_x_every_reduced_form(trid, orc, dt, M, n):
 # power of two: Table 3's 48..112-point meshes, a two-lines-per-wavefront
 # length), the 16-byte staged per-point kernel (nx = 8 P, also rows spanning
 # two wavefronts at 512 FP64), the constant-row kernels; per-point and
-# constant s, ragged last blocks
+# constant s, ragged last blocks, and planes of whole blocks (slab order)
 RHS_LANES = [((80, 7, 5), 2), ((96, 5, 3), 3), ((112, 3, 4), 2), ((48, 9, 2), 2), ((200, 4, 3), 1),
-             ((80, 11), 3), ((512, 3, 2), 2), ((32, 9, 5), 3), ((64, 7), 5), ((128, 5, 3), 1), ((256, 3, 3), 1)]
+             ((80, 11), 3), ((512, 3, 2), 2), ((32, 9, 5), 3), ((64, 7), 5), ((128, 5, 3), 1), ((256, 3, 3), 1),
+             ((80, 40, 3), 2), ((96, 32, 4), 1)]
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
