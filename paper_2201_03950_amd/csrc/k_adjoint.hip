@@ -5,7 +5,7 @@
 //   ubar += 2 L (s rbar)        (L is symmetric)
 // One thread per mesh point, one block per chunk of an x line (so the line's
 // y/z position is one scalar division per block); neighbours are read through
-// the caches with branch-free loads.  The transposed line solves of the step's
+// the caches with branch-free loads, blocks in XCD-contiguous order.  The transposed line solves of the step's
 // reverse pass are the adjoint epilogues of the line-solve kernels (lines.hpp).
 #include <algorithm>
 
@@ -18,7 +18,9 @@ template <typename T, int NDIM>
 __global__ __launch_bounds__(256) void k_stencil_adjoint(const T *__restrict__ u, const T *__restrict__ s,
                                                          const T *__restrict__ rbar, T *__restrict__ ubar,
                                                          T *__restrict__ sbar, int nx, int ny, int nz, int cpl) {
-    const i64 b = blockIdx.x;
+    // XCD-contiguous block order: the neighbour lines and planes a block reads
+    // were read by the blocks just before it on the same XCD (its L2)
+    const i64 b = xcd_block_id();
     const i64 line = b / cpl;  // uniform: scalar unit
     const int i = (int)(b - line * cpl) * (int)blockDim.x + (int)threadIdx.x;
     const int j = (int)(line % ny);
