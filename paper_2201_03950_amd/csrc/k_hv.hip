@@ -57,7 +57,9 @@ __global__ __launch_bounds__(256) void k_hv_pred(HvGeom g, T *__restrict__ u, T 
                                                  T *__restrict__ z, const T *__restrict__ a,
                                                  const T *__restrict__ b, const T *__restrict__ c,
                                                  T *__restrict__ sa, T *__restrict__ sb) {
-    const i64 p = (i64)blockIdx.x * blockDim.x + threadIdx.x;
+    // XCD-contiguous block order: the rows above and below a block's points were
+    // read by the neighbouring blocks on the same XCD (its L2)
+    const i64 p = xcd_block_id() * blockDim.x + threadIdx.x;
     if (p >= g.total) return;
     const T dt = (T)g.dt, th = (T)g.theta;
     if constexpr (WHICH == 4) {
