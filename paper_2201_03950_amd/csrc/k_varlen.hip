@@ -359,8 +359,8 @@ hipError_t launch_persistent(K kernel, int nt, size_t lds, const VarlenSchedule 
 // The (M, NT) variants compiled for each precision.
 // The first variant whose tiles hold the longest system is the default plan.
 const std::vector<VarlenVariant> &varlen_variants(int prec) {
-    static const std::vector<VarlenVariant> f64 = {{16, 512, 0, 1}, {8, 1024}, {16, 512}, {32, 256},
-                                                   {8, 256}, {16, 512, 1}, {32, 256, 1}};
+    static const std::vector<VarlenVariant> f64 = {{16, 512, 0, 1}, {8, 1024, 0, 1}, {8, 1024}, {16, 512},
+                                                   {32, 256}, {8, 256}, {16, 512, 1}, {32, 256, 1}};
     static const std::vector<VarlenVariant> f32 = {{16, 512, 0, 1}, {32, 256, 0, 1}, {8, 1024}, {16, 512}, {32, 256},
                                                    {8, 256}, {16, 512, 1}, {32, 256, 1}};
     static const std::vector<VarlenVariant> ref = {{16, 512, 0, 1}, {8, 1024}, {16, 512}, {32, 256}, {8, 256}};

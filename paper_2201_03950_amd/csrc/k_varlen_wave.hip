@@ -582,6 +582,8 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
 template <class F>
 auto with_wave_kernel(int prec, int M, int NW, F &&f) -> decltype(f(k_vlw_refine<16, 8>, 512, size_t(0))) {
     if (prec == 2) return f(k_vlw_refine<16, 8>, 512, VlwLds<16, 8, double, float>::bytes(2));
+    if (prec == 0 && M == 8)  // 16 wavefronts, 4 per SIMD: 128 VGPRs (28 bytes per lane spilled)
+        return f(k_vlw_plain<double, 8, 16, true>, 1024, VlwLds<8, 16, double, double>::bytes(1));
     if (prec == 0) return f(k_vlw_plain<double, 16, 8, true>, 512, VlwLds<16, 8, double, double>::bytes(1));
     if (M == 32) return f(k_vlw_plain<float, 32, 4, true>, 256, VlwLds<32, 4, float, float>::bytes(1));
     return f(k_vlw_plain<float, 16, 8, false, 4>, 512, VlwLds<16, 8, float, float>::bytes(1));
@@ -603,7 +605,7 @@ int wave_occupancy(K kernel, int nt, size_t lds) {
 
 // Wavefront variants: M rows per tile, NW wavefronts per workgroup (the
 // longest system is 64 NW tiles).
-int varlen_wave_NW(int prec, int M) { return (prec == 1 && M == 32) ? 4 : 8; }
+int varlen_wave_NW(int prec, int M) { return (prec == 1 && M == 32) ? 4 : ((prec == 0 && M == 8) ? 16 : 8); }
 
 void varlen_wave_pack(const int64_t *off, std::vector<int> ids, int M, int NW, std::vector<int> *order,
                       std::vector<int> *tstart, std::vector<int> *wdesc) {

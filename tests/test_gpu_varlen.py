@@ -112,12 +112,16 @@ FORCED = {
     # reduced systems solved by Thomas on one thread per system (Thomas-Thomas)
     "thomas16": '"%s": {"M": 16, "NT": 512, "reduced": "thomas"}',
     "thomas32": '"%s": {"M": 32, "NT": 256, "reduced": "thomas"}',
+    # wavefront-level items: 8-row FP64 tiles, 16 wavefronts per workgroup
+    "wave8": '"%s": {"M": 8, "NT": 1024, "reduced": "wave"}',
+    "wave16": '"%s": {"M": 16, "NT": 512, "reduced": "wave"}',
 }
 
 
 @pytest.mark.parametrize("prec,plan", [("f64", "split"), ("f32", "split"), ("refine", "split"),
                                        ("f64", "thomas16"), ("f64", "thomas32"), ("f32", "thomas16"),
-                                       ("f32", "thomas32")])
+                                       ("f32", "thomas32"), ("f64", "wave8"), ("f64", "wave16"),
+                                       ("f32", "wave16"), ("refine", "wave16")])
 def test_varlen_forced_plan_matches_oracle(trid, orc, tmp_path, monkeypatch, prec, plan):
     """A plan forced through the plan cache of a fresh handle."""
     import json
