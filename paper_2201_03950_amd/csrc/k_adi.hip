@@ -1,5 +1,5 @@
-// k_adi.hip -- the explicit-stencil right-hand side of the ADI step (Alg. 3,
-// line 2) fused with the x-line solve (Alg. 3, line 3): u is read once, the RHS
+// k_adi.hip -- the explicit-stencil right-hand side of the ADI step (Alg. 3)
+// fused with the step's x-line solve (Alg. 3): u is read once, the RHS
 // d = 2 s L u is formed while staging the block's x lines into LDS, the rows
 // (-s, 1 + 2 s, -s) are generated in-kernel (Section IV-A: coefficient
 // generation fused into the solver), and only d is written.

@@ -1,4 +1,4 @@
-// k_adjoint.hip -- reverse mode of the ADI right-hand side (Alg. 3, line 2).
+// k_adjoint.hip -- reverse mode of the ADI step's explicit right-hand side (Alg. 3).
 // Forward: d = 2 s (L u) with L the 7-point (3D) / 5-point (2D) Laplacian and
 // zero values outside the mesh.  Given rbar = dLoss/dd:
 //   sbar += 2 rbar (L u)

@@ -52,10 +52,10 @@ def _product_tol(tol, lam, x, grad, k):
     return tol * k * float(np.max(np.abs(lam)) * np.max(np.abs(x)) / np.max(np.abs(grad))) + 8 * eps
 
 
-# ------------------------------------------------------------------ config 0 --
+# ------------------------------------------- 1024 systems of 256 rows, FP64 --
 
 @pytest.mark.parametrize("layout", ["x", "y"])
-def test_config0_1024_systems_n256_fp64(trid, orc, layout):
+def test_1024_systems_n256_fp64(trid, orc, layout):
     a, b, c, d = gen.dd_lines(1024, 256, seed=0)
     if layout == "x":  # dims [256, 1024], axis 0: each system contiguous
         arrs = [v[None] for v in (a, b, c, d)]
@@ -70,7 +70,7 @@ def test_config0_1024_systems_n256_fp64(trid, orc, layout):
 
 
 @pytest.mark.parametrize("layout", ["x", "y"])
-def test_config0_graph_replays_match_eager(trid, orc, layout):
+def test_1024_systems_graph_replays_match_eager(trid, orc, layout):
     """The batched solve captured in a torch CUDA graph (the library launches on
     the capturing stream) and replayed three times, with eager work between the
     replays: every replay equals the eager call bitwise and the oracle to 1e-12."""
