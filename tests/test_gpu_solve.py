@@ -360,6 +360,28 @@ def test_rhs_x_whole_lines_per_wavefront(trid, orc, dt, perpoint, dims, batch):
     assert _field_err(tu.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
 
 
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("perpoint", [False, True])
+def test_adi_step_on_unaligned_views(trid, orc, dt, perpoint):
+    """Arrays one element past a 16-byte boundary: the 16-byte staged kernels
+    decline them and the general kernels run (same results)."""
+    dims, batch = (64, 12, 5), 2
+    u = gen.adi3d_field(dims, batch, seed=21).astype(dt)
+    s = (0.2 * np.random.default_rng(22).lognormal(0.0, 0.5, u.shape)).astype(dt) if perpoint else None
+    ref = orc.adi_step(u, s=s, s0=0.2, nsteps=2)
+
+    def unaligned(a):
+        buf = torch.zeros(a.size + 1, dtype=_t(a).dtype, device="cuda")
+        v = buf[1:].view(a.shape)
+        v.copy_(_t(a))
+        return v
+
+    tu = unaligned(u)
+    assert tu.data_ptr() % 16 != 0
+    trid.adi_step(tu, s=unaligned(s) if s is not None else None, s0=0.2, nsteps=2, stream=True)
+    assert _field_err(tu.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
+
+
 # x lines take the LDS-staged transposed solve: line lengths across the tile
 # sizes and the one-line-per-block limit, line counts with a ragged last block
 S_ADJ_X = [(1, 7), (2, 5), (8, 33), (9, 70), (33, 9), (64, 21), (100, 10), (128, 19), (255, 13), (256, 40),
