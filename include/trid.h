@@ -121,9 +121,12 @@ int trid_version(void);
 int trid_set_tile(trid_handle_t h, int M, int L);
 
 /* Per-kernel timing with HIP events (for measurement tools).  With on != 0,
- * every kernel this handle launches outside graph capture is bracketed by two
- * events recorded on the launch stream; on = 0 stops it.  Either call first
- * waits for pending events and clears the accumulated totals.
+ * every kernel this handle launches outside graph capture has its start and
+ * end stamped into two events by its dispatch (work replayed from a graph,
+ * such as an uneven batch with several launches, is bracketed by two events
+ * recorded on the stream instead; an uneven batch of one persistent launch
+ * then runs directly, not from its captured graph); on = 0 stops it.  Either
+ * call first waits for pending events and clears the accumulated totals.
  * trid_timing_read waits for pending events, then writes NUL-terminated JSON
  * text {"kernel": [launch count, total milliseconds], ...} into buf (len bytes).
  * Errors: TRID_ERR_ARG (NULL handle or buffer, buffer too small), TRID_ERR_HIP. */

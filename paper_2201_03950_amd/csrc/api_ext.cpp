@@ -530,6 +530,14 @@ int trid_gtsv_varlen(trid_handle_t h, trid_prec_t prec, const void *a, const voi
         });
     }
     trid::VarlenSchedule &sc = **found;
+    // With the kernel timer on, a schedule of one persistent launch runs
+    // directly, so that its dispatch stamps the kernel's own start and end
+    // (events around a graph launch would also count the launch latency).
+    if (xs.timer.on && sc.nitems > 0 && !sc.next && sc.long_off.empty()) {
+        hipError_t e = xs.timer.time("varlen", st, [&] { return trid::varlen_launch(sc, a, b, c, d, x, st); });
+        if (e != hipSuccess) return trid::handle_hip_fail(h, e, "uneven batch: launch");
+        return TRID_OK;
+    }
     // one persistent launch, replayed from a captured graph per (pointers, stream)
     const trid::VarlenSchedule::GraphKey gkey = std::make_tuple(a, b, c, d, x, st);
     hipGraphExec_t *git = sc.graphs.find(gkey);
