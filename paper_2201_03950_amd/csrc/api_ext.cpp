@@ -959,7 +959,7 @@ int trid_model_adi(trid_handle_t h, trid_dtype_t dt, int ndim, const int64_t *di
         if (rc) return rc;
     }
     // 16-byte aligned stand-ins: the plans depend on the arrays' alignment only
-    static const double pad[2] = {0, 0};
+    alignas(16) static const double pad[2] = {0, 0};
     trid::AdiReq r;
     r.f64 = dt == TRID_F64;
     r.ndim = ndim;

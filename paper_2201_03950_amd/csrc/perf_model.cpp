@@ -320,17 +320,18 @@ bool model_hv(bool f64, i64 nx, i64 ny, i64 batch, int nsteps, bool stream, std:
     const AdiParams &ap = adi_params();
     const int w = f64 ? 8 : 4;
     ks->clear();
-    static char one = 0;  // non-NULL markers for the requests' arrays (16-byte aligned values do not matter)
+    // 16-byte aligned non-NULL stand-ins for the requests' arrays (the plans depend on alignment only)
+    alignas(16) static char one[16] = {0};
     if (!stream) {
         ResidentReq rr;
         rr.f64 = f64;
-        rr.u = &one;
+        rr.u = one;
         rr.nx = nx;
         rr.ny = ny;
         rr.batch = batch;
         rr.nsteps = nsteps;
         rr.hv = true;
-        rr.a = rr.b = rr.c = &one;
+        rr.a = rr.b = rr.c = one;
         int64_t lay[10];
         if (resident_fits(rr) && resident_layout(rr, 0, lay)) {
             const int threads = (int)lay[8];
@@ -360,9 +361,9 @@ bool model_hv(bool f64, i64 nx, i64 ny, i64 batch, int nsteps, bool stream, std:
         LineReq q;
         q.f64 = f64;
         q.mode = Mode::S;
-        q.s = &one;
-        q.d = &one;
-        q.x = &one;
+        q.s = one;
+        q.d = one;
+        q.x = one;
         q.out = Out::Store;
         q.inner = axis == 0 ? 1 : nx;
         q.n = axis == 0 ? nx : ny;
