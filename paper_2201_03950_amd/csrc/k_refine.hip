@@ -235,6 +235,127 @@ __global__ __launch_bounds__(256) void k_refine_staged(StagedGeom gm, RefPtrs sr
     stage_out<double, M>(x + off, ost, cnt, n, ls);
 }
 
+// ---------------------------------------------------- staged, lean --
+// x lines of per-point s and FP32 d whose P tiles (a power of two up to 64)
+// sit in adjacent lanes of one wavefront: the block's s and d are staged into LDS,
+// and each thread keeps only its tile's s, the FP32 solution and the
+// residual.  Each FP32 solve finds the tile's boundary equations by two
+// streaming sweeps (tile_ends_fn), the reduced system by lane moves (no LDS,
+// no barrier), and the interior by Thomas (Alg. 1) with both end values known.
+// The neighbours of a tile's end rows for the FP64 residual come from the
+// adjacent lanes; d is read again from its staged slots.  Rows past the line
+// are identity rows (s = d = 0, solution 0).
+template <typename TD, int M>
+__global__ __launch_bounds__(256, 3) void k_refine_staged_lean(StagedGeom gm, const float *__restrict__ s,
+                                                            const TD *__restrict__ d, double *__restrict__ x) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int L = gm.L, P = gm.P, n = gm.n, ls = gm.ls;
+    const int reg = L * ls;
+    float *cst = reinterpret_cast<float *>(smem_raw);  // staged s
+    const size_t doff = ((size_t)reg * sizeof(float) + 15) & ~(size_t)15;
+    TD *dst = reinterpret_cast<TD *>(smem_raw + doff);  // staged d
+    const int t = threadIdx.x, p = t % P, l = t / P;
+    const i64 o0 = xcd_block_id() * L;
+    const int nl = (int)((gm.nlines - o0) < (i64)L ? (gm.nlines - o0) : (i64)L);
+    const i64 off = o0 * n;
+    const int cnt = nl * n;
+    stage_in<float, M>(cst, s + off, cnt, n, ls);
+    stage_in<TD, M>(dst, d + off, cnt, n, ls);
+    __syncthreads();
+    const bool act = l < nl;
+    // threads of lines past the block's last line (l < L always) take their
+    // own unstaged slots and mask what they read there
+    const int pos = l * ls + p * (M + 1);
+    const int g0 = p * M;
+    float sv[M], w[M], cs[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const bool v = act && g0 + k < n;
+        const float sk = cst[pos + k];
+        const TD dk = dst[pos + k];
+        sv[k] = v ? sk : 0.f;
+        w[k] = v ? (float)dk : 0.f;
+    }
+    auto rows = [&](int k, float &a, float &b, float &c) {
+        const float sk = sv[k];
+        a = -sk;
+        b = 1.f + 2.f * sk;
+        c = -sk;
+    };
+    auto fence = [&] {
+#pragma unroll
+        for (int k = 0; k < M; ++k) asm volatile("" : "+v"(sv[k]));
+    };
+    // one FP32 solve of the right-hand side in v, in place
+    auto solve32 = [&](float (&v)[M]) {
+        TileEnds<float> e;
+        tile_ends_fn<float, M>(rows, v, e, fence);
+        fence();
+        float f, lv;
+        reduced_solve<float, M>(e, nullptr, 0, P, p, t, 1, f, lv);
+        float cprev = 0.f, dprev = 0.f;
+#pragma unroll
+        for (int k = 1; k < M - 1; ++k) {
+            float a, b, c;
+            rows(k, a, b, c);
+            float rhs = v[k];
+            if (k == 1) {
+                rhs -= a * f;
+                a = 0.f;
+            }
+            if (k == M - 2) {
+                rhs -= c * lv;
+                c = 0.f;
+            }
+            const float r = fast_rcp(b - a * cprev);
+            cprev = c * r;
+            dprev = (rhs - a * dprev) * r;
+            cs[k] = cprev;
+            v[k] = dprev;
+        }
+        v[0] = f;
+        v[M - 1] = lv;
+#pragma unroll
+        for (int k = M - 3; k >= 1; --k) v[k] -= cs[k] * v[k + 1];
+        fence();
+    };
+    solve32(w);
+    // x32 goes to the thread's own staged-s slots (s is in registers now; no
+    // other thread reads them); the neighbours of the tile's end rows come
+    // from the adjacent lanes (0 outside the line)
+    float *xm = cst + pos;
+    double xprev = (double)lane_up(w[M - 1], 1), xnext = (double)lane_down(w[0], 1);
+    if (p == 0) xprev = 0.0;
+    if (p + 1 >= P) xnext = 0.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) xm[k] = w[k];
+    // r = d - A x32 in FP64, into w
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        const bool v = act && g0 + k < n;
+        const double dk = (double)dst[pos + k];
+        const double sk = (double)sv[k];
+        const double um = k > 0 ? (double)xm[k - 1] : xprev;
+        const double up = k < M - 1 ? (double)xm[k + 1] : xnext;
+        const double rk = dk - (-sk * um + (1.0 + 2.0 * sk) * (double)xm[k] - sk * up);
+        w[k] = v ? (float)rk : 0.f;
+    }
+    solve32(w);
+    float xo[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) xo[k] = xm[k];
+    // every thread has read its staged inputs: the area takes the FP64 result
+    // at the same staged positions
+    __syncthreads();
+    double *ost = reinterpret_cast<double *>(smem_raw);
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < M; ++k) ost[pos + k] = (double)xo[k] + (double)w[k];
+    }
+    __syncthreads();
+    stage_out<double, M>(x + off, ost, cnt, n, ls);
+}
+
 // ---------------------------------------------------------------- host --
 
 namespace {
@@ -309,10 +430,25 @@ hipError_t go_lean(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename TD>
+hipError_t go_staged_lean(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
+    StagedGeom g;
+    g.nlines = r.outer;
+    g.n = (int)r.n;
+    g.L = pl.L;
+    g.P = pl.P;
+    g.ls = pl.ls;
+    launch((k_refine_staged_lean<TD, 16>), dim3((unsigned)pl.nblocks), dim3(pl.L * pl.P), pl.shmem, s, g,
+           r.src.s, static_cast<const TD *>(r.d), r.x);
+    return hipGetLastError();
+}
+
 template <typename TD, bool SM>
 hipError_t go_m(const RefineReq &r, const RefPlan &pl, hipStream_t s) {
     if constexpr (SM) {
-        if (pl.lean) return go_lean<TD>(r, pl, s);
+        if (pl.lean && !pl.staged) return go_lean<TD>(r, pl, s);
+        if constexpr (std::is_same<TD, float>::value)
+            if (pl.lean) return go_staged_lean<TD>(r, pl, s);
     }
     if (pl.staged) return pl.M == 32 ? go_staged<TD, 32, SM>(r, pl, s) : go_staged<TD, 16, SM>(r, pl, s);
     return pl.M == 32 ? go_strided<TD, 32, SM>(r, pl, s) : go_strided<TD, 16, SM>(r, pl, s);
@@ -346,6 +482,34 @@ bool plan_refine(const RefineReq &r, RefPlan *pl, std::string *err) {
                     *pl = p;
                     return true;
                 }
+            }
+        }
+    }
+    // x lines of per-point s and FP32 d with P = n / 16 tiles a power of two up
+    // to 64: the register-lean staged kernel (a line's tiles in adjacent lanes
+    // of one wavefront), 256 threads, 3 workgroups per CU (168 VGPRs)
+    if (sm && r.inner == 1 && !r.d_f64 && (!r.force_M || r.force_M == 16)) {
+        const i64 P = cdiv(r.n, 16);
+        if (P <= 64 && (P & (P - 1)) == 0) {
+            const int ls = (int)P * 17;
+            int L = r.force_L ? r.force_L : 256 / (int)P;
+            L = std::max(1, std::min(L, pow2_ceil(r.outer)));
+            const size_t dw = r.d_f64 ? 8 : 4;
+            auto bytes = [&](int LL) {
+                const size_t reg = (size_t)LL * ls;
+                return std::max(((reg * 4 + 15) & ~(size_t)15) + reg * dw, reg * 8) + 16;
+            };
+            if ((i64)L * P <= 256 && bytes(L) <= kMaxShmem && cdiv(r.outer, L) < (i64)1 << 31) {
+                p.M = 16;
+                p.P = (int)P;
+                p.L = L;
+                p.ls = ls;
+                p.staged = true;
+                p.lean = true;
+                p.shmem = bytes(L);
+                p.nblocks = cdiv(r.outer, L);
+                *pl = p;
+                return true;
             }
         }
     }

@@ -28,7 +28,7 @@ struct RefineReq {
 struct RefPlan {
     int M = 16, L = 1, P = 1, ls = 0;
     bool staged = false;
-    bool lean = false;  // strided s-form lines, register-lean tiles (k_refine_lean)
+    bool lean = false;  // s-form lines, register-lean tiles (k_refine_lean; staged: k_refine_staged_lean)
     size_t shmem = 0;
     i64 nblocks = 0;
 };
