@@ -62,14 +62,18 @@ __global__ __launch_bounds__(MAXT) void k_refine_strided(StridedGeom gm, RefPtrs
 
 // --------------------------------------------------------- strided, lean --
 // Rows (-s, 1 + 2 s, -s) from FP32 s on strided lines, with a thread's
-// registers holding only its tile's s, x32 and right-hand side: each FP32
-// solve finds the tile's boundary equations by two streaming sweeps
-// (tile_ends_fn), the reduced system as the other kernels do, and the
-// interior by Thomas (Alg. 1) with the tile's end values known.  d is read
-// again for the FP64 residual (from the caches: the block read it just
-// before), so it is not held in registers.  Rows past the line are identity
-// rows (s = d = 0, solution 0).  32-bit row offsets from the line's first
-// element (the host checks that a line spans less than 2^31 elements).
+// registers holding only its tile's s, its right-hand side and one more tile
+// of values: each FP32 solve finds the tile's boundary equations by two
+// streaming sweeps (tile_ends_fn), the reduced system as the other kernels
+// do, and the interior by Thomas (Alg. 1) with the tile's end values known.
+// d is read from HBM once: its FP32 rounding d32 goes to LDS, and for FP64 d
+// so does the tail fp32(d - d32), so the residual takes d as d32 + tail (48
+// significant bits, a relative error of at most 2^-48 in d).  The tail waits
+// in the thread's x32 slots during the first solve and moves to the
+// registers of the Thomas multipliers once that solve is done.
+// Rows past the line are identity rows (s = d = 0, solution 0).  32-bit row
+// offsets from the line's first element (the host checks that a line spans
+// less than 2^31 elements).
 template <typename TD, int M, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_refine_lean(StridedGeom gm, const float *__restrict__ s,
                                                       const TD *__restrict__ d, double *__restrict__ x) {
@@ -77,6 +81,7 @@ __global__ __launch_bounds__(MAXT) void k_refine_lean(StridedGeom gm, const floa
     const int L = gm.L, P = gm.P, S = L * P, n = gm.n;
     float *red = reinterpret_cast<float *>(smem_raw);  // 6 S: reduced-solve scratch
     float *xs = red + 6 * S;                           // S (M + 1): every tile's x32 (padded)
+    float *dh = xs + S * (M + 1);                      // M S: d32, row k of tile t at k S + t
     const int t = threadIdx.x, l = t % L, p = t / L;
     const i64 blk = xcd_block_id();
     const i64 ib = blk % gm.nib, ob = blk / gm.nib;
@@ -88,17 +93,28 @@ __global__ __launch_bounds__(MAXT) void k_refine_lean(StridedGeom gm, const floa
     const TD *dp = d + base;
     const int g0 = p * M;
     float sv[M], w[M], cs[M];
+    TD dk[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const int g = g0 + k;
         const unsigned o = (act && g < n) ? (unsigned)g * st : 0u;
         sv[k] = sp[o];
-        w[k] = (float)dp[o];
+        dk[k] = dp[o];
     }
     asm volatile("" ::: "memory");
+    // x32 goes to LDS (tile t at t (M + 1)) after the first solve: the residual
+    // reads the tile's rows and the adjacent tiles' boundary rows (tiles p -+ 1
+    // of the line are threads t -+ L) from there; until then the slots hold
+    // the tail of d
+    float *xm = xs + t * (M + 1);
 #pragma unroll
-    for (int k = 0; k < M; ++k)
-        if (!(act && g0 + k < n)) sv[k] = w[k] = 0.f;
+    for (int k = 0; k < M; ++k) {
+        const bool v = act && g0 + k < n;
+        w[k] = v ? (float)dk[k] : 0.f;
+        if constexpr (sizeof(TD) == 8) xm[k] = v ? (float)((double)dk[k] - (double)w[k]) : 0.f;
+        if (!v) sv[k] = 0.f;
+        dh[k * S + t] = w[k];
+    }
     auto rows = [&](int k, float &a, float &b, float &c) {
         const float sk = sv[k];
         a = -sk;
@@ -143,25 +159,23 @@ __global__ __launch_bounds__(MAXT) void k_refine_lean(StridedGeom gm, const floa
         fence();
     };
     solve32();
-    // x32 goes to LDS (tile t at t (M + 1)): the residual reads the tile's rows
-    // and the adjacent tiles' boundary rows (tiles p -+ 1 of the line are
-    // threads t -+ L) from there
-    float *xm = xs + t * (M + 1);
 #pragma unroll
-    for (int k = 0; k < M; ++k) xm[k] = w[k];
+    for (int k = 0; k < M; ++k) {
+        cs[k] = sizeof(TD) == 8 ? xm[k] : 0.f;  // the tail of d
+        xm[k] = w[k];
+    }
     __syncthreads();
     const double xprev = (p > 0) ? (double)xs[(t - L) * (M + 1) + M - 1] : 0.0;
     const double xnext = (p + 1 < P) ? (double)xs[(t + L) * (M + 1)] : 0.0;
-    // r = d - A x32 in FP64, d read again
+    // r = d - A x32 in FP64
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        const int g = g0 + k;
-        const bool v = act && g < n;
-        const double dk = (double)dp[v ? (unsigned)g * st : 0u];
+        const bool v = act && g0 + k < n;
+        const double dd = (double)dh[k * S + t] + (double)cs[k];
         const double sk = (double)sv[k];
         const double um = k > 0 ? (double)xm[k - 1] : xprev;
         const double up = k < M - 1 ? (double)xm[k + 1] : xnext;
-        const double r = dk - (-sk * um + (1.0 + 2.0 * sk) * (double)xm[k] - sk * up);
+        const double r = dd - (-sk * um + (1.0 + 2.0 * sk) * (double)xm[k] - sk * up);
         w[k] = v ? (float)r : 0.f;
     }
     solve32();
@@ -476,7 +490,7 @@ bool plan_refine(const RefineReq &r, RefPlan *pl, std::string *err) {
                 p.P = (int)P;
                 p.L = L;
                 p.lean = true;
-                p.shmem = (size_t)(6 + 17) * L * P * sizeof(float);
+                p.shmem = (size_t)(6 + 17 + 16) * L * P * sizeof(float);
                 p.nblocks = cdiv(r.inner, L) * r.outer;
                 if (p.nblocks < (i64)1 << 31) {
                     *pl = p;
