@@ -476,11 +476,13 @@ bool plan_refine(const RefineReq &r, RefPlan *pl, std::string *err) {
     RefPlan p;
     const bool sm = r.smode;
     // strided lines of per-point s of at least 512 rows: the register-lean
-    // kernel, 16-row tiles, as many adjacent lines as 1024 threads hold
+    // kernel, 16-row tiles, as many adjacent lines as 512 threads hold (two
+    // workgroups per CU, so one's loads overlap the other's solves; 1024
+    // threads for lines of more than 512 tiles)
     if (sm && r.inner > 1 && r.n >= 512 && r.n * r.inner < ((i64)1 << 31) && (!r.force_M || r.force_M == 16)) {
         const i64 P = cdiv(r.n, 16);
         if (P <= 1024) {
-            int L = r.force_L ? r.force_L : pow2_floor(1024 / P);
+            int L = r.force_L ? r.force_L : pow2_floor(std::max<i64>(1, 512 / P));
             if (!r.force_L) {
                 if (r.inner < L) L = std::max(1, pow2_ceil(r.inner));
                 while (L > 4 && cdiv(r.inner, L) * r.outer < 512) L /= 2;

@@ -40,7 +40,10 @@ GEOMS = [((33, 41, 10), 2, 0), ((33, 41, 10), 2, 1), ((33, 41, 10), 2, 2), ((100
          # 16-row tiles up to 4096 rows, 32-row tiles beyond, up to the 8192-row limit
          ((4096, 2), 1, 0), ((4097, 2), 1, 0), ((8192, 2), 1, 0), ((3, 8192), 1, 1),
          # x lines of 2^k 16-row tiles (the register-lean staged kernel), ragged last tiles and blocks
-         ((1017, 5), 1, 0), ((120, 9), 2, 0), ((512, 3), 3, 0)]
+         ((1017, 5), 1, 0), ((120, 9), 2, 0), ((512, 3), 3, 0),
+         # strided lines of >= 512 rows (the register-lean kernel, 512-thread blocks): a ragged
+         # last block of 1024-row lines, z lines of 34 tiles
+         ((37, 1024), 1, 1), ((7, 5, 530), 1, 2)]
 
 
 @pytest.mark.parametrize("d64", [True, False])
