@@ -83,7 +83,7 @@ __global__ __launch_bounds__(MAXT) void k_refine_lean(StridedGeom gm, const floa
     float *xs = red + 6 * S;                           // S (M + 1): every tile's x32 (padded)
     float *dh = xs + S * (M + 1);                      // M S: d32, row k of tile t at k S + t
     const int t = threadIdx.x, l = t % L, p = t / L;
-    const i64 blk = xcd_block_id();
+    const i64 blk = xcd_group_block_id<16>();
     const i64 ib = blk % gm.nib, ob = blk / gm.nib;
     const i64 ii = ib * L + l;
     const bool act = ii < gm.inner;

@@ -375,7 +375,7 @@ __global__ __launch_bounds__(MAXT) void k_strided_lean(StridedGeom gm, const T *
     T *sh = reinterpret_cast<T *>(smem_raw);
     const int L = gm.L, P = gm.P, n = gm.n;
     const int t = threadIdx.x, l = t % L, p = t / L;
-    const i64 blk = xcd_block_id();
+    const i64 blk = xcd_group_block_id<16>();
     const i64 ib = blk % gm.nib, ob = blk / gm.nib;
     const i64 ii = ib * L + l;
     const bool act = ii < gm.inner;

@@ -32,6 +32,21 @@ __device__ __forceinline__ i64 xcd_block_id() {
     return (x < r) ? (i64)x * (q + 1) + idx : (i64)r * (q + 1) + (i64)(x - r) * q + idx;
 }
 
+// Block order for strided lines of many rows, whose consecutive blocks read
+// adjacent segments of the same rows: groups of K consecutive blocks run on
+// one XCD (blocks whose segments share cache lines share its L2), and
+// consecutive groups go to consecutive XCDs, so the blocks dispatched
+// together cover whole rows and each DRAM page is read by many of them at
+// about the same time (the trailing partial round of 8 K blocks keeps its
+// order).  Hardware dispatch sends block i to XCD i mod 8.
+template <unsigned K>
+__device__ __forceinline__ i64 xcd_group_block_id() {
+    const unsigned G = gridDim.x, b = blockIdx.x, W = 8u * K;
+    if (b >= G / W * W) return b;
+    const unsigned x = b & 7u, r = b >> 3;
+    return (i64)(r / K) * W + x * K + r % K;
+}
+
 // Reciprocal for the elimination pivots.  FP32: the hardware reciprocal
 // (about 1 ulp), well inside the FP32 tolerance.  FP64: the hardware estimate
 // refined by two Newton-Raphson steps r <- r + r (1 - x r), each of which

@@ -43,7 +43,9 @@ GEOMS = [((33, 41, 10), 2, 0), ((33, 41, 10), 2, 1), ((33, 41, 10), 2, 2), ((100
          ((1017, 5), 1, 0), ((120, 9), 2, 0), ((512, 3), 3, 0),
          # strided lines of >= 512 rows (the register-lean kernel, 512-thread blocks): a ragged
          # last block of 1024-row lines, z lines of 34 tiles
-         ((37, 1024), 1, 1), ((7, 5, 530), 1, 2)]
+         ((37, 1024), 1, 1), ((7, 5, 530), 1, 2),
+         # 798 blocks of 512-row y lines: the grouped block order's trailing partial round
+         ((600, 512), 21, 1)]
 
 
 @pytest.mark.parametrize("d64", [True, False])

@@ -126,7 +126,10 @@ def test_arrays_any_axis(trid, orc, dt, geom):
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("mode", ["const", "s"])
 @pytest.mark.parametrize("geom", [((33, 41, 10), 2, 0), ((33, 41, 10), 2, 1), ((33, 41, 10), 2, 2),
-                                  ((300, 7), 1, 0), ((7, 300), 1, 1), ((9, 1100), 1, 1), ((6, 4, 1500), 1, 2)])
+                                  ((300, 7), 1, 0), ((7, 300), 1, 1), ((9, 1100), 1, 1), ((6, 4, 1500), 1, 2),
+                                  # 512-row y lines in 672 blocks: the grouped block order's trailing
+                                  # partial round
+                                  ((1000, 512), 21, 1)])
 def test_generated_coefficients(trid, orc, dt, mode, geom):
     dims, batch, axis = geom
     rng = np.random.default_rng(5)
