@@ -73,7 +73,11 @@ __device__ __forceinline__ void const_tile_backsub(const ConstTab<T> &tb, T f, T
 
 // ---------------------------------------------------------------- strided --
 // y / z lines: 64 lanes = 64 adjacent lines, wavefront w = tile w (uniform, so
-// every table read is a scalar load).  Block = 64 lines x P tiles.
+// every table read is a scalar load).  Block = 64 lines x P tiles.  Lines are
+// numbered across outer indices (line j: outer j / inner, inner j % inner), so
+// when inner is not a multiple of 64 a block runs on past the last line of one
+// outer index into the next instead of leaving lanes idle (the planner keeps
+// inner * outer below 2^32).
 
 template <typename T, int M, class Epi>
 __global__ __launch_bounds__(64 * kConstMaxP) void k_strided_const(StridedGeom gm, ConstTab<T> tb,
@@ -82,12 +86,25 @@ __global__ __launch_bounds__(64 * kConstMaxP) void k_strided_const(StridedGeom g
     const int l = threadIdx.x & 63;
     const int p = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int P = tb.P;
-    const i64 blk = xcd_block_id();
-    const i64 ib = blk % gm.nib, ob = blk / gm.nib;
-    const i64 ii = ib * 64 + l;
-    const bool act = ii < gm.inner;
+    // the block's first line is split by one scalar division; a lane moves on
+    // by at most one outer index when inner >= 64
+    const unsigned in = (unsigned)gm.inner;
+    const unsigned j0 = (unsigned)xcd_block_id() * 64u;
+    const unsigned ob0 = j0 / in, ii0 = j0 - ob0 * in;
+    const bool act = j0 + (unsigned)l < gm.lines;
+    unsigned ob = ob0, ii = ii0 + (unsigned)l;
+    if (in >= 64u) {
+        if (ii >= in) {
+            ii -= in;
+            ++ob;
+        }
+    } else {
+        ob += ii / in;
+        ii %= in;
+    }
+    if (!act) ob = ii = 0u;
     const i64 st = gm.inner;
-    const i64 base = ob * (i64)gm.n * st + (act ? ii : 0);
+    const i64 base = (i64)ob * (i64)gm.n * st + ii;
     const int g0 = p * M;
     // rows of one tile lie within one slab of n * inner < 2^31 elements (planner):
     // 32-bit offsets from the tile's first row

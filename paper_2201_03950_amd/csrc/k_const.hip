@@ -168,7 +168,8 @@ hipError_t go_strided(const LineReq &r, const ConstTab<T> &tb, Epi epi, hipStrea
     g.n = (int)r.n;
     g.L = 64;
     g.P = tb.P;
-    const i64 nb = g.nib * r.outer;
+    g.lines = (unsigned)(r.inner * r.outer);
+    const i64 nb = cdiv(r.inner * r.outer, 64);
     launch((k_strided_const<T, M, Epi>), dim3((unsigned)nb), dim3(64 * tb.P), 0, s, g, tb,
                        static_cast<const T *>(r.d), epi);
     return hipGetLastError();
@@ -310,6 +311,7 @@ int const_lines_M(const LineReq &r) {
     if (r.mode != Mode::Const || (r.out != Out::Store && r.out != Out::Add)) return 0;
     if (r.inner == 1 && r.out != Out::Store) return 0;
     if (r.n * r.inner >= ((i64)1 << 31)) return 0;  // 32-bit row offsets within a slab
+    if (r.inner > 1 && r.inner * r.outer >= ((i64)1 << 32)) return 0;  // 32-bit line numbers
     const int M = r.inner == 1 ? const_staged_M(r.n, r.f64 ? 8 : 4, r.force_M) : const_M(r.n, r.force_M);
     if (!M) return 0;
     if (r.inner == 1) {

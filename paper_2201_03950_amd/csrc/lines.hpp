@@ -28,6 +28,7 @@ struct StridedGeom {
     int n;      // line length
     int L;      // lines per block
     int P;      // tiles per line
+    unsigned lines = 0;  // inner * outer (k_strided_const: lines numbered across outer indices)
 };
 
 // ------------------------------------------------------------------ sources --

@@ -217,7 +217,7 @@ KernelPred line_kernel(const char *name, const LineReq &q, int launches, std::st
         const int P = (int)(q.n / cm);
         int words = 2 + (q.out == Out::Add ? 1 : 0);
         const double rows = (double)q.n * (double)q.inner * (double)q.outer;
-        const i64 nb = ((q.inner + 63) / 64) * q.outer;
+        const i64 nb = (q.inner * q.outer + 63) / 64;
         return stream_kernel(name, "const_lines", words * w * rows, nb, 64 * P, 2.0 * 8 * 64 * w, cm, w, ap.cs_eff,
                              ap.cs_blk_us, launches);
     }

@@ -414,7 +414,11 @@ def test_s_adjoint_x_lines(trid, orc, dt, n, lines):
 
 CONST_GEOMS = [((64, 96, 32), 2, 0), ((64, 96, 32), 2, 1), ((64, 96, 32), 2, 2),
                ((256, 3), 5, 0), ((100, 256), 1, 1), ((70, 3, 128), 1, 2), ((32,), 7, 0),
-               ((80, 7), 3, 0), ((96, 5, 3), 2, 0), ((48, 9), 4, 0), ((112, 3), 5, 0), ((160, 3), 2, 0)]
+               ((80, 7), 3, 0), ((96, 5, 3), 2, 0), ((48, 9), 4, 0), ((112, 3), 5, 0), ((160, 3), 2, 0),
+               # strided lines whose count per outer index is not a multiple of 64: blocks run on
+               # across outer indices
+               ((80, 80, 9), 2, 1), ((80, 80, 9), 2, 2), ((96, 40, 7), 1, 1), ((33, 41, 10), 2, 1),
+               ((33, 41, 10), 2, 2)]
 
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
@@ -430,7 +434,8 @@ def test_const_fast_path_matches_oracle(trid, orc, dt, geom):
 
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("dims,batch", [((64, 96, 32), 2), ((256, 40, 24), 1), ((128, 70), 3),
-                                         ((32, 3, 5), 2), ((64, 5, 7), 3), ((64, 1, 9), 1), ((32, 2), 5)])
+                                         ((32, 3, 5), 2), ((64, 5, 7), 3), ((64, 1, 9), 1), ((32, 2), 5),
+                                         ((80, 80, 80), 1), ((96, 24, 40), 2)])
 def test_adi_const_fast_path_matches_oracle(trid, orc, dt, dims, batch):
     u = gen.adi3d_field(dims, batch, seed=4).astype(dt)
     ref = orc.adi_step(u, s0=0.2, nsteps=3)
