@@ -133,6 +133,18 @@ int trid_set_tile(trid_handle_t h, int M, int L);
 int trid_timing_enable(trid_handle_t h, int on);
 int trid_timing_read(trid_handle_t h, char *buf, int64_t len);
 
+/* Thin out the per-kernel timing: only launches named `name` (a name that
+ * trid_timing_read reports, such as "adi_z_update"; NULL or "" = every name),
+ * and of each timed name only every `every`-th launch (the first after this
+ * call, then every `every`-th).  The other launches run without events, which
+ * cost a few microseconds of dispatch time each; with name NULL and every = k,
+ * a loop of steps is stamped in every k-th step.  (NULL, 1) times every launch
+ * again.  Like trid_timing_enable, it first waits for pending events and
+ * clears the totals; it does not switch timing on or off.
+ * Errors: TRID_ERR_ARG (NULL handle, name over 200 characters, every < 1),
+ * TRID_ERR_HIP. */
+int trid_timing_select(trid_handle_t h, const char *name, int every);
+
 /* ------------------------------------------------------- batched solves -- */
 
 /* Solve every line of `axis` of `batch` meshes: A x = d with per-point

@@ -38,4 +38,5 @@ from ._binding import (  # noqa: F401
     set_tile,
     timing_enable,
     timing_read,
+    timing_select,
 )

@@ -40,6 +40,7 @@ SIGNATURES = {
     "trid_set_tile": ([_H, _I, _I], _I),
     "trid_timing_enable": ([_H, _I], _I),
     "trid_timing_read": ([_H, ctypes.c_char_p, _I64], _I),
+    "trid_timing_select": ([_H, ctypes.c_char_p, _I], _I),
     "trid_gtsv_batched": ([_H, _I, _P, _P, _P, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_const": ([_H, _I, _D, _D, _D, _P, _I, _I64P, _I, _I64], _I),
     "trid_gtsv_batched_s": ([_H, _I, _P, _P, _I, _I64P, _I, _I64], _I),
@@ -170,6 +171,12 @@ def timing_enable(on=True):
     """Bracket this thread's later launches with HIP events (clears totals)."""
     h = handle()
     _check(load_library().trid_timing_enable(h, 1 if on else 0), h)
+
+
+def timing_select(name=None, every=1):
+    """Time only launches named ``name`` (None: every name), every ``every``-th of each; clears totals."""
+    h = handle()
+    _check(load_library().trid_timing_select(h, name.encode() if name else None, int(every)), h)
 
 
 def timing_read():

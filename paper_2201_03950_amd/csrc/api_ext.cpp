@@ -96,6 +96,20 @@ int trid_timing_enable(trid_handle_t h, int on) {
     return TRID_OK;
 }
 
+int trid_timing_select(trid_handle_t h, const char *name, int every) {
+    if (!h) return TRID_ERR_ARG;
+    if (name && strlen(name) > 200) return trid::handle_fail(h, TRID_ERR_ARG, "kernel name too long");
+    if (every < 1) return trid::handle_fail(h, TRID_ERR_ARG, "every must be >= 1");
+    trid::ExtState &x = trid::handle_ext(h);
+    hipError_t e = x.timer.flush();
+    if (e != hipSuccess) return trid::handle_hip_fail(h, e, "timing flush");
+    x.timer.acc.clear();
+    x.timer.only = name ? name : "";
+    x.timer.every = every;
+    x.timer.seen.clear();
+    return TRID_OK;
+}
+
 int trid_timing_read(trid_handle_t h, char *buf, int64_t len) {
     if (!h || !buf || len < 3) return h ? trid::handle_fail(h, TRID_ERR_ARG, "bad buffer") : TRID_ERR_ARG;
     trid::ExtState &x = trid::handle_ext(h);

@@ -24,9 +24,20 @@ struct VarlenSchedule;  // defined with the uneven-batch solver
 // end of the kernel, see launch()); time_recorded() brackets work that is not
 // a direct kernel launch (a graph launch) with two events recorded on the
 // stream.  flush() waits for them and accumulates (count, milliseconds) per
-// name.  Launches under graph capture are not timed.
+// name.  Launches under graph capture are not timed.  A non-empty `only`
+// restricts timing to launches of that name (the others run without events);
+// `every` > 1 times only every `every`-th launch of each timed name, counting
+// from the first after the selection.
 struct KernelTimer {
     bool on = false;
+    std::string only;
+    long every = 1;
+    std::map<std::string, long> seen;
+    bool wants(const char *name) {
+        if (!on) return false;
+        if (!only.empty() && only != name) return false;
+        return every <= 1 || seen[name]++ % every == 0;
+    }
     struct Pending {
         std::string name;
         hipEvent_t e0, e1;
@@ -49,7 +60,7 @@ struct KernelTimer {
     template <class F>
     hipError_t time(const char *name, hipStream_t st, F &&f) {
         (void)st;
-        if (!on) return f();
+        if (!wants(name)) return f();
         hipEvent_t e0 = take(), e1 = take();
         if (!e0 || !e1) return f();
         LaunchEvents &ev = launch_events();
@@ -70,7 +81,7 @@ struct KernelTimer {
     // f() enqueues work on st that is not a direct kernel launch.
     template <class F>
     hipError_t time_recorded(const char *name, hipStream_t st, F &&f) {
-        if (!on) return f();
+        if (!wants(name)) return f();
         hipEvent_t e0 = take(), e1 = take();
         if (!e0 || !e1) return f();
         hipEventRecord(e0, st);

@@ -127,6 +127,16 @@ def test_set_tile_validation(lib, h):
     assert lib.trid_set_tile(None, 0, 0) == 1
 
 
+def test_timing_select_validation(lib, h):
+    assert lib.trid_timing_select(None, b"adi_y", 1) == 1
+    assert lib.trid_timing_select(h, b"x" * 201, 1) == 1
+    assert lib.trid_timing_select(h, b"adi_y", 0) == 1
+    assert lib.trid_timing_select(h, b"adi_z_update", 4) == 0
+    assert lib.trid_timing_select(h, None, 0) == 1
+    assert lib.trid_timing_select(h, None, 3) == 0
+    assert lib.trid_timing_select(h, b"", 1) == 0
+
+
 def test_set_stream_and_error_text(lib, h):
     assert lib.trid_set_stream(h, None) == 0
     assert lib.trid_set_stream(None, None) == 1
