@@ -77,7 +77,7 @@ __device__ __forceinline__ void const_tile_backsub(const ConstTab<T> &tb, T f, T
 // numbered across outer indices (line j: outer j / inner, inner j % inner), so
 // when inner is not a multiple of 64 a block runs on past the last line of one
 // outer index into the next instead of leaving lanes idle (the planner keeps
-// inner * outer below 2^32).
+// inner * outer below 2^31).
 
 template <typename T, int M, class Epi>
 __global__ __launch_bounds__(64 * kConstMaxP) void k_strided_const(StridedGeom gm, ConstTab<T> tb,

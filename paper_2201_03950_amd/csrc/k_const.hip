@@ -311,7 +311,8 @@ int const_lines_M(const LineReq &r) {
     if (r.mode != Mode::Const || (r.out != Out::Store && r.out != Out::Add)) return 0;
     if (r.inner == 1 && r.out != Out::Store) return 0;
     if (r.n * r.inner >= ((i64)1 << 31)) return 0;  // 32-bit row offsets within a slab
-    if (r.inner > 1 && r.inner * r.outer >= ((i64)1 << 32)) return 0;  // 32-bit line numbers
+    // 32-bit line numbers: a block's first line plus its lane stays below 2^32
+    if (r.inner > 1 && r.inner * r.outer >= ((i64)1 << 31)) return 0;
     const int M = r.inner == 1 ? const_staged_M(r.n, r.f64 ? 8 : 4, r.force_M) : const_M(r.n, r.force_M);
     if (!M) return 0;
     if (r.inner == 1) {
