@@ -341,11 +341,13 @@ __device__ __forceinline__ void vlw_finish(int *counter) {
     }
 }
 
-// PIPE: the next array's loads are issued before the current one is staged
-// (more loads in flight, more registers).
+// PIPE: 0 loads and stages one array at a time; 1 issues the next array's
+// loads before the current one is staged; 2 issues all four arrays' loads
+// before the first is staged (the most loads in flight; the raw tiles then
+// occupy no more registers than the elimination that follows).
 // WPE: wavefronts per SIMD the register allocation must allow (two
 // workgroups of 8 wavefronts per CU need 4).
-template <typename T, int M, int NW, bool PIPE, int WPE = 1>
+template <typename T, int M, int NW, int PIPE, int WPE = 1>
 __global__ __launch_bounds__(WL *NW, WPE) void k_vlw_plain(VlwArgs g) {
     using Lds = VlwLds<M, NW, T, T>;
     __shared__ int s_next[2];
@@ -373,7 +375,27 @@ __global__ __launch_bounds__(WL *NW, WPE) void k_vlw_plain(VlwArgs g) {
         const LanePlace L = vlw_place<M>(g, sl, w, lane, map);
         vlw_ranges<M>(L, lane, s_base, s_cnt);
         T ra[M], rb[M], rc[M], rd[M];
-        {
+        if constexpr (PIPE == 2) {
+            T v[4][M];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) vlw_load<T, M>(v[r], arr[r], s_base, s_cnt, lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                vlw_put<T, M>(st, v[r], lane);
+                wave_sync();
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    const int row = L.p * M + k;
+                    const bool ok = L.act && row < L.n;
+                    const T val = st[lane * (M + 1) + k];
+                    if (r == 0) ra[k] = (ok && row > 0) ? val : T(0);
+                    if (r == 1) rb[k] = ok ? val : T(1);
+                    if (r == 2) rc[k] = (ok && row < L.n - 1) ? val : T(0);
+                    if (r == 3) rd[k] = ok ? val : T(0);
+                }
+                wave_sync();
+            }
+        } else {
             T vn[M];
             vlw_load<T, M>(vn, arr[0], s_base, s_cnt, lane);
 #pragma unroll
@@ -583,10 +605,10 @@ template <class F>
 auto with_wave_kernel(int prec, int M, int NW, F &&f) -> decltype(f(k_vlw_refine<16, 8>, 512, size_t(0))) {
     if (prec == 2) return f(k_vlw_refine<16, 8>, 512, VlwLds<16, 8, double, float>::bytes(2));
     if (prec == 0 && M == 8)  // 16 wavefronts, 4 per SIMD: 128 VGPRs (28 bytes per lane spilled)
-        return f(k_vlw_plain<double, 8, 16, true>, 1024, VlwLds<8, 16, double, double>::bytes(1));
-    if (prec == 0) return f(k_vlw_plain<double, 16, 8, true>, 512, VlwLds<16, 8, double, double>::bytes(1));
-    if (M == 32) return f(k_vlw_plain<float, 32, 4, true>, 256, VlwLds<32, 4, float, float>::bytes(1));
-    return f(k_vlw_plain<float, 16, 8, false, 4>, 512, VlwLds<16, 8, float, float>::bytes(1));
+        return f(k_vlw_plain<double, 8, 16, 1>, 1024, VlwLds<8, 16, double, double>::bytes(1));
+    if (prec == 0) return f(k_vlw_plain<double, 16, 8, 2>, 512, VlwLds<16, 8, double, double>::bytes(1));
+    if (M == 32) return f(k_vlw_plain<float, 32, 4, 1>, 256, VlwLds<32, 4, float, float>::bytes(1));
+    return f(k_vlw_plain<float, 16, 8, 2, 4>, 512, VlwLds<16, 8, float, float>::bytes(1));
 }
 
 template <class K>
