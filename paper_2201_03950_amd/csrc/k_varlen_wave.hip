@@ -492,17 +492,15 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
         float ra[M], rb[M], rc[M];
         double dd[M];
         {
-            float vn[M];
+            // every array's loads of the item in flight before the first is staged
+            float vn[3][M];
             double vd[M];
-            vlw_load<float, M>(vn, arr[0], s_base, s_cnt, lane);
+#pragma unroll
+            for (int r = 0; r < 3; ++r) vlw_load<float, M>(vn[r], arr[r], s_base, s_cnt, lane);
+            vlw_load<double, M>(vd, dg, s_base, s_cnt, lane);
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
-                float vc[M];
-#pragma unroll
-                for (int k = 0; k < M; ++k) vc[k] = vn[k];
-                if (r < 2) vlw_load<float, M>(vn, arr[r + 1], s_base, s_cnt, lane);
-                if (r == 2) vlw_load<double, M>(vd, dg, s_base, s_cnt, lane);  // in flight while c is staged
-                vlw_put<float, M>(stf, vc, lane);
+                vlw_put<float, M>(stf, vn[r], lane);
                 wave_sync();
 #pragma unroll
                 for (int k = 0; k < M; ++k) {
