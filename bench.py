@@ -544,6 +544,7 @@ def extra_perf_model(trid):
     import numpy as np
     import torch
 
+    from paper_2201_03950_amd.model_calibrate import kernel_median_us
     from workloads import gen
 
     errs, worst = [], []
@@ -572,17 +573,10 @@ def extra_perf_model(trid):
                             b = a.abs() + c.abs() + 1.0
                             call = lambda: trid.gtsv(a, b, c, d, axis)  # noqa: E731
                         pred, _ = trid.model_gtsv(dt, form, dims, axis, batch)
-                        # the first event-stamped launch of a kernel carries a one-time
-                        # cost: warm up with timing on, then restart the accumulators
-                        trid.timing_enable(True)
-                        call()
-                        sync()
-                        trid.timing_enable(True)
-                        for _ in range(5):
-                            call()
-                        (k, ms), = trid.timing_read().values()
-                        trid.timing_enable(False)
-                        meas = ms / k * 1e3
+                        # steady-state kernel time: the median of individually timed calls
+                        # after warm-up calls (the first launches on freshly allocated
+                        # arrays can take several times as long)
+                        meas = kernel_median_us(trid, call)
                         e = abs(pred - meas) / meas
                         errs.append(e)
                         worst.append((e, "%s form%d axis%d n%d rows%d pred %.1f meas %.1f" % (

@@ -5,7 +5,8 @@
     python -m paper_2201_03950_amd.model_calibrate adi-sweep OUT.jsonl   # on the GPU
     python -m paper_2201_03950_amd.model_calibrate adi-fit OUT.jsonl     # on any host
 
-``sweep`` measures kernel durations (dispatch-stamped events) of the batched
+``sweep`` measures kernel durations (dispatch-stamped events; the median of
+individually timed calls after warm-up calls, ``kernel_median_us``) of the batched
 line solves over both forms (s and coefficient arrays), FP64 and FP32, x/y/z
 lines of 32..8192 rows, 2^16..2^24 rows per call, automatic and forced tile
 plans, together with each launch's plan (``model_gtsv``); and every plan of the
@@ -54,6 +55,25 @@ def _mixes():
     return m
 
 
+def kernel_median_us(trid, call, reps=7, warm=3):
+    """Median kernel microseconds of `reps` individually timed calls of `call`
+    (one kernel launch each), after `warm` calls on the timed launch path: the
+    first launches on freshly allocated arrays, or after a large free, can take
+    several times the steady-state duration."""
+    trid.timing_enable(True)
+    for _ in range(warm):
+        call()
+    ts = []
+    for _ in range(reps):
+        trid.timing_enable(True)  # waits for pending events, clears the totals
+        call()
+        (k, ms), = trid.timing_read().values()
+        ts.append(ms / k * 1e3)
+    trid.timing_enable(False)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
 def sweep(path):
     import numpy as np
     import torch
@@ -95,17 +115,10 @@ def sweep(path):
                                 pred, plan = trid.model_gtsv(dt, form, dims, axis, batch)
                             except trid.TridError:
                                 continue
-                            trid.timing_enable(True)  # warm up with timing on, then restart
-                            call()
-                            torch.cuda.synchronize()
-                            trid.timing_enable(True)
-                            for _ in range(3 if size >= (1 << 24) else 10):
-                                call()
-                            (k, ms), = trid.timing_read().values()
-                            trid.timing_enable(False)
+                            meas = kernel_median_us(trid, call)
                             out.write(json.dumps({"kind": "lines", "dtype": str(dt)[6:], "form": form, "axis": axis,
                                                   "n": n, "size": size, "dims": dims, "batch": batch, "force_M": M,
-                                                  "meas_us": ms / k * 1e3, "pred_us": pred, "plan": plan}) + "\n")
+                                                  "meas_us": meas, "pred_us": pred, "plan": plan}) + "\n")
                         trid.set_tile(0, 0)
                         torch.cuda.empty_cache()
             print("lines %s form %d done" % (dt, form), flush=True)
