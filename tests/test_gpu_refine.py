@@ -45,7 +45,9 @@ GEOMS = [((33, 41, 10), 2, 0), ((33, 41, 10), 2, 1), ((33, 41, 10), 2, 2), ((100
          # last block of 1024-row lines, z lines of 34 tiles
          ((37, 1024), 1, 1), ((7, 5, 530), 1, 2),
          # 798 blocks of 512-row y lines: the grouped block order's trailing partial round
-         ((600, 512), 21, 1)]
+         ((600, 512), 21, 1),
+         # y and z lines of 1, 2 and 3 rows
+         ((6, 1), 2, 1), ((70, 2), 2, 1), ((4, 3, 3), 2, 2)]
 
 
 @pytest.mark.parametrize("d64", [True, False])

@@ -109,6 +109,8 @@ GEOMS = [
     ((1,), 9, 0), ((2,), 9, 0), ((3,), 9, 0),
     ((64, 1000), 1, 1), ((1000, 5), 1, 0), ((9, 10, 129), 1, 2),
     ((130, 1, 17), 2, 1),
+    # y and z lines shorter than a tile: 1, 2 and 3 rows
+    ((6, 1), 2, 1), ((6, 2), 2, 1), ((5, 3), 3, 1), ((4, 3, 1), 2, 2), ((4, 3, 2), 2, 2), ((70, 2, 3), 1, 2),
 ]
 
 
@@ -129,7 +131,10 @@ def test_arrays_any_axis(trid, orc, dt, geom):
                                   ((300, 7), 1, 0), ((7, 300), 1, 1), ((9, 1100), 1, 1), ((6, 4, 1500), 1, 2),
                                   # 512-row y lines in 672 blocks: the grouped block order's trailing
                                   # partial round
-                                  ((1000, 512), 21, 1)])
+                                  ((1000, 512), 21, 1),
+                                  # y and z lines of 1, 2 and 3 rows
+                                  ((6, 1), 2, 1), ((70, 2), 2, 1), ((5, 3), 3, 1), ((4, 3, 1), 2, 2),
+                                  ((65, 3, 2), 2, 2), ((9, 4, 3), 1, 2)])
 def test_generated_coefficients(trid, orc, dt, mode, geom):
     dims, batch, axis = geom
     rng = np.random.default_rng(5)
