@@ -61,11 +61,20 @@ extern "C" {
 typedef struct trid_handle_s *trid_handle_t;
 typedef void *trid_stream_t; /* a hipStream_t; NULL is the null stream */
 
-typedef enum { TRID_F32 = 0, TRID_F64 = 1 } trid_dtype_t;
+/* (the two sentinels give the enum the range of int, so an out-of-range
+ * value a caller passes is still a value of the type, which the entry points
+ * reject with TRID_ERR_ARG) */
+typedef enum { TRID_F32 = 0, TRID_F64 = 1, TRID_DTYPE_MIN_ = -0x7fffffff - 1, TRID_DTYPE_MAX_ = 0x7fffffff } trid_dtype_t;
 
 /* precision of a solve: plain FP64, plain FP32, or FP32 bulk solves with one
  * FP64 residual and refinement sweep */
-typedef enum { TRID_PREC_F64 = 0, TRID_PREC_F32 = 1, TRID_PREC_F32_REFINE64 = 2 } trid_prec_t;
+typedef enum {
+    TRID_PREC_F64 = 0,
+    TRID_PREC_F32 = 1,
+    TRID_PREC_F32_REFINE64 = 2,
+    TRID_PREC_MIN_ = -0x7fffffff - 1, /* range sentinels, as for trid_dtype_t */
+    TRID_PREC_MAX_ = 0x7fffffff
+} trid_prec_t;
 
 enum {
     TRID_OK = 0,
