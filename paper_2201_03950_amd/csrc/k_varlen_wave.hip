@@ -189,6 +189,57 @@ __device__ __forceinline__ void vlw_store(E *__restrict__ dst, const E *__restri
     }
 }
 
+// The tile sweep of eq. (7) run on the tile's two halves side by side (two
+// independent dependency chains per lane instead of one twice as long), the
+// halves then joined into the whole tile's boundary equations: eliminating
+// the two unknowns where they meet, l_A (last of the upper half) and f_B
+// (first of the lower half), is the tiles' own reduction applied to a pair of
+// half-tiles.  Both are kept as functions of the tile's f and l:
+//     f_B = bt + bf f + bl l,   l_A = dt + df f + dl l.
+template <typename T, int M>
+struct HalfTiles : TileEnds<T> {
+    TileState<T, M / 2> A, B;
+    T bt, bf, bl, dt, df, dl;
+};
+
+template <typename T, int M>
+__device__ __forceinline__ void half_eliminate(const T (&ra)[M], const T (&rb)[M], const T (&rc)[M],
+                                               const T (&rd)[M], HalfTiles<T, M> &s) {
+    constexpr int H = M / 2;
+    using Half = const T(&)[H];
+    tile_eliminate<T, H>(reinterpret_cast<Half>(ra[0]), reinterpret_cast<Half>(rb[0]),
+                         reinterpret_cast<Half>(rc[0]), reinterpret_cast<Half>(rd[0]), s.A);
+    tile_eliminate<T, H>(reinterpret_cast<Half>(ra[H]), reinterpret_cast<Half>(rb[H]),
+                         reinterpret_cast<Half>(rc[H]), reinterpret_cast<Half>(rd[H]), s.B);
+    const TileState<T, H> &A = s.A, &B = s.B;
+    // B's first row fa_B l_A + fb_B f_B + fc_B l = fd_B with A's last row l_A = ld_A - la_A f - lc_A f_B
+    const T rg = fast_rcp(B.fb - B.fa * A.lc);
+    s.bt = (B.fd - B.fa * A.ld) * rg;
+    s.bf = B.fa * A.la * rg;
+    s.bl = -B.fc * rg;
+    s.dt = A.ld - A.lc * s.bt;
+    s.df = -A.la - A.lc * s.bf;
+    s.dl = -A.lc * s.bl;
+    // the tile's first row is A's with l_A substituted, its last row B's with f_B substituted
+    s.fa = A.fa;
+    s.fb = A.fb + A.fc * s.df;
+    s.fc = A.fc * s.dl;
+    s.fd = A.fd - A.fc * s.dt;
+    const T rn = fast_rcp(T(1) + B.la * s.bl);
+    s.la = B.la * s.bf * rn;
+    s.lc = B.lc * rn;
+    s.ld = (B.ld - B.la * s.bt) * rn;
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void half_backsub(const HalfTiles<T, M> &s, T f, T lv, T (&u)[M]) {
+    constexpr int H = M / 2;
+    const T fB = s.bt + s.bf * f + s.bl * lv;
+    const T lA = s.dt + s.df * f + s.dl * lv;
+    tile_backsub<T, H>(s.A, f, lA, reinterpret_cast<T(&)[H]>(u[0]));
+    tile_backsub<T, H>(s.B, fB, lv, reinterpret_cast<T(&)[H]>(u[H]));
+}
+
 // One PCR level (Alg. 2) across lanes: neighbours at distance S within the
 // lane's segment [lane - q, lane - q + Q).
 template <typename T>
@@ -420,8 +471,8 @@ __global__ __launch_bounds__(WL *NW, WPE) void k_vlw_plain(VlwArgs g) {
                 wave_sync();
             }
         }
-        TileState<T, M> ts;
-        tile_eliminate<T, M>(ra, rb, rc, rd, ts);
+        HalfTiles<T, M> ts;
+        half_eliminate<T, M>(ra, rb, rc, rd, ts);
         T f, lv;
         T y = T(0), v = T(0), wv = T(0);
         T *xb = xbuf + par * (2 * NW * 4);
@@ -443,7 +494,7 @@ __global__ __launch_bounds__(WL *NW, WPE) void k_vlw_plain(VlwArgs g) {
             lv = lane == WL - 1 ? Lw : ts.ld - ts.la * f - ts.lc * fn;
         }
         T u[M];
-        tile_backsub<T, M>(ts, f, lv, u);
+        half_backsub<T, M>(ts, f, lv, u);
 #pragma unroll
         for (int k = 0; k < M; ++k) st[lane * (M + 1) + k] = u[k];
         wave_sync();
@@ -602,7 +653,7 @@ __global__ __launch_bounds__(WL *NW) void k_vlw_refine(VlwArgs g) {
 template <class F>
 auto with_wave_kernel(int prec, int M, int NW, F &&f) -> decltype(f(k_vlw_refine<16, 8>, 512, size_t(0))) {
     if (prec == 2) return f(k_vlw_refine<16, 8>, 512, VlwLds<16, 8, double, float>::bytes(2));
-    if (prec == 0 && M == 8)  // 16 wavefronts, 4 per SIMD: 128 VGPRs (28 bytes per lane spilled)
+    if (prec == 0 && M == 8)  // 16 wavefronts, 4 per SIMD: 128 VGPRs (40 bytes per lane spilled)
         return f(k_vlw_plain<double, 8, 16, 1>, 1024, VlwLds<8, 16, double, double>::bytes(1));
     if (prec == 0) return f(k_vlw_plain<double, 16, 8, 2>, 512, VlwLds<16, 8, double, double>::bytes(1));
     if (M == 32) return f(k_vlw_plain<float, 32, 4, 1>, 256, VlwLds<32, 4, float, float>::bytes(1));
