@@ -101,6 +101,21 @@ def time_calls(fn, reps, warm=2):
     return (time.perf_counter() - t0) / reps
 
 
+def timed_calls(trid, fn, reps, warm=2):
+    """(mean wall seconds per call, per-kernel timings) of `reps` calls of fn()
+    with the library's kernel timer on; the `warm` calls before them run with
+    the timer off (the first launches after an allocation or a free can take
+    several times the steady-state time)."""
+    for _ in range(warm):
+        fn()
+    sync()
+    trid.timing_enable(True)
+    t = time_calls(fn, reps, warm=0)
+    kt = trid.timing_read()
+    trid.timing_enable(False)
+    return t, kt
+
+
 def adi_main(trid, steps, warmup):
     import torch
 
@@ -180,10 +195,7 @@ def extra_workloads(trid):
     for _ in range(5):  # fresh allocations: first touches stay out of the timing
         trid.adi_step(u, s0=0.2, nsteps=1)
     sync()
-    trid.timing_enable(True)
-    t = time_calls(lambda: trid.adi_step(u, s0=0.2, nsteps=1), 10)
-    kt = trid.timing_read()
-    trid.timing_enable(False)
+    t, kt = timed_calls(trid, lambda: trid.adi_step(u, s0=0.2, nsteps=1), 10)
     pts = 256 ** 3
     words = {"adi_stencil_x": 2, "adi_y": 2, "adi_z_update": 3}
     out["adi3d_256_f32"] = {"ms_per_step": round(t * 1e3, 4), "kernels": {
@@ -232,10 +244,7 @@ def extra_workloads(trid):
         ta, tb, tc, td = (torch.from_numpy(v).cuda() for v in arr)
         del arr
         axis = 0 if lay == "x" else 1
-        trid.timing_enable(True)
-        t = time_calls(lambda: trid.gtsv(ta, tb, tc, td, axis), 10)
-        kt = trid.timing_read()
-        trid.timing_enable(False)
+        t, kt = timed_calls(trid, lambda: trid.gtsv(ta, tb, tc, td, axis), 10)
         name, (cnt, ms) = next(iter(kt.items()))
         kern = ms / cnt * 1e-3
         byts = alg_bytes("arrays", 8, nsys * 256)
@@ -379,10 +388,7 @@ def extra_long(trid):
         else:
             ax = _apply_rows(tb[:2], x, 0)
         resid = _err_vs(d0[:2], ax)
-        trid.timing_enable(True)
-        t = time_calls(call, 10)
-        kt = trid.timing_read()
-        trid.timing_enable(False)
+        t, kt = timed_calls(trid, call, 10)
         cnt, ms = kt["gtsv_long"]
         kern = ms / cnt * 1e-3
         byts = alg_bytes(mode, 8, nl * n)
@@ -420,10 +426,7 @@ def extra_small_batched(trid):
                 res = {}
                 for mode in ("resident", "streamed"):
                     stream = mode == "streamed"
-                    trid.timing_enable(True)
-                    t = time_calls(lambda: trid.adi_step(u, s0=0.2, nsteps=steps, stream=stream), 2, warm=1)
-                    kt = trid.timing_read()
-                    trid.timing_enable(False)
+                    t, kt = timed_calls(trid, lambda: trid.adi_step(u, s0=0.2, nsteps=steps, stream=stream), 2, warm=1)
                     if mode == "resident" and "adi2d_resident" not in kt:
                         continue  # does not fit one workgroup's LDS
                     pts = batch * n * n * steps
@@ -710,6 +713,9 @@ def extra_varlen(trid):
 
     a32, b32, c32, d64, off = gen.varlen_batch()
     rows = int(off[-1])
+    # Each precision's first call times its candidate plans and frees the
+    # losers' schedules; the launches after it run slower for a few
+    # milliseconds, so ten untimed calls precede each timed ten.
     # fresh device allocations for the arrays (torch's cached blocks of the
     # earlier workloads released first): the work items read them at scattered
     # positions, and placements inside reused blocks measured up to 18% slower
@@ -722,10 +728,7 @@ def extra_varlen(trid):
     tune = {}
     trid.gtsv_varlen(trid.PREC_F64, a64, b64, c64, td, x64, off)  # the autotuned first call
     tune["f64"] = trid.autotune_report()
-    trid.timing_enable(True)
-    time_calls(lambda: trid.gtsv_varlen(trid.PREC_F64, a64, b64, c64, td, x64, off), 10)
-    kt = trid.timing_read()
-    trid.timing_enable(False)
+    _, kt = timed_calls(trid, lambda: trid.gtsv_varlen(trid.PREC_F64, a64, b64, c64, td, x64, off), 10, warm=10)
     cnt, ms = kt["varlen"]
     kern = ms / cnt * 1e-3
     byts = alg_bytes("arrays", 8, rows)
@@ -736,10 +739,7 @@ def extra_varlen(trid):
     x32 = torch.empty_like(td32)
     trid.gtsv_varlen(trid.PREC_F32, ta, tb, tc, td32, x32, off)
     tune["f32"] = trid.autotune_report()
-    trid.timing_enable(True)
-    time_calls(lambda: trid.gtsv_varlen(trid.PREC_F32, ta, tb, tc, td32, x32, off), 10)
-    kt = trid.timing_read()
-    trid.timing_enable(False)
+    _, kt = timed_calls(trid, lambda: trid.gtsv_varlen(trid.PREC_F32, ta, tb, tc, td32, x32, off), 10, warm=10)
     cnt, ms = kt["varlen"]
     kern = ms / cnt * 1e-3
     byts = alg_bytes("arrays", 4, rows)
@@ -748,10 +748,7 @@ def extra_varlen(trid):
     x = torch.empty_like(td)
     trid.gtsv_varlen(trid.PREC_F32_REFINE64, ta, tb, tc, td, x, off)
     tune["f32_refine64"] = trid.autotune_report()
-    trid.timing_enable(True)
-    time_calls(lambda: trid.gtsv_varlen(trid.PREC_F32_REFINE64, ta, tb, tc, td, x, off), 10)
-    kt = trid.timing_read()
-    trid.timing_enable(False)
+    _, kt = timed_calls(trid, lambda: trid.gtsv_varlen(trid.PREC_F32_REFINE64, ta, tb, tc, td, x, off), 10, warm=10)
     cnt, ms = kt["varlen"]
     kern = ms / cnt * 1e-3
     ref = x64.cpu().numpy()
