@@ -70,6 +70,16 @@ const VarlenParams &varlen_params() {
     return p;
 }
 
+// Fitted on the wavefront plans of the same three calibration mixes, with
+// t0 held within 2..6 us and the FP64 and refinement row factors at least 1.
+const VarlenWaveParams &varlen_wave_params() {
+    static const VarlenWaveParams p{
+        /*t0_us*/ 6.0,     /*bw_gbs*/ 3493.40,    /*lat_us*/ 4.0953, /*cu_gbs*/ 362.45,
+        /*row_ns*/ 538.09, /*f64_factor*/ 1.045, /*lvl_ns*/ 331.99, /*ref_factor*/ 1.0037,
+    };
+    return p;
+}
+
 // Fitted like LinesParams: on the calibration shapes of model_calibrate.py's
 // ADI sweep (the other shapes are its validation set).
 const AdiParams &adi_params() {
@@ -121,13 +131,13 @@ ModelTerms model_lines(const LineReq &r, const LinePlan &pl) {
 // they need no barrier), plus one level for the exchange of a long system.
 static ModelTerms model_varlen_wave(const int64_t *off, const std::vector<int> &ids, int prec, const VarlenVariant &v,
                                     int blocks) {
-    const VarlenParams &p = varlen_params();
+    const VarlenWaveParams &p = varlen_wave_params();
     const int NW = varlen_wave_NW(prec, v.M);
     std::vector<int> order, tstart, wdesc;
     varlen_wave_pack(off, ids, v.M, NW, &order, &tstart, &wdesc);
     ModelTerms t;
     const double per_row = prec == 0 ? 40.0 : (prec == 1 ? 20.0 : 28.0);
-    const double f = prec == 1 ? 1.0 : p.f64_factor;
+    const double f = prec == 0 ? p.f64_factor : (prec == 1 ? 1.0 : p.ref_factor);
     const size_t nitems = wdesc.size() / 4 / NW;
     double sum = 0, rows = 0, mx = 0;
     for (size_t i = 0; i < nitems; ++i) {

@@ -37,6 +37,15 @@ struct LinesParams {
 struct VarlenParams {
     double t0_us, bw_gbs, lat_us, cu_gbs, row_ns, f64_factor, lvl_ns, thomas_ns;
 };
+// The same cost form for the wavefront-level plans (a work item is a
+// workgroup's wavefront slots, solved without block barriers), with its own
+// constants: the tile sweep's M rows cost row_ns each (times f64_factor for
+// FP64, ref_factor for the refinement), the in-wavefront reduced solve six
+// lane-move levels of lvl_ns / 4 and a long system's exchange one lvl_ns (both
+// twice for the refinement).
+struct VarlenWaveParams {
+    double t0_us, bw_gbs, lat_us, cu_gbs, row_ns, f64_factor, lvl_ns, ref_factor;
+};
 // Model constants of the ADI-step kernels and of the resident time loops, on top
 // of LinesParams (t0, bw): the stencil + x kernels and the constant-row y/z
 // kernels each stream at bw * eff with a per-round latency blk_us (rounds =
@@ -50,6 +59,7 @@ struct AdiParams {
 };
 const LinesParams &lines_params();
 const VarlenParams &varlen_params();
+const VarlenWaveParams &varlen_wave_params();
 const AdiParams &adi_params();
 
 struct ModelTerms {

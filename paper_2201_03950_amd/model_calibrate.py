@@ -37,6 +37,7 @@ import sys
 LINE_NAMES = ["t0_us", "bw_gbs", "seg_half", "staged_eff", "xs_eff", "arr_eff", "lat_us", "row_ns", "f64_factor",
               "lvl_ns", "lvl_wave_ns", "issue_row_ns", "issue_lvl_ns"]
 VARLEN_NAMES = ["t0_us", "bw_gbs", "lat_us", "cu_gbs", "row_ns", "f64_factor", "lvl_ns", "thomas_ns"]
+VARLEN_WAVE_NAMES = ["t0_us", "bw_gbs", "lat_us", "cu_gbs", "row_ns", "f64_factor", "lvl_ns", "ref_factor"]
 CAL_MIXES = ("loguni_32_8192_x20000", "uni_32_512_x100000", "bimodal_64_4096_x20000")
 
 
@@ -332,6 +333,89 @@ def _varlen_launches(lens, q):
     return out
 
 
+def _wave_nw(prec, M):
+    """Mirror of varlen_wave_NW: wavefronts per workgroup of a wavefront plan."""
+    return 4 if (prec == 1 and M == 32) else (16 if (prec == 0 and M == 8) else 8)
+
+
+def _wave_stats(lens, M, NW, WL=64):
+    """Mirror of varlen_wave_pack, reduced to what the wavefront model reads:
+    (items, rows, items holding a long system, most rows of such an item, most
+    rows of an item without one)."""
+    lens = [int(v) for v in lens]
+    ids = sorted(range(len(lens)), key=lambda s: -lens[s])  # stable, longest first
+    tiles = lambda s: (lens[s] + M - 1) // M  # noqa: E731
+    order, slots = [], []
+    used, i = NW, 0
+    while i < len(ids) and tiles(ids[i]) > WL:  # long systems: k consecutive wavefronts
+        k = (tiles(ids[i]) + WL - 1) // WL
+        if used + k > NW:
+            while used < NW and slots:
+                slots.append((0, 0, 0, 0))
+                used += 1
+            used = 0
+        order.append(ids[i])
+        slots += [(len(order) - 1, 1, used, k)] * k
+        used += k
+        i += 1
+    free = [j for j in range(len(slots)) if slots[j][1] == 0]
+    while used < NW and slots:
+        free.append(len(slots))
+        slots.append((0, 0, 0, 0))
+        used += 1
+    fi = 0
+    while i < len(ids):  # short systems: whole systems per wavefront, next fit
+        first, lanes, cnt = len(order), 0, 0
+        while i < len(ids) and lanes + tiles(ids[i]) <= WL:
+            order.append(ids[i])
+            lanes += tiles(ids[i])
+            i += 1
+            cnt += 1
+        if fi < len(free):
+            slots[free[fi]] = (first, cnt, 0, 0)
+            fi += 1
+        else:
+            slots.append((first, cnt, 0, 0))
+    while len(slots) % NW:
+        slots.append((0, 0, 0, 0))
+    n = sr = nl = 0
+    rl = rs = -1
+    for it in range(0, len(slots), NW):
+        rows, lng = 0, False
+        for w in range(NW):
+            f, c, w0, k = slots[it + w]
+            if k > 0:
+                lng = True
+                rows += lens[order[f]] if w0 == w else 0
+            else:
+                rows += sum(lens[order[f + j]] for j in range(c))
+        n += 1
+        sr += rows
+        if lng:
+            nl += 1
+            rl = max(rl, rows)
+        else:
+            rs = max(rs, rows)
+    return n, sr, nl, rl, rs
+
+
+def _pred_varlen_wave(p, prec, st, M, blocks):
+    """Mirror of model_varlen_wave (perf_model.cpp) on _wave_stats output."""
+    t0, bw, lat, cub, row, fx, lvl, fr = p
+    n, sr, nl, rl, rs = st
+    per_row = {0: 40.0, 1: 20.0, 2: 28.0}[prec]
+    f = {0: fx, 1: 1.0, 2: fr}[prec]
+    k = 2 if prec == 2 else 1
+    base = lat + (M * row * f + 6 * lvl / 4 * k) * 1e-3
+    s = n * base + sr * per_row / (cub * 1e3) + nl * lvl * k * 1e-3
+    mx = 0.0
+    if rl >= 0:
+        mx = base + rl * per_row / (cub * 1e3) + lvl * k * 1e-3
+    if rs >= 0:
+        mx = max(mx, base + rs * per_row / (cub * 1e3))
+    return t0 + max(per_row * sr / (bw * 1e3), s / max(1, min(blocks, n)), mx)
+
+
 def _pred_varlen(p, prec, launches):
     """Mirror of model_varlen (perf_model.cpp), summed over a plan's launches."""
     t0, bw, lat, cub, row, fx, lvl, th = p
@@ -376,7 +460,8 @@ def fit(path):
     print("  calibration", _accuracy([(_pred_lines(pl, r), r["meas_us"]) for r in cal]))
     print("  validation ", _accuracy([(_pred_lines(pl, r), r["meas_us"]) for r in val]))
 
-    var = [(r, q, _varlen_launches(r["lens"], q)) for r in recs if r["kind"] == "varlen" for q in r["plans"]]
+    var = [(r, q, _varlen_launches(r["lens"], q)) for r in recs if r["kind"] == "varlen" for q in r["plans"]
+           if q.get("reduced") != "wave" and q["meas_us"] > 0]
     vcal = [x for x in var if x[0]["mix"] in CAL_MIXES]
     vval = [x for x in var if x[0]["mix"] not in CAL_MIXES]
     lb = [0, 500, 0, 0.5, 0, 1, 0, 0]
@@ -393,6 +478,30 @@ def fit(path):
     print("VarlenParams", {k: round(float(v), 4) for k, v in zip(VARLEN_NAMES, pv)})
     print("  calibration", _accuracy([(_pred_varlen(pv, x[0]["prec"], x[2]), x[1]["meas_us"]) for x in vcal]))
     print("  validation ", _accuracy([(_pred_varlen(pv, x[0]["prec"], x[2]), x[1]["meas_us"]) for x in vval]))
+
+    # wavefront plans: their own constants, t0 held within 2..6 us and the FP64
+    # and refinement row factors at least 1 (the fit is otherwise free to trade
+    # a large fixed cost against the per-item terms on the large mixes)
+    wav = [(r["mix"], r["prec"], _wave_stats(r["lens"], q["M"], _wave_nw(r["prec"], q["M"])), q["M"], q["blocks"],
+            q["meas_us"]) for r in recs if r["kind"] == "varlen" for q in r["plans"]
+           if q.get("reduced") == "wave" and q["meas_us"] > 0]
+    if wav:
+        wcal = [x for x in wav if x[0] in CAL_MIXES]
+        wval = [x for x in wav if x[0] not in CAL_MIXES]
+        lb = [2, 500, 0, 10, 0, 1, 0, 1]
+        ub = [6, 8000, 100, 20000, 5000, 10, 20000, 10]
+        hi = [6, 7000, 20, 5000, 500, 4, 3000, 4]
+        best = None
+        for _ in range(40):
+            q0 = [rng.uniform(lo, h) for lo, h in zip(lb, hi)]
+            f = least_squares(lambda p: np.array([math.log(_pred_varlen_wave(p, *x[1:5]) / x[5]) for x in wcal]), q0,
+                              bounds=(lb, ub))
+            if best is None or f.cost < best.cost:
+                best = f
+        pw = best.x
+        print("VarlenWaveParams", {k: round(float(v), 4) for k, v in zip(VARLEN_WAVE_NAMES, pw)})
+        print("  calibration", _accuracy([(_pred_varlen_wave(pw, *x[1:5]), x[5]) for x in wcal]))
+        print("  validation ", _accuracy([(_pred_varlen_wave(pw, *x[1:5]), x[5]) for x in wval]))
 
 
 if __name__ == "__main__":

@@ -182,6 +182,22 @@ def test_varlen_autotune_pruned_by_the_model(trid, orc, monkeypatch, top):
     assert len(timed) == (len(rep) if top == 0 else min(top, len(rep)))
     assert timed == rep[:len(timed)]
     assert _sys_err(x.cpu().numpy(), ref, off) <= 1e-12
+    # the calibration script's mirror of the wavefront-plan model (its packing
+    # included) reproduces the library's predictions with the library's constants
+    import re
+
+    from paper_2201_03950_amd import model_calibrate as mc
+
+    src = open(os.path.join(os.path.dirname(trid.__file__), "csrc", "perf_model.cpp")).read()
+    body = src[src.index("const VarlenWaveParams &varlen_wave_params()"):]
+    pw = [float(v) for v in re.findall(r"/\*\w+\*/\s*([-0-9.eE]+)", body[:body.index("};")])]
+    assert len(pw) == len(mc.VARLEN_WAVE_NAMES)
+    lens = np.diff(off)
+    waves = [q for q in rep if q["reduced"] == "wave"]
+    assert waves
+    for q in waves:
+        st = mc._wave_stats(lens, q["M"], mc._wave_nw(0, q["M"]))
+        assert mc._pred_varlen_wave(pw, 0, st, q["M"], q["blocks"]) == pytest.approx(q["pred_us"], rel=1e-3)
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
