@@ -75,6 +75,15 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
     // FP64 generated rows on long strided lines (>= 128 tiles of 8): 16-row
     // tiles in 512-thread blocks (measured 7% faster on 1024-row y lines)
     if (!r.force_M && r.f64 && r.mode != Mode::Arrays && r.inner > 1 && cdiv(r.n, 8) >= 128) M = 16;
+    // FP64 generated rows on x lines of about 1000 rows or more: 16-row staged
+    // tiles when they fill their wavefronts as well as 8-row tiles do (measured
+    // 3-12% faster on 1000-, 1024- and 2048-row lines; on 1536-row lines, whose
+    // 96 tiles leave half a wavefront idle, 7% slower)
+    if (!r.force_M && r.f64 && (r.mode == Mode::S || r.mode == Mode::Const) && r.inner == 1 &&
+        r.out == Out::Store && r.n >= 1000) {
+        auto fill = [](i64 tiles) { return (double)tiles / (64.0 * (double)cdiv(tiles, 64)); };
+        if (fill(cdiv(r.n, 16)) >= fill(cdiv(r.n, 8))) M = 16;
+    }
     if (M != 8 && M != 16 && M != 32) {
         *err = "tile size must be 8, 16 or 32";
         return false;
@@ -124,21 +133,34 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
         }
     }
     const int regions = staged_regions(r.mode);
+    // The staged kernel holds a line of up to kStagedMaxThreads tiles: longer
+    // x lines take bigger tiles there when the LDS holds the line (measured
+    // 1.6-2.0x faster than the strided kernel on 4096-row FP64 lines with
+    // 16-row tiles, 2.0-2.7x on 8192-row FP32 lines with 32-row tiles)
+    int Ms = M;
+    i64 Ps = P;
+    if (r.inner == 1 && !r.force_M && regions > 0 && r.out == Out::Store)
+        while (Ps > kStagedMaxThreads && Ms < 32) {
+            Ms *= 2;
+            Ps = cdiv(r.n, Ms);
+        }
     const bool want_staged = r.inner == 1 && !r.force_strided &&
                              ((regions > 0 && r.out == Out::Store) || (adj_s && M <= 16)) &&
-                             P <= kStagedMaxThreads;
+                             Ps <= kStagedMaxThreads;
     if (want_staged) {
         // about one wavefront per block: the block's barriers then cost little
         // and many blocks per CU overlap their load, solve and store phases
         // (measured faster than 256-thread blocks for line lengths 128..256)
-        int L = r.force_L ? r.force_L : std::max(1, 64 / (int)P);
+        int L = r.force_L ? r.force_L : std::max(1, 64 / (int)Ps);
         L = std::max(1, std::min(L, pow2_ceil(r.outer)));
-        const int ls = (int)P * (M + 1);
+        const int ls = (int)Ps * (Ms + 1);
         auto bytes = [&](int LL) {  // one staging region + reduced-solve scratch
-            return (size_t)LL * ls * w + (size_t)6 * LL * P * w;
+            return (size_t)LL * ls * w + (size_t)6 * LL * Ps * w;
         };
         while (bytes(L) > kMaxShmem && L > 1) L /= 2;
-        if (bytes(L) <= kMaxShmem && L * P <= kStagedMaxThreads) {
+        if (bytes(L) <= kMaxShmem && L * Ps <= kStagedMaxThreads) {
+            p.M = Ms;
+            p.P = (int)Ps;
             p.staged = true;
             p.L = L;
             p.ls = ls;
@@ -148,10 +170,10 @@ bool plan_lines(const LineReq &r, LinePlan *pl, std::string *err) {
             return true;
         }
     }
-    // x lines too long to stage (over 4096 rows): each lane reads its own
-    // tile's rows, and 8-row tiles (the most lanes per line, the shortest
-    // per-lane segments) stream best: measured 1.3-1.5x faster than 16 or 32
-    // rows on 8192-row FP64 lines and 1.3-3.8x on FP32 ones
+    // x lines of over 4096 rows that do not stage (FP64 lines whose 32-row
+    // tiles exceed the LDS): each lane reads its own tile's rows, and 8-row
+    // tiles (the most lanes per line, the shortest per-lane segments) stream
+    // best: measured 1.3-1.5x faster than 16 or 32 rows on 8192-row FP64 lines
     if (r.inner == 1 && !r.force_M && M != 8 && r.n > 4096 && r.out == Out::Store &&
         (r.mode == Mode::S || r.mode == Mode::Arrays) && cdiv(r.n, 8) <= strided_max_threads(8, w, wide)) {
         M = 8;

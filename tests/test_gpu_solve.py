@@ -168,14 +168,15 @@ def test_x_lines_large_grid(trid, orc, dt, mode):
     assert _line_err(td.cpu().numpy().astype(np.float64), ref, 0) <= TOL[dt]
 
 
-@pytest.mark.parametrize("n", [8192, 5001])
+@pytest.mark.parametrize("n", [8192, 5001, 4096, 3000])
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 @pytest.mark.parametrize("mode", ["arrays", "s", "const"])
 @pytest.mark.parametrize("axis", [0, 1])
 def test_lines_of_maximum_length(trid, orc, dt, mode, axis, n):
     """Lines of TRID_MAX_LINE = 8192 rows, the longest one workgroup holds, and
-    of 5001 rows (a ragged last tile), along x (too long to stage: each lane
-    loads its own 8-row tile) and y (strided, 3 lines)."""
+    of 5001, 4096 and 3000 rows, along x (staged with 16- or 32-row tiles where
+    the LDS holds the line; FP64 8192-row lines with each lane loading its own
+    8-row tile) and y (strided, 3 lines)."""
     m = 3
     a, b, c, d = (v.astype(dt) for v in gen.dd_lines(m, n, seed=81))
     if axis == 1:  # dims [3, 8192]: the 3 lines interleaved
