@@ -8,6 +8,7 @@
 // (Section III-B), as in the plain kernels.  Not in the paper: the precision
 // scheme is an addition of this library.
 #include <algorithm>
+#include <type_traits>
 
 #include "dispatch.hpp"
 #include "lines.hpp"
@@ -249,13 +250,69 @@ __global__ __launch_bounds__(256) void k_refine_staged(StagedGeom gm, RefPtrs sr
     stage_out<double, M>(x + off, ost, cnt, n, ls);
 }
 
+// The two streaming sweeps of tile_ends_fn with the forward sweep's pivot
+// reciprocals rf[k] = 1 / (b_k - a_k cp_{k-1}), k = 1..M-1, kept: they depend on
+// the matrix only, so the interior sweep of the same solve (whose pivots are
+// the same) and every later solve with the same matrix reuse them (HAVE: rf
+// holds them already).
+template <typename T, int M, bool HAVE, class Rows, class Fence>
+__device__ __forceinline__ void tile_ends_rf(const Rows &rows, const T (&rd)[M], T (&rf)[M], TileEnds<T> &e,
+                                             Fence &&fence) {
+    static_assert(M >= 3, "tiles need at least three rows");
+    T a, b, c;
+    rows(1, a, b, c);
+    T r;
+    if constexpr (HAVE) {
+        r = rf[1];
+    } else {
+        r = fast_rcp(b);
+        rf[1] = r;
+    }
+    T ap = a * r, cp = c * r, dp = rd[1] * r;
+#pragma unroll
+    for (int k = 2; k < M; ++k) {
+        rows(k, a, b, c);
+        if constexpr (HAVE) {
+            r = rf[k];
+        } else {
+            r = fast_rcp(b - a * cp);
+            rf[k] = r;
+        }
+        ap = -r * a * ap;
+        cp = r * c;
+        dp = r * (rd[k] - a * dp);
+    }
+    e.la = ap;
+    e.lc = cp;
+    e.ld = dp;
+    fence();
+    rows(M - 2, a, b, c);
+    r = fast_rcp(b);
+    T al = -a * r, be = -c * r, ga = rd[M - 2] * r;
+#pragma unroll
+    for (int k = M - 3; k >= 1; --k) {
+        rows(k, a, b, c);
+        r = fast_rcp(b + c * al);
+        be = -c * be * r;
+        ga = (rd[k] - c * ga) * r;
+        al = -a * r;
+    }
+    rows(0, a, b, c);
+    e.fa = a;
+    e.fb = b + c * al;
+    e.fc = c * be;
+    e.fd = rd[0] - c * ga;
+}
+
 // ---------------------------------------------------- staged, lean --
 // x lines of per-point s and FP32 d whose P tiles (a power of two up to 64)
 // sit in adjacent lanes of one wavefront: the block's s and d are staged into LDS,
 // and each thread keeps only its tile's s, the FP32 solution and the
 // residual.  Each FP32 solve finds the tile's boundary equations by two
-// streaming sweeps (tile_ends_fn), the reduced system by lane moves (no LDS,
-// no barrier), and the interior by Thomas (Alg. 1) with both end values known.
+// streaming sweeps (tile_ends_rf: the forward sweep's pivot reciprocals are
+// kept for the interior sweep and the second solve), the reduced system by
+// lane moves (no LDS, no barrier), and the interior by Thomas (Alg. 1) with
+// both end values known.
 // The neighbours of a tile's end rows for the FP64 residual come from the
 // adjacent lanes; d is read again from its staged slots.  Rows past the line
 // are identity rows (s = d = 0, solution 0).
@@ -281,7 +338,7 @@ __global__ __launch_bounds__(256, 3) void k_refine_staged_lean(StagedGeom gm, co
     // own unstaged slots and mask what they read there
     const int pos = l * ls + p * (M + 1);
     const int g0 = p * M;
-    float sv[M], w[M], cs[M];
+    float sv[M], w[M], rf[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         const bool v = act && g0 + k < n;
@@ -300,14 +357,17 @@ __global__ __launch_bounds__(256, 3) void k_refine_staged_lean(StagedGeom gm, co
 #pragma unroll
         for (int k = 0; k < M; ++k) asm volatile("" : "+v"(sv[k]));
     };
-    // one FP32 solve of the right-hand side in v, in place
-    auto solve32 = [&](float (&v)[M]) {
+    // one FP32 solve of the right-hand side in v, in place; the first keeps
+    // the forward pivots' reciprocals in rf, the second (same matrix) reuses
+    // them.  The interior sweep (both end values known) has the same pivots
+    // b_k - a_k cp_{k-1} for k = 1..M-2, and its c' = c_k rf[k].
+    auto solve32 = [&](float (&v)[M], auto have) {
         TileEnds<float> e;
-        tile_ends_fn<float, M>(rows, v, e, fence);
+        tile_ends_rf<float, M, decltype(have)::value>(rows, v, rf, e, fence);
         fence();
         float f, lv;
         reduced_solve<float, M>(e, nullptr, 0, P, p, t, 1, f, lv);
-        float cprev = 0.f, dprev = 0.f;
+        float dprev = 0.f;
 #pragma unroll
         for (int k = 1; k < M - 1; ++k) {
             float a, b, c;
@@ -317,23 +377,21 @@ __global__ __launch_bounds__(256, 3) void k_refine_staged_lean(StagedGeom gm, co
                 rhs -= a * f;
                 a = 0.f;
             }
-            if (k == M - 2) {
-                rhs -= c * lv;
-                c = 0.f;
-            }
-            const float r = fast_rcp(b - a * cprev);
-            cprev = c * r;
-            dprev = (rhs - a * dprev) * r;
-            cs[k] = cprev;
+            if (k == M - 2) rhs -= c * lv;
+            dprev = (rhs - a * dprev) * rf[k];
             v[k] = dprev;
         }
         v[0] = f;
         v[M - 1] = lv;
 #pragma unroll
-        for (int k = M - 3; k >= 1; --k) v[k] -= cs[k] * v[k + 1];
+        for (int k = M - 3; k >= 1; --k) {
+            float a, b, c;
+            rows(k, a, b, c);
+            v[k] -= c * rf[k] * v[k + 1];
+        }
         fence();
     };
-    solve32(w);
+    solve32(w, std::false_type{});
     // x32 goes to the thread's own staged-s slots (s is in registers now; no
     // other thread reads them); the neighbours of the tile's end rows come
     // from the adjacent lanes (0 outside the line)
@@ -354,7 +412,7 @@ __global__ __launch_bounds__(256, 3) void k_refine_staged_lean(StagedGeom gm, co
         const double rk = dk - (-sk * um + (1.0 + 2.0 * sk) * (double)xm[k] - sk * up);
         w[k] = v ? (float)rk : 0.f;
     }
-    solve32(w);
+    solve32(w, std::true_type{});
     float xo[M];
 #pragma unroll
     for (int k = 0; k < M; ++k) xo[k] = xm[k];
